@@ -1,0 +1,104 @@
+"""Seeded synthetic matrices for the FEAST workloads (no FEAST arithmetic here).
+
+All generation runs in FP64 on the host with ``numpy.random.default_rng``.
+Draw order per workload is fixed so that a seed names one input exactly.
+"""
+
+import numpy as np
+
+
+def column_major(M):
+    """Fortran-ordered copy: element (i, j) at i + j * n, as the C interface expects."""
+    return np.asfortranarray(M)
+
+
+def helloworld():
+    """4 x 4 real symmetric matrix of the guide's HelloWorld example (Section 2.4)."""
+    return np.array([[2.0, -1.0, -1.0, 0.0],
+                     [-1.0, 3.0, -1.0, -1.0],
+                     [-1.0, -1.0, 3.0, -1.0],
+                     [0.0, -1.0, -1.0, 2.0]])
+
+
+def laplacian_1d_dense(n, diag_shift=None):
+    """Dense tridiag(-1, 2, -1) of order n; optional diagonal added (vector of length n)."""
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    if diag_shift is not None:
+        A = A + np.diag(np.asarray(diag_shift, dtype=np.float64))
+    return A
+
+
+def laplacian_1d_eigs(n):
+    """Eigenvalues 2 - 2 cos(k pi / (n + 1)), k = 1..n, ascending (closed form)."""
+    k = np.arange(1, n + 1, dtype=np.float64)
+    return np.sort(2.0 - 2.0 * np.cos(k * np.pi / (n + 1)))
+
+
+def _haar_unitary(rng, n, complex_):
+    """Haar-distributed orthogonal/unitary matrix: QR of a Gaussian with R-diagonal phase fix."""
+    if complex_:
+        Z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    else:
+        Z = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(Z)
+    d = np.diag(R)
+    ph = d / np.abs(d)
+    return Q * ph[None, :]
+
+
+def prescribed_complex_pencil(n, seed, lam_lo=-10.0, lam_hi=10.0, b_scale=0.1):
+    """Generalized complex Hermitian pencil with a known spectrum.
+
+    Draw order from default_rng(seed): lambda ~ U[lam_lo, lam_hi]^n, then C (complex
+    Gaussian n x n), then the Haar unitary U.  B = I + b_scale * C C^H / n,
+    L = chol(B), A = L U diag(lambda) U^H L^H symmetrised.  Exact eigenvectors are
+    X = L^-H U (B-orthonormal).  Returns (A, B, lam_sorted, X_sorted).
+    """
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(lam_lo, lam_hi, n)
+    C = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    U = _haar_unitary(rng, n, True)
+    B = np.eye(n, dtype=np.complex128) + b_scale * (C @ C.conj().T) / n
+    B = 0.5 * (B + B.conj().T)
+    L = np.linalg.cholesky(B)
+    LU = L @ U
+    A = (LU * lam[None, :]) @ LU.conj().T
+    A = 0.5 * (A + A.conj().T)
+    order = np.argsort(lam)
+    X = np.linalg.solve(L.conj().T, U)
+    return A, B, lam[order], X[:, order]
+
+
+def prescribed_real_problem(n, rng, lam_lo=-10.0, lam_hi=10.0):
+    """Real symmetric A = U diag(lambda) U^T with Haar-orthogonal U (draws: lambda, U)."""
+    lam = rng.uniform(lam_lo, lam_hi, n)
+    U = _haar_unitary(rng, n, False)
+    A = (U * lam[None, :]) @ U.T
+    A = 0.5 * (A + A.T)
+    order = np.argsort(lam)
+    return A, lam[order], U[:, order]
+
+
+def batched_real_problems(nprob, seed, n_lo=256, n_hi=2048, c_lo=24, c_hi=48):
+    """Independent real symmetric problems of uneven size, each with a known interval.
+
+    Draw order from default_rng(seed): all sizes n_p ~ U{n_lo..n_hi} first; then per
+    problem lambda, U (see prescribed_real_problem), the count c_p ~ U{c_lo..c_hi}
+    and the start index s_p ~ U{1..n_p - c_p - 1} in the sorted spectrum.  The interval
+    edges are midpoints between sorted neighbours, so it holds exactly c_p
+    eigenvalues; M0_p = ceil(1.5 c_p).
+    Returns a list of dicts with A, lam (sorted), emin, emax, count, m0.
+    """
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, size=nprob)
+    probs = []
+    for p in range(nprob):
+        n = int(ns[p])
+        A, lam, U = prescribed_real_problem(n, rng)
+        c = int(rng.integers(c_lo, c_hi + 1))
+        s = int(rng.integers(1, n - c))
+        emin = 0.5 * (lam[s - 1] + lam[s])
+        emax = 0.5 * (lam[s + c - 1] + lam[s + c])
+        probs.append({"A": A, "lam": lam, "U": U, "emin": emin, "emax": emax,
+                      "count": c, "m0": int(np.ceil(1.5 * c)), "start": s})
+    return probs
