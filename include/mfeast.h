@@ -1,0 +1,113 @@
+/*
+ * mfeast: Hermitian FEAST contour-integration eigensolver for AMD MI355X (gfx950).
+ *
+ * C interface of libmfeast.so.  The problem statement follows the FEAST v4.0 User
+ * Guide (arXiv:2002.04807): find the eigenpairs (lambda, x) of A x = lambda B x,
+ * A Hermitian (real symmetric), B Hermitian positive definite (or B = I), with
+ * lambda in the closed interval [Emin, Emax], using a search subspace of size M0
+ * (Section 3.2 "FEAST Hermitian", Table tab-common1 for the common arguments,
+ * Table tab-spec1 for the dense storage arguments).  Algorithm options travel in the
+ * integer array fpm[64] (Table tab_fpm; C index = Fortran index - 1), results and
+ * errors use the guide's info codes (Table tab_info).
+ *
+ * Conventions for every entry point:
+ *  - Matrix and vector arguments named "device" are HIP device pointers (for example
+ *    the data pointers of PyTorch tensors on the GPU); everything else is host memory.
+ *  - Dense matrices are column-major with a leading dimension (LAPACK), as in the
+ *    guide; complex numbers are interleaved (re, im) doubles.
+ *  - The caller owns every buffer passed in; the library never frees them.  A handle
+ *    owns its workspace (including the stored LU factors of all contour nodes), which
+ *    grows on demand, is reused by later calls and is released by mfeast_destroy.
+ *  - Every call returns info.  Argument checks run on the host before any device
+ *    work, in the order of Table tab_info: 202 (N), 201 (M0), 200 (Emin/Emax),
+ *    100+i (fpm(i), Fortran numbering), then -(100+i) for an invalid i-th argument of
+ *    the call (1-based position in the C prototype).  Warnings: 1 no eigenvalue in the
+ *    interval, 2 no convergence within fpm(4) loops, 3 M0 too small (M >= M0),
+ *    4 subspace returned after one contour (fpm(14)=1).  Errors: -2 device or
+ *    factorization failure (zero pivot, non-finite value, HIP error), -3 the reduced
+ *    problem is not positive definite (B may not be positive definite).
+ *    -900 no usable HIP device for the handle (a code outside the guide's ranges).
+ *  - Calls are synchronous with respect to the host: the results are complete on the
+ *    device when the call returns (the subspace iteration needs host-visible scalars
+ *    after every Rayleigh-Ritz step).  A handle may be used by one thread at a time.
+ */
+#ifndef MFEAST_H
+#define MFEAST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfeast_ctx* mfeast_handle;
+
+/* Create a handle bound to HIP device `device`; work is issued on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Returns 0, -101 (h NULL) or -900. */
+int mfeast_create(mfeast_handle* h, int device, void* hip_stream);
+
+/* Release the handle and its workspace.  Returns 0 or -101. */
+int mfeast_destroy(mfeast_handle h);
+
+/* Change the stream later calls of this handle issue work on. */
+int mfeast_set_stream(mfeast_handle h, void* hip_stream);
+
+/* Default parameters (feastinit; Table tab_fpm).  fpm: 64 int32 (host).
+ * Project slot fpm(51) (reserved in the guide): seed of the random starting block. */
+void mfeast_init(int32_t* fpm);
+
+/* Half-contour nodes and weights (zfeast_contour; Section 4.2 "Search contour",
+ * Table tab_contour).  Ellipse through Emin and Emax centred on the real axis with
+ * axis ratio ratio_pct/100; rule 0 Gauss-Legendre (ne in 1..20, 24, 32, 40, 48, 56),
+ * 1 trapezoidal (ne >= 1).  zne, wne: host arrays of 2*ne doubles (re, im) receiving
+ * the upper-half nodes z_j (j = 1 nearest Emin) and weights w_j such that the spectral
+ * projector is approximated by sum_j [w_j f(z_j) + conj(w_j) f(conj z_j)].
+ * Returns 0, 200, 102, 116, 118 or -(100+i) for a NULL array. */
+int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct,
+                   double* zne, double* wne);
+
+/* Dense real symmetric problem (dfeast_sygv / dfeast_syev and their {x} forms).
+ *  h       handle
+ *  uplo    'F', 'L' or 'U': which part of A (and B) is referenced (Table tab-spec1)
+ *  n       order of the system
+ *  A       device, n x n column-major, leading dimension lda >= n
+ *  B       device, n x n column-major (ldb >= n), or NULL for B = I (standard problem)
+ *  fpm     host, 64 int32 (in/out; fpm(60) unused here)
+ *  emin, emax  search interval (closed)
+ *  m0      host, in: subspace size M0 (1 <= M0 <= n); out: possibly reduced M0
+ *  E       device, m0 doubles: eigenvalues, inside pairs first (ascending), then outside
+ *          (in: initial guess when fpm(5)=1)
+ *  X       device, n x m0 column-major (ldx >= n): eigenvectors following E, or the
+ *          subspace Q after one contour when fpm(14)=1 (in: initial subspace when fpm(5)=1)
+ *  M       host: number of eigenvalues found in [emin, emax]
+ *  res     device, m0 doubles: ||A x_i - lambda_i B x_i|| / ||alpha B x_i||,
+ *          alpha = max(|emin|, |emax|)
+ *  epsout  host: relative trace change |trace_k - trace_{k-1}| / alpha
+ *  loop    host: index of the last subspace iteration (0 = first contour)
+ *  zne,wne host, 2*fpm(2) doubles each, or both NULL: custom nodes and half-contour
+ *          weights (expert mode); NULL = generated from fpm(2), fpm(16), fpm(18)
+ * fpm(42)=1 (default) factors and solves the shifted systems in complex FP32 with the
+ * FP64 residual form of the iteration; fpm(42)=0 uses complex FP64 throughout. */
+int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, int32_t* fpm, double emin, double emax,
+                 int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
+                 double* epsout, int32_t* loop, const double* zne, const double* wne);
+
+/* Dense complex Hermitian problem (zfeast_hegv / zfeast_heev).  Same arguments as
+ * mfeast_dsygv with A, B, X complex (interleaved doubles).  The conjugate contour node
+ * is handled by a solve with (z B - A)^H that reuses the factorization of z B - A
+ * (Hermitian RCI cases 20/21). */
+int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, int32_t* fpm, double emin, double emax,
+                 int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
+                 double* epsout, int32_t* loop, const double* zne, const double* wne);
+
+/* Timing of the last call, seconds (Fact, Solve, Ax/Bx/RR products, reduced eig, Misc,
+ * Total, iterations, FP64 residual).  out: host, 8 doubles. */
+int mfeast_get_timing(mfeast_handle h, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFEAST_H */

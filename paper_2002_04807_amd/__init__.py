@@ -1,0 +1,210 @@
+"""Python binding of libmfeast.so (Hermitian FEAST contour-integration eigensolver, MI355X).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of the
+library.  PyTorch provides device memory and the stream.  The functions named like
+the C entry points (``mfeast_*``) map one to one onto ``include/mfeast.h``;
+``feast`` is a convenience wrapper that allocates the outputs.
+
+If the compiled library is missing the import still succeeds (so CPU-only tools can
+read the module), but every call raises: there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfeast.so")
+
+_lib = None
+_lib_error = None
+
+EXPORTED = (
+    "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_contour",
+    "mfeast_dsygv", "mfeast_zhegv", "mfeast_get_timing",
+)
+
+
+def _load():
+    global _lib, _lib_error
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        _lib_error = "libmfeast.so not built (run __graft_entry__.build())"
+        raise RuntimeError(_lib_error)
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_i32p, c_dp, c_vp = ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p, ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.mfeast_create.argtypes = [ctypes.POINTER(c_vp), c_int, c_vp]
+    lib.mfeast_create.restype = c_int
+    lib.mfeast_destroy.argtypes = [c_vp]
+    lib.mfeast_destroy.restype = c_int
+    lib.mfeast_set_stream.argtypes = [c_vp, c_vp]
+    lib.mfeast_set_stream.restype = c_int
+    lib.mfeast_init.argtypes = [c_i32p]
+    lib.mfeast_init.restype = None
+    lib.mfeast_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, c_dp, c_dp]
+    lib.mfeast_contour.restype = c_int
+    dense = [c_vp, ctypes.c_char, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.c_double, ctypes.c_double,
+             c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
+    for name in ("mfeast_dsygv", "mfeast_zhegv"):
+        fn = getattr(lib, name)
+        fn.argtypes = dense
+        fn.restype = c_int
+    lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
+    lib.mfeast_get_timing.restype = c_int
+    _lib = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _load()
+
+
+# ----------------------------------------------------------------------------- helpers
+
+def _ptr(t):
+    """Device (or host) address of a tensor / ndarray, or None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _fpm_array(fpm):
+    arr = np.ascontiguousarray(np.asarray(fpm, dtype=np.int32))
+    if arr.size != 64:
+        raise ValueError("fpm must have 64 entries")
+    return arr
+
+
+def mfeast_init():
+    """Default fpm[64] (feastinit) as an int32 numpy array."""
+    fpm = np.zeros(64, dtype=np.int32)
+    _load().mfeast_init(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return fpm
+
+
+def mfeast_contour(emin, emax, ne, rule=0, ratio_pct=30):
+    """(info, z, w): half-contour nodes and weights as complex128 arrays."""
+    zb = np.zeros(2 * max(int(ne), 1), dtype=np.float64)
+    wb = np.zeros_like(zb)
+    info = _load().mfeast_contour(float(emin), float(emax), int(ne), int(rule), int(ratio_pct),
+                                  zb.ctypes.data, wb.ctypes.data)
+    return info, zb.view(np.complex128)[:ne].copy(), wb.view(np.complex128)[:ne].copy()
+
+
+class Handle:
+    """Owns an mfeast handle bound to a device and a HIP stream (torch's current by default)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        lib = _load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = ctypes.c_void_p()
+        info = lib.mfeast_create(ctypes.byref(h), int(device), ctypes.c_void_p(raw))
+        if info != 0:
+            raise RuntimeError("mfeast_create failed with info %d" % info)
+        self.ptr = h
+        self.device = device
+
+    def close(self):
+        if self.ptr is not None and self.ptr.value:
+            _load().mfeast_destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self):
+        out = (ctypes.c_double * 8)()
+        _load().mfeast_get_timing(self.ptr, out)
+        return list(out)
+
+
+def _dense_call(name, h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
+    lib = _load()
+    fpm_a = _fpm_array(fpm)
+    m0_c = ctypes.c_int32(int(m0))
+    M_c = ctypes.c_int32(0)
+    eps_c = ctypes.c_double(0.0)
+    loop_c = ctypes.c_int32(0)
+    zb = wb = None
+    if zne is not None:
+        zb = np.ascontiguousarray(np.asarray(zne, dtype=np.complex128)).view(np.float64)
+        wb = np.ascontiguousarray(np.asarray(wne, dtype=np.complex128)).view(np.float64)
+    hp = h.ptr if isinstance(h, Handle) else h
+    info = getattr(lib, name)(
+        hp, uplo.encode() if isinstance(uplo, str) else uplo, int(n), _ptr(A), int(lda), _ptr(B), int(ldb),
+        fpm_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(emin), float(emax), ctypes.byref(m0_c),
+        _ptr(E), _ptr(X), int(ldx), ctypes.byref(M_c), _ptr(res), ctypes.byref(eps_c), ctypes.byref(loop_c),
+        None if zb is None else zb.ctypes.data, None if wb is None else wb.ctypes.data)
+    if isinstance(fpm, np.ndarray) and fpm.dtype == np.int32 and fpm.size == 64:
+        fpm[:] = fpm_a
+    return {"info": int(info), "m0": int(m0_c.value), "M": int(M_c.value), "epsout": float(eps_c.value),
+            "loop": int(loop_c.value)}
+
+
+def mfeast_dsygv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
+    """C mfeast_dsygv; A, B, E, X, res are device tensors (column-major A, B, X)."""
+    return _dense_call("mfeast_dsygv", h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne, wne)
+
+
+def mfeast_zhegv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
+    """C mfeast_zhegv; complex128 device tensors (interleaved re, im)."""
+    return _dense_call("mfeast_zhegv", h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne, wne)
+
+
+def colmajor(t):
+    """(tensor, leading dimension) with element (i, j) at i + j*ld; copies only if needed."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    if t.stride(0) == 1 and t.stride(1) >= t.shape[0]:
+        return t, t.stride(1)
+    c = t.mT.contiguous().mT
+    return c, c.stride(1)
+
+
+def feast(A, B, emin, emax, m0, fpm=None, X0=None, uplo="F", handle=None, zne=None, wne=None):
+    """Eigenpairs of A x = lambda B x with lambda in [emin, emax] (B None means identity).
+
+    A, B: torch tensors on the GPU (float64 or complex128).  Returns a dict with E, X
+    (n x M0 column-major tensor), res, M, m0, loop, epsout, info.  fpm defaults to
+    mfeast_init(); X0 (with fpm[4] = 1) is the starting subspace.
+    """
+    import torch
+    n = A.shape[0]
+    cplx = A.is_complex() or (B is not None and B.is_complex())
+    dt = torch.complex128 if cplx else torch.float64
+    dev = A.device
+    fpm = mfeast_init() if fpm is None else _fpm_array(fpm).copy()
+    A_, lda = colmajor(A.to(dt))
+    B_, ldb = (None, n) if B is None else colmajor(B.to(dt))
+    X = torch.zeros((m0, n), dtype=dt, device=dev).mT
+    if X0 is not None:
+        X.copy_(X0.to(dt))
+        fpm[4] = 1
+    E = torch.zeros(m0, dtype=torch.float64, device=dev)
+    res = torch.zeros(m0, dtype=torch.float64, device=dev)
+    own = handle is None
+    h = Handle(dev.index or 0) if own else handle
+    try:
+        fn = mfeast_zhegv if cplx else mfeast_dsygv
+        out = fn(h, uplo, n, A_, lda, B_, ldb, fpm, emin, emax, m0, E, X, n, res, zne, wne)
+        out["timing"] = h.timing()
+    finally:
+        if own:
+            h.close()
+    m = out["m0"]
+    out.update(E=E[:m], X=X[:, :m], res=res[:m], fpm=fpm)
+    return out

@@ -1,0 +1,645 @@
+// Host side of the Hermitian FEAST contour-integration subspace iteration (C interface).
+//
+// One call runs the whole method of the FEAST v4.0 guide for a dense Hermitian
+// (real symmetric) pencil, every numerical step in the HIP kernels of this library:
+//   factor    Az_j = z_j B - A for every node, blocked LU with partial pivoting,
+//             factors kept for all iterations (RCI case 10, fpm(10)=1)
+//   contour   iteration 0: solve Az_j Q_j = B Y for the starting block Y (case 11,
+//             and case 21 with Az_j^H for complex Hermitian problems);
+//             iteration k > 0: residual inverse iteration (v4.0, Section 1.2 and the
+//             Tips of Section 3.1): only R = A X - B X Lambda (FP64) is solved and
+//             Q = X diag(rho(Lambda)) + sum_j [w_j d_j diag(1/(z_j - lambda)) + ...],
+//             so that FP32 solves (fpm(42)=1) keep FP64 accuracy
+//   RR        A Q, B Q (cases 30/40), Aq = Q^H A Q, Bq = Q^H B Q, reduced eigenproblem,
+//             X = Q W, residuals res_i = ||A x_i - lambda_i B x_i|| / ||alpha B x_i||
+//   stop      M = #lambda in [Emin, Emax]; converged when max_{i<=M} res_i < 10^-fpm(3)
+//             (fpm(6)=1) or epsout < 10^-fpm(3) (fpm(6)=0); fpm(4) bounds the loops.
+// The host only sequences launches and reads back O(M0) scalars per iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mfeast.h"
+#include "kernels.hpp"
+
+using namespace mf;
+
+namespace {
+
+constexpr double RANK_TOL = 1.0e-13;  // kept directions of the equilibrated overlap: s > RANK_TOL * max s
+
+enum Slot {
+  S_LU, S_DINV, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
+  S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
+  S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
+  S_SMALL, S_PART, S_FLAG, S_NSLOTS
+};
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0;
+  void start() { t0 = std::chrono::steady_clock::now(); }
+  double stop() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+}  // namespace
+
+struct mfeast_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* buf[S_NSLOTS] = {};
+  size_t cap[S_NSLOTS] = {};
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  double timing[8] = {};
+
+  void* ws(Slot s, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (cap[s] < bytes) {
+      if (buf[s]) (void)hipFree(buf[s]);
+      buf[s] = nullptr;
+      cap[s] = 0;
+      if (hipMalloc(&buf[s], bytes) != hipSuccess) return nullptr;
+      cap[s] = bytes;
+    }
+    return buf[s];
+  }
+  char* host(size_t bytes) {
+    if (pinned_cap < bytes) {
+      if (pinned) (void)hipHostFree(pinned);
+      pinned = nullptr;
+      pinned_cap = 0;
+      if (hipHostMalloc((void**)&pinned, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      pinned_cap = bytes;
+    }
+    return pinned;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// contour (host, FP64): Gauss-Legendre nodes by Newton iteration on P_n
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    // initial guess for the i-th largest root, refined by Newton's method
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = (n == 1) ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[n - 1 - i] = z;  // ascending order
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static bool gauss_allowed(int ne) {
+  return (ne >= 1 && ne <= 20) || ne == 24 || ne == 32 || ne == 40 || ne == 48 || ne == 56;
+}
+
+// nodes z_j and half-contour weights w_j on the ellipse through emin, emax (see mfeast.h)
+static void make_contour(double emin, double emax, int ne, int rule, int ratio_pct, std::vector<c64>& z,
+                         std::vector<c64>& w) {
+  const double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin), e = ratio_pct / 100.0;
+  z.resize(ne);
+  w.resize(ne);
+  std::vector<double> x, om;
+  if (rule == 0) gauss_legendre(ne, x, om);
+  for (int j = 0; j < ne; ++j) {
+    double th, sc;
+    if (rule == 0) {
+      th = 0.5 * M_PI * (1.0 - x[j]);
+      sc = om[j] / 4.0;
+    } else {
+      th = M_PI * (ne - (j + 1) + 0.5) / ne;
+      sc = 1.0 / (2.0 * ne);
+    }
+    z[j] = c64(c + r * std::cos(th), e * r * std::sin(th));
+    w[j] = c64(sc * e * r * std::cos(th), sc * r * std::sin(th));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// argument checks shared by the dense drivers (Table tab_info order)
+static int check_fpm(const int32_t* fpm, bool expert) {
+  auto f = [&](int i) { return fpm[i - 1]; };
+  if (!expert) {
+    if (f(16) != 0 && f(16) != 1) return 116;
+    if (f(16) == 0 && !gauss_allowed(f(2))) return 102;
+    if (f(16) == 1 && f(2) < 1) return 102;
+    if (f(18) <= 0) return 118;
+  } else if (f(2) < 1) {
+    return 102;
+  }
+  if (f(3) < 0 || f(3) > 16) return 103;
+  if (f(4) < 0) return 104;
+  if (f(5) != 0 && f(5) != 1) return 105;
+  if (f(6) != 0 && f(6) != 1) return 106;
+  if (f(14) != 0 && f(14) != 1) return 114;
+  if (f(42) != 0 && f(42) != 1) return 142;
+  return 0;
+}
+
+template <typename T> static int gemmT(hipStream_t s, bool am, bool cj, const GemmArgs& g) {
+  return gemm<double, is_cplx<T>::value>(s, am, cj, g, 1);
+}
+
+// row-major product C(MxN) = op(A) * B, helper for the internal blocks
+template <typename T>
+static int rm_gemm(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, bool a_mcontig, bool conj_a,
+                   const T* B, int64_t ldb, T* C, int64_t ldc, double alpha = 1.0, double beta = 0.0) {
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.a_bs = 0;
+  g.B = B; g.ldb = ldb; g.b_bs = 0;
+  g.C = C; g.ldc = ldc; g.c_bs = 0;
+  g.alpha = alpha; g.beta = beta;
+  return gemmT<T>(s, a_mcontig, conj_a, g);
+}
+
+#define MF_TRY(...)                      \
+  do {                                   \
+    if ((__VA_ARGS__) != 0) return -2;   \
+  } while (0)
+
+template <typename T, typename C>
+static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
+                       int32_t* fpm, double emin, double emax, int32_t* m0p, double* E, T* Xu, int64_t ldx,
+                       int32_t* Mout, double* res_out, double* epsout, int32_t* loop, const double* zne,
+                       const double* wne) {
+  constexpr bool CPLX = is_cplx<T>::value;
+  Timer total_t, ph;
+  total_t.start();
+  double t_fact = 0, t_solve = 0, t_prod = 0, t_eig = 0;
+  hipStream_t s = h->stream;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  auto f = [&](int i) { return fpm[i - 1]; };
+  const int ne = f(2);
+  int m0 = *m0p;
+  const double alpha = std::max(std::fabs(emin), std::fabs(emax));
+  const double eps = std::pow(10.0, -f(3));
+
+  std::vector<c64> z, w;
+  if (zne != nullptr) {
+    z.resize(ne);
+    w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+      z[j] = c64(zne[2 * j], zne[2 * j + 1]);
+      w[j] = c64(wne[2 * j], wne[2 * j + 1]);
+    }
+  } else {
+    make_contour(emin, emax, ne, f(16), f(18), z, w);
+  }
+
+  // ---------------- workspace
+  const int64_t nblk = (n + LU_NB - 1) / LU_NB;
+  const size_t szT = sizeof(T), szC = sizeof(C);
+  C* LU = (C*)h->ws(S_LU, (size_t)ne * n * n * szC);
+  C* Dinv = (C*)h->ws(S_DINV, (size_t)ne * nblk * 2 * LU_NB * LU_NB * szC);
+  int* ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
+  int* perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);
+  int* pinv = (int*)h->ws(S_PINV, (size_t)ne * n * 4);
+  int* linfo = (int*)h->ws(S_INFO, (size_t)ne * 4 + 64);
+  c64* zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
+  C* Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0 * szC);
+  C* Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0 * szC) : nullptr;
+  const size_t blk = (size_t)n * m0 * szT;
+  T* Xw = (T*)h->ws(S_X, blk);
+  T* Q = (T*)h->ws(S_Q, blk);
+  T* R = (T*)h->ws(S_R, blk);
+  T* AQ = (T*)h->ws(S_AQ, blk);
+  T* BQ = B ? (T*)h->ws(S_BQ, blk) : Q;
+  T* AX = (T*)h->ws(S_AX, blk);
+  T* BX = B ? (T*)h->ws(S_BX, blk) : Xw;
+  const size_t sq = (size_t)m0 * m0 * szT;
+  T* Sm = (T*)h->ws(S_S, sq);
+  T* Tm = (T*)h->ws(S_T, sq);
+  T* Hw = (T*)h->ws(S_HW, sq);
+  T* V = (T*)h->ws(S_V, sq);
+  T* G = (T*)h->ws(S_G, sq);
+  T* TG = (T*)h->ws(S_TG, sq);
+  T* Cm = (T*)h->ws(S_C, sq);
+  T* Zm = (T*)h->ws(S_Z2, sq);
+  T* GZ = (T*)h->ws(S_GZ, sq);
+  T* W = (T*)h->ws(S_W, sq);
+  // small device arrays, packed
+  const size_t nsmall = (size_t)m0 * 12 + (size_t)ne * m0 * 4 + 64;
+  double* small = (double*)h->ws(S_SMALL, nsmall * sizeof(double));
+  const int nchunk = (int)((n + 255) / 256);
+  double* part = (double*)h->ws(S_PART, (size_t)nchunk * m0 * 2 * sizeof(double));
+  int* dflag = (int*)h->ws(S_FLAG, 256);
+  char* hp = h->host(nsmall * sizeof(double) + 4096);
+  if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Xw || !Q || !R ||
+      !AQ || !BQ || !AX || !BX || !Sm || !Tm || !Hw || !V || !G || !TG || !Cm || !Zm || !GZ || !W || !small ||
+      !part || !dflag || !hp)
+    return -2;
+  double* d_absmax = small;             // m0
+  double* d_cs = small + m0;            // m0
+  double* d_us = small + 2 * m0;        // m0
+  double* d_rho = small + 3 * m0;       // m0
+  double* d_dscale = small + 4 * m0;    // m0
+  double* d_evals = small + 5 * m0;     // m0
+  double* d_lam = small + 6 * m0;       // m0
+  double* d_rn = small + 7 * m0;        // m0
+  double* d_bn = small + 8 * m0;        // m0
+  double* d_gs = small + 9 * m0;        // m0
+  int* d_idx = (int*)(small + 10 * m0); // m0 ints (fits in m0 doubles)
+  int* d_perm = (int*)(small + 11 * m0);
+  c64* d_cf = (c64*)(small + 12 * m0);               // ne*m0
+  c64* d_cc = d_cf + (size_t)ne * m0;                // ne*m0
+  int* d_sweeps = (int*)(small + 12 * m0 + 4 * (size_t)ne * m0);
+  // pinned host staging (same packing)
+  double* h_absmax = (double*)hp;
+  double* h_cs = h_absmax + m0;
+  double* h_us = h_absmax + 2 * m0;
+  double* h_rho = h_absmax + 3 * m0;
+  double* h_evals = h_absmax + 5 * m0;
+  double* h_lam = h_absmax + 6 * m0;
+  double* h_rn = h_absmax + 7 * m0;
+  double* h_bn = h_absmax + 8 * m0;
+  double* h_gs = h_absmax + 9 * m0;
+  int* h_idx = (int*)(h_absmax + 10 * m0);
+  int* h_perm = (int*)(h_absmax + 11 * m0);
+  c64* h_cf = (c64*)(h_absmax + 12 * m0);
+  c64* h_cc = h_cf + (size_t)ne * m0;
+  int* h_flag = (int*)(h_absmax + 12 * m0 + 4 * (size_t)ne * m0);
+
+  // ---------------- full storage if a triangle was given
+  const T* Af = A;
+  int64_t ldaf = lda;
+  const T* Bf = B;
+  int64_t ldbf = ldb;
+  if (uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u') {
+    T* a2 = (T*)h->ws(S_AF, (size_t)n * n * szT);
+    if (!a2) return -2;
+    MF_TRY(expand_full<T>(s, uplo, n, A, lda, a2));
+    Af = a2;
+    ldaf = n;
+    if (B) {
+      T* b2 = (T*)h->ws(S_BF, (size_t)n * n * szT);
+      if (!b2) return -2;
+      MF_TRY(expand_full<T>(s, uplo, n, B, ldb, b2));
+      Bf = b2;
+      ldbf = n;
+    }
+  }
+
+  // ---------------- factor every shifted matrix
+  ph.start();
+  MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+  MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
+  MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
+  MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
+  std::vector<int> hinfo(ne);
+  MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
+  MF_HIP_CHECK(hipStreamSynchronize(s));
+  t_fact += ph.stop();
+  for (int j = 0; j < ne; ++j)
+    if (hinfo[j] != 0) return -2;
+
+  // ---------------- starting block
+  if (f(5) == 1) MF_TRY(copy_cm_to_rm<T>(s, n, m0, Xu, ldx, Xw, m0));
+  else MF_TRY(random_block<T>(s, n, m0, (uint64_t)(uint32_t)f(51), Xw, m0));
+
+  std::vector<double> lam_sorted;
+  double trace_prev = 0.0;
+  int info = 0;
+  int M = 0;
+  int k = 0;
+  std::vector<double> res_h;
+  for (;;) {
+    // ---- right-hand side block: B*Y (first contour) or the FP64 residual R
+    ph.start();
+    const bool resid = (k > 0);
+    const T* rhs;
+    if (!resid) {
+      if (B) {
+        MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Xw, m0, R, m0));
+        rhs = R;
+      } else {
+        rhs = Xw;
+      }
+    } else {
+      rhs = R;
+    }
+    MF_TRY(col_absmax<T>(s, n, m0, rhs, m0, d_absmax));
+    MF_HIP_CHECK(hipMemcpyAsync(h_absmax, d_absmax, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < m0; ++c) {
+      const double a = h_absmax[c];
+      const bool ok = a > 0.0 && std::isfinite(a);
+      if (!std::isfinite(a)) return -2;
+      h_cs[c] = ok ? 1.0 / a : 1.0;
+      h_us[c] = ok ? a : 1.0;
+    }
+    for (int j = 0; j < ne; ++j) {
+      for (int c = 0; c < m0; ++c) {
+        if (resid) {
+          const std::complex<double> zj(z[j].re, z[j].im), wj(w[j].re, w[j].im);
+          const std::complex<double> a = wj / (zj - lam_sorted[c]);
+          const std::complex<double> b = std::conj(wj) / (std::conj(zj) - lam_sorted[c]);
+          h_cf[(size_t)j * m0 + c] = c64(a.real(), a.imag());
+          h_cc[(size_t)j * m0 + c] = c64(b.real(), b.imag());
+        } else {
+          h_cf[(size_t)j * m0 + c] = w[j];
+          h_cc[(size_t)j * m0 + c] = c64(w[j].re, -w[j].im);
+        }
+      }
+    }
+    for (int c = 0; c < m0; ++c) {
+      double rho = 0.0;
+      if (resid) {
+        for (int j = 0; j < ne; ++j) {
+          const std::complex<double> zj(z[j].re, z[j].im), wj(w[j].re, w[j].im);
+          rho += 2.0 * (wj / (zj - lam_sorted[c])).real();
+        }
+      }
+      h_rho[c] = rho;
+    }
+    // slots are laid out for the initial M0; m0 may have shrunk since, so copy each array
+    MF_HIP_CHECK(hipMemcpyAsync(d_cs, h_cs, m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_us, h_us, m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_rho, h_rho, m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_cf, h_cf, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_cc, h_cc, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_TRY(rhs_prepare<T, C>(s, n, m0, rhs, m0, d_cs, ne, perm, Wf, Wc));
+    MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Dinv, Wf, Wc));
+    MF_TRY(accumulate<T, C>(s, n, m0, ne, Wf, Wc, pinv, d_cf, d_cc, d_rho, d_us, Xw, Q, resid ? 1 : 0));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_solve += ph.stop();
+
+    if (f(14) == 1) {
+      MF_TRY(copy_rm_to_cm<T>(s, n, m0, Q, m0, Xu, ldx));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      *m0p = m0;
+      *Mout = 0;
+      *loop = 0;
+      *epsout = 1.0;
+      info = 4;
+      break;
+    }
+
+    // ---- Rayleigh-Ritz
+    ph.start();
+    MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Af, ldaf, true, false, Q, m0, AQ, m0));
+    if (B) MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Q, m0, BQ, m0));
+    MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, BQ, m0, Sm, m0));
+    MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, AQ, m0, Tm, m0));
+    MF_HIP_CHECK(hipMemsetAsync(dflag, 0, 16, s));
+    MF_TRY(gram_equilibrate<T>(s, m0, Sm, Tm, d_dscale, dflag));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_prod += ph.stop();
+    ph.start();
+    MF_TRY(jacobi_eigh<T>(s, m0, Sm, V, d_evals, d_sweeps, (double*)Hw));
+    MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(h_flag, dflag, 4, hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    if (h_flag[0] != 0) { info = -3; break; }
+    double smax = 0.0;
+    for (int i = 0; i < m0; ++i) smax = std::max(smax, h_evals[i]);
+    int kk = 0;
+    for (int i = 0; i < m0; ++i)
+      if (smax > 0.0 && h_evals[i] > RANK_TOL * smax) {
+        h_idx[kk] = i;
+        h_gs[kk] = 1.0 / std::sqrt(h_evals[i]);
+        ++kk;
+      }
+    if (kk == 0) { info = -3; break; }
+    MF_HIP_CHECK(hipMemcpyAsync(d_idx, h_idx, kk * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_gs, h_gs, kk * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_TRY(gather_scale_cols<T>(s, m0, kk, V, m0, d_idx, d_gs, G, kk));
+    MF_TRY(rm_gemm<T>(s, m0, kk, m0, Tm, m0, false, false, G, kk, TG, kk));
+    MF_TRY(rm_gemm<T>(s, kk, kk, m0, G, kk, true, true, TG, kk, Cm, kk));
+    MF_TRY(jacobi_eigh<T>(s, kk, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
+    MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    ph.start();
+    // order: inside [emin, emax] ascending, then outside ascending
+    std::vector<int> ord(kk);
+    for (int i = 0; i < kk; ++i) ord[i] = i;
+    auto inside = [&](double l) { return l >= emin && l <= emax; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      const bool ia = inside(h_evals[a]), ib = inside(h_evals[b]);
+      if (ia != ib) return ia;
+      return h_evals[a] < h_evals[b];
+    });
+    M = 0;
+    lam_sorted.assign(kk, 0.0);
+    for (int i = 0; i < kk; ++i) {
+      h_perm[i] = ord[i];
+      lam_sorted[i] = h_evals[ord[i]];
+      h_lam[i] = lam_sorted[i];
+      if (inside(lam_sorted[i])) ++M;
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(d_perm, h_perm, kk * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_lam, h_lam, kk * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_TRY(rm_gemm<T>(s, m0, kk, kk, G, kk, false, false, Zm, kk, GZ, kk));
+    MF_TRY(scale_rows_permute_cols<T>(s, m0, kk, GZ, kk, d_dscale, d_perm, W, kk));
+    // X = Q W, AX = (AQ) W, BX = (BQ) W; the new blocks are n x kk with leading dimension kk
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, W, kk, Xw, kk));
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, W, kk, AX, kk));
+    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQ, m0, false, false, W, kk, BX, kk));
+    m0 = kk;
+    MF_TRY(residual_norms<T>(s, n, m0, AX, BX, d_lam, R, d_rn, d_bn, part));
+    MF_HIP_CHECK(hipMemcpyAsync(h_rn, d_rn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(h_bn, d_bn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_prod += ph.stop();
+    res_h.assign(m0, 0.0);
+    double maxres = 0.0;
+    bool finite = true;
+    for (int i = 0; i < m0; ++i) {
+      res_h[i] = std::sqrt(h_rn[i]) / (alpha * std::sqrt(h_bn[i]));
+      if (!std::isfinite(res_h[i])) finite = false;
+      if (i < M) maxres = std::max(maxres, res_h[i]);
+    }
+    if (!finite) { info = -2; break; }
+    double trace = 0.0;
+    for (int i = 0; i < M; ++i) trace += lam_sorted[i];
+    const double eo = (k == 0) ? 1.0 : std::fabs(trace - trace_prev) / alpha;
+    trace_prev = trace;
+    *epsout = eo;
+    *loop = k;
+    *Mout = M;
+    if (k == 0 && M == 0) { info = 1; break; }
+    if (M >= m0) { info = 3; break; }
+    const bool conv = (f(6) == 1) ? (maxres < eps) : (eo < eps);
+    if (conv) { info = 0; break; }
+    if (k >= f(4)) { info = 2; break; }
+    ++k;
+  }
+
+  if (info != 4 && info != -3 && info != -2) {
+    // copy eigenpairs to the caller's layout
+    MF_TRY(copy_rm_to_cm<T>(s, n, m0, Xw, m0, Xu, ldx));
+    MF_HIP_CHECK(hipMemcpyAsync(E, lam_sorted.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(res_out, res_h.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    *m0p = m0;
+  }
+  h->timing[0] = t_fact;
+  h->timing[1] = t_solve;
+  h->timing[2] = t_prod;
+  h->timing[3] = t_eig;
+  h->timing[5] = total_t.stop();
+  h->timing[4] = h->timing[5] - t_fact - t_solve - t_prod - t_eig;
+  h->timing[6] = (double)(*loop + 1);
+  h->timing[7] = 0.0;
+  return info;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X,
+                       int64_t ldx, int32_t* M, double* res, double* epsout, int32_t* loop, const double* zne,
+                       const double* wne) {
+  // Table tab_info order: N, M0, interval, fpm, then argument positions
+  if (n < 1) return 202;
+  if (m0 == nullptr) return -111;
+  if (*m0 < 1 || *m0 > n) return 201;
+  if (!(emin < emax)) return 200;
+  if (fpm == nullptr) return -108;
+  if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -119 : -120;
+  const int fi = check_fpm(fpm, zne != nullptr);
+  if (fi) return fi;
+  if (h == nullptr) return -101;
+  if (!(uplo == 'F' || uplo == 'f' || uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) return -102;
+  if (A == nullptr) return -104;
+  if (lda < n) return -105;
+  if (B != nullptr && ldb < n) return -107;
+  if (E == nullptr) return -112;
+  if (X == nullptr) return -113;
+  if (ldx < n) return -114;
+  if (M == nullptr) return -115;
+  if (res == nullptr) return -116;
+  if (epsout == nullptr) return -117;
+  if (loop == nullptr) return -118;
+  const T* At = reinterpret_cast<const T*>(A);
+  const T* Bt = reinterpret_cast<const T*>(B);
+  T* Xt = reinterpret_cast<T*>(X);
+  if (fpm[41] == 1)
+    return feast_dense<T, c32>(h, uplo, n, At, lda, Bt, ldb, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop,
+                               zne, wne);
+  return feast_dense<T, c64>(h, uplo, n, At, lda, Bt, ldb, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop,
+                             zne, wne);
+}
+
+extern "C" {
+
+int mfeast_create(mfeast_handle* h, int device, void* hip_stream) {
+  if (h == nullptr) return -101;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0 || device < 0 || device >= count) return -900;
+  if (hipSetDevice(device) != hipSuccess) return -900;
+  mfeast_ctx* c = new mfeast_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *h = c;
+  return 0;
+}
+
+int mfeast_destroy(mfeast_handle h) {
+  if (h == nullptr) return -101;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (int i = 0; i < S_NSLOTS; ++i)
+    if (h->buf[i]) (void)hipFree(h->buf[i]);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return 0;
+}
+
+int mfeast_set_stream(mfeast_handle h, void* hip_stream) {
+  if (h == nullptr) return -101;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return 0;
+}
+
+void mfeast_init(int32_t* fpm) {
+  if (fpm == nullptr) return;
+  for (int i = 0; i < 64; ++i) fpm[i] = 0;
+  fpm[0] = 0;    // fpm(1)  no runtime comments
+  fpm[1] = 8;    // fpm(2)  half-contour nodes
+  fpm[2] = 12;   // fpm(3)  eps = 1e-12
+  fpm[3] = 20;   // fpm(4)  refinement loops
+  fpm[4] = 0;    // fpm(5)  no initial guess
+  fpm[5] = 1;    // fpm(6)  residual criterion
+  fpm[7] = 16;   // fpm(8)  full-contour nodes (non-Hermitian, unused)
+  fpm[9] = 1;    // fpm(10) factorizations stored
+  fpm[13] = 0;   // fpm(14) normal run
+  fpm[14] = 2;   // fpm(15) left = right* (Hermitian)
+  fpm[15] = 0;   // fpm(16) Gauss-Legendre
+  fpm[17] = 30;  // fpm(18) ellipse ratio 0.30
+  fpm[40] = 1;   // fpm(41) matrix scaling (sparse drivers)
+  fpm[41] = 1;   // fpm(42) single-precision solves
+  fpm[44] = 1;   // fpm(45) BiCGStab accuracy 1e-1
+  fpm[45] = 40;  // fpm(46) BiCGStab iterations
+  fpm[50] = 0;   // fpm(51) seed of the random starting block
+}
+
+int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct, double* zne, double* wne) {
+  if (!(emin < emax)) return 200;
+  if (rule != 0 && rule != 1) return 116;
+  if ((rule == 0 && !gauss_allowed(ne)) || ne < 1) return 102;
+  if (ratio_pct <= 0) return 118;
+  if (zne == nullptr) return -106;
+  if (wne == nullptr) return -107;
+  std::vector<c64> z, w;
+  make_contour(emin, emax, ne, rule, ratio_pct, z, w);
+  for (int j = 0; j < ne; ++j) {
+    zne[2 * j] = z[j].re;
+    zne[2 * j + 1] = z[j].im;
+    wne[2 * j] = w[j].re;
+    wne[2 * j + 1] = w[j].im;
+  }
+  return 0;
+}
+
+int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M,
+                 double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
+  return dense_entry<double>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, zne,
+                             wne);
+}
+
+int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M,
+                 double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
+  return dense_entry<c64>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, zne,
+                          wne);
+}
+
+int mfeast_get_timing(mfeast_handle h, double* out) {
+  if (h == nullptr) return -101;
+  if (out == nullptr) return -102;
+  for (int i = 0; i < 8; ++i) out[i] = h->timing[i];
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Launch wrappers of the HIP kernels behind the C interface (internal header).
+//
+// Conventions shared by every kernel:
+//  * the user's A, B, X are column-major with a leading dimension (LAPACK);
+//  * every internal n x m block (Q, X, R, A*Q, B*Q, right-hand sides) is
+//    row-major, so a row permutation moves contiguous rows;
+//  * the shifted matrices z_j B - A and their LU factors are row-major, one
+//    n x n matrix per quadrature node, stored back to back;
+//  * complex values are interleaved (re, im).
+#pragma once
+
+#include "common.hpp"
+
+namespace mf {
+
+// ------------------------------------------------------------------ GEMM
+struct GemmArgs {
+  int M, N, K;
+  const void* A;
+  int64_t lda, a_bs;  // element (i,k) of op(A): A[i*lda+k] (K-contiguous) or A[i+k*lda] (M-contiguous)
+  const void* B;
+  int64_t ldb, b_bs;  // element (k,j) of B: B[k*ldb+j]
+  void* C;
+  int64_t ldc, c_bs;  // element (i,j) of C: C[i*ldc+j]
+  double alpha, beta;
+};
+template <typename R, bool CPLX>
+int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batch);
+
+// ------------------------------------------------------------------ LU
+constexpr int LU_NB = 64;  // outer panel width of the blocked LU and of the blocked solves
+
+// Full Hermitian/symmetric copy (ld = n, column-major) from the triangle named by uplo.
+template <typename T>
+int expand_full(hipStream_t s, char uplo, int64_t n, const T* src, int64_t lds, T* dst);
+
+// LU_j = z_j * B - A, row-major, for j = 0..ne-1 (B == nullptr means identity);
+// also sets perm_j = identity.  A, B: full storage column-major (ld).
+template <typename T, typename C>
+int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
+               const c64* z_dev, int ne, C* LU, int* perm);
+
+// Blocked right-looking LU with partial pivoting of all ne matrices (P A = L U).
+// ipiv (n per node, global row indices), perm (n per node: (PA)[i] = A[perm[i]]),
+// perm_inv, a per-node info flag (>0: first zero pivot + 1), and Dinv: per node and per
+// diagonal block, the inverses of the unit-lower and of the upper LU_NB x LU_NB blocks
+// (row-major, 2 * LU_NB^2 entries per block, ceil(n / LU_NB) blocks per node).
+template <typename C>
+int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int* perm_inv, int* info,
+              C* Dinv);
+
+// ------------------------------------------------------------------ solves
+// Build per-node right-hand sides W_j (row-major n x m, type C) from an FP64 block RHS
+// (row-major, ld), each column multiplied by colscale[c]; forward blocks are gathered
+// with perm_j (W_j[i] = RHS[perm_j[i]]), conjugate-transpose blocks are not permuted.
+template <typename T, typename C>
+int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const double* colscale,
+                int ne, const int* perm, C* Wf, C* Wc);
+
+// Solve LU_j x = W_j (forward direction; Wf already permuted) and, if Wc != nullptr,
+// (LU_j)^H y = W_j for the conjugate direction (unpermuted on output; perm_inv is
+// applied by the accumulation).  In place, all nodes batched.
+template <typename C>
+int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv, C* Wf, C* Wc);
+
+// Q = (resid ? X*diag(rho) : 0) + diag-scaled sum over nodes (see accumulate in solve.hip).
+template <typename T, typename C>
+int accumulate(hipStream_t s, int64_t n, int m, int ne, const C* Wf, const C* Wc, const int* perm_inv,
+               const c64* coef_f, const c64* coef_c, const double* rho, const double* unscale,
+               const T* X, T* Q, int resid);
+
+// ------------------------------------------------------------------ Rayleigh-Ritz helpers
+template <typename T>
+int col_absmax(hipStream_t s, int64_t n, int m, const T* X, int64_t ld, double* out);  // out[c] = max_r |X[r][c]|
+template <typename T>
+int gram_equilibrate(hipStream_t s, int m, T* S, T* Tm, double* d, int* flag);
+template <typename T>
+int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work);
+template <typename T>
+int gather_scale_cols(hipStream_t s, int rows, int k, const T* V, int ldv, const int* idx,
+                      const double* scale, T* G, int ldg);
+template <typename T>
+int scale_rows_permute_cols(hipStream_t s, int rows, int k, const T* GZ, int ldgz, const double* d,
+                            const int* perm, T* W, int ldw);
+template <typename T>
+int residual_norms(hipStream_t s, int64_t n, int m, const T* AX, const T* BX, const double* lam, T* R,
+                   double* rnorm2, double* bnorm2, double* partial);
+template <typename T>
+int copy_rm_to_cm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
+template <typename T>
+int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
+template <typename T>
+int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld);
+
+}  // namespace mf

@@ -1,0 +1,99 @@
+"""CPU-side checks of the C interface: the library loads, exports every declared
+symbol, and its host logic (defaults, contour, argument checks) agrees with the
+guide's tables.  No call here touches a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfeast.h")
+
+mf = pytest.importorskip("paper_2002_04807_amd")
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void)\s+(mfeast_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mf.library()
+    names = _declared_symbols()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mf.EXPORTED)
+
+
+def test_defaults_match_feastinit_table():
+    got = mf.mfeast_init()
+    want = oracle.feastinit()
+    np.testing.assert_array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("rule,ratio,ne", [(0, 30, 8), (0, 100, 16), (0, 50, 5), (1, 100, 4), (1, 100, 16),
+                                           (0, 30, 56), (0, 30, 1)])
+def test_contour_matches_oracle(rule, ratio, ne):
+    info, z, w = mf.mfeast_contour(-0.7, 2.2, ne, rule, ratio)
+    assert info == 0
+    zo, wo = oracle.half_contour(-0.7, 2.2, ne, rule=rule, ratio_pct=ratio)
+    np.testing.assert_allclose(z, zo, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(w, wo, rtol=0, atol=1e-14)
+
+
+def test_contour_errors():
+    assert mf.mfeast_contour(1.0, 1.0, 8)[0] == 200
+    assert mf.mfeast_contour(0.0, 1.0, 21, 0)[0] == 102
+    assert mf.mfeast_contour(0.0, 1.0, 21, 1)[0] == 0
+    assert mf.mfeast_contour(0.0, 1.0, 8, 2)[0] == 116
+    assert mf.mfeast_contour(0.0, 1.0, 8, 0, 0)[0] == 118
+
+
+def _call(name, n=10, m0=4, emin=0.0, emax=1.0, fpm=None, handle=None, **kw):
+    """Invoke a dense entry point with host dummies and a NULL handle: only the
+    host-side argument checks can run (no device pointer is ever dereferenced)."""
+    fpm = oracle.feastinit().astype(np.int32) if fpm is None else fpm
+    dummy = np.zeros(8)
+    args = dict(uplo="F", A=dummy, lda=max(n, 1), B=None, ldb=max(n, 1), E=dummy, X=dummy, ldx=max(n, 1),
+                res=dummy)
+    args.update(kw)
+    out = getattr(mf, name)(handle, args["uplo"], n, args["A"], args["lda"], args["B"], args["ldb"], fpm,
+                            emin, emax, m0, args["E"], args["X"], args["ldx"], args["res"])
+    return out["info"]
+
+
+@pytest.mark.parametrize("name", ["mfeast_dsygv", "mfeast_zhegv"])
+def test_argument_checks_in_table_order(name):
+    assert _call(name, n=0) == 202
+    assert _call(name, m0=0) == 201
+    assert _call(name, m0=11) == 201
+    assert _call(name, emin=1.0, emax=1.0) == 200
+    for idx, val, code in [(1, 21, 102), (2, 17, 103), (3, -1, 104), (4, 2, 105), (5, 2, 106),
+                           (13, 3, 114), (15, 2, 116), (17, 0, 118), (41, 2, 142)]:
+        f = oracle.feastinit().astype(np.int32)
+        f[idx] = val
+        assert _call(name, fpm=f) == code, (idx, val)
+    # a consistent call reaches the handle check
+    assert _call(name) == -101
+    assert _call(name, handle=ctypes.c_void_p(1), uplo="X") == -102
+    assert _call(name, handle=ctypes.c_void_p(1), A=None) == -104
+    assert _call(name, handle=ctypes.c_void_p(1), lda=5) == -105
+    assert _call(name, handle=ctypes.c_void_p(1), B=np.zeros(4), ldb=3) == -107
+    assert _call(name, handle=ctypes.c_void_p(1), E=None) == -112
+    assert _call(name, handle=ctypes.c_void_p(1), X=None) == -113
+    assert _call(name, handle=ctypes.c_void_p(1), ldx=2) == -114
+    assert _call(name, handle=ctypes.c_void_p(1), res=None) == -116
+
+
+def test_create_without_device_reports_minus_900():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert mf.library().mfeast_create(ctypes.byref(h), 0, None) == -900
