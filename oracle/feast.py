@@ -27,8 +27,15 @@ What is computed follows the guide:
 
 Readings where the guide is silent (each is listed with its reason in the
 design notes of the repository):
-  R-order   E(1:M) are the Ritz values inside [Emin, Emax] ascending, followed by
-            the outside ones ascending; X columns follow E.
+  R-spur    a Ritz pair counts as found (one of the M) when its value lies in
+            [Emin, Emax] and its relative residual is below SPURIOUS_RES = 0.1.
+            Ritz values inside the interval with a larger residual are spurious:
+            their Ritz vectors mix eigenvectors from both sides of the interval
+            whose filter weights are small, so they carry no eigenvalue; they are
+            listed with the outside values.  M, the trace and the convergence test
+            use the found pairs only.
+  R-order   E(1:M) are the found Ritz values ascending, followed by all others
+            ascending; X columns follow E.
   R-closed  the interval is closed.
   R-rank    the reduced overlap S = Q^H B Q is equilibrated (unit diagonal), then
             eigen-decomposed; directions with eigenvalue <= RANK_TOL * max are
@@ -37,8 +44,10 @@ design notes of the repository):
             nothing is kept.
   R-loop    loop is the index of the last iteration; iteration 0 is the first
             contour (HelloWorld output prints rows 0 and 1, then loop = 1).
-  R-info1   info = 1 when no Ritz value lies in the interval after iteration 0.
-  R-info3   info = 3 when every Ritz value lies in the interval (M >= M0).
+  R-info1   info = 1 when no Ritz value at all lies in the interval (after any
+            iteration); found pairs are required before convergence is declared.
+  R-info3   info = 3 when every Ritz value lies in the interval (no outside
+            value shows that the subspace holds all of them; M0 too small).
   R-conv    convergence is tested on the M pairs inside the interval only; at
             iteration 0 epsout = 1.
 """
@@ -50,6 +59,7 @@ from .contour import GAUSS_ALLOWED, half_contour, rational_filter
 from .splitmix import initial_subspace
 
 RANK_TOL = 1.0e-13
+SPURIOUS_RES = 1.0e-1
 
 
 def feastinit():
@@ -133,14 +143,18 @@ def expand_uplo(A, uplo):
     return T + T.conj().T + D
 
 
-def _ordered(lam, emin, emax):
-    """Permutation: Ritz values inside [emin, emax] ascending, then outside ascending."""
+def _ordered(lam, res, emin, emax):
+    """Permutation: found pairs (R-spur) ascending, then all others ascending.
+
+    Returns (perm, M, n_inside) with n_inside the count of Ritz values in the
+    interval regardless of their residual."""
     inside = (lam >= emin) & (lam <= emax)
-    idx_in = np.where(inside)[0]
-    idx_out = np.where(~inside)[0]
+    found = inside & (res < SPURIOUS_RES)
+    idx_in = np.where(found)[0]
+    idx_out = np.where(~found)[0]
     idx_in = idx_in[np.argsort(lam[idx_in], kind="stable")]
     idx_out = idx_out[np.argsort(lam[idx_out], kind="stable")]
-    return np.concatenate([idx_in, idx_out]), int(idx_in.size)
+    return np.concatenate([idx_in, idx_out]), int(idx_in.size), int(np.sum(inside))
 
 
 def rayleigh_ritz(Q, A, B):
@@ -278,12 +292,12 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
         if rinfo:
             out.update(info=rinfo, loop=k)
             return out
-        perm, M = _ordered(lam, emin, emax)
-        lam_sorted = lam[perm]
-        X = Q @ W[:, perm]
+        X = Q @ W
         BX = X if B is None else B @ X
-        R = A @ X - BX * lam_sorted[None, :]
+        R = A @ X - BX * lam[None, :]
         res = np.linalg.norm(R, axis=0) / (alpha * np.linalg.norm(BX, axis=0))
+        perm, M, n_inside = _ordered(lam, res, emin, emax)
+        lam_sorted, X, res = lam[perm], X[:, perm], res[perm]
         trace = float(np.sum(lam_sorted[:M]))
         epsout = 1.0 if trace_prev is None else abs(trace - trace_prev) / alpha
         trace_prev = trace
@@ -291,13 +305,13 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
         out["history"].append({"it": k, "M": M, "trace": trace, "epsout": epsout,
                                "maxres": maxres, "m0": X.shape[1]})
         out.update(E=lam_sorted, X=X, M=M, res=res, epsout=epsout, loop=k, m0=X.shape[1])
-        if k == 0 and M == 0:
+        if n_inside == 0:
             out["info"] = 1
             return out
-        if M >= X.shape[1]:
+        if n_inside >= X.shape[1]:
             out["info"] = 3
             return out
-        converged = (maxres < eps) if f(6) == 1 else (epsout < eps)
+        converged = M > 0 and ((maxres < eps) if f(6) == 1 else (epsout < eps))
         if converged:
             out["info"] = 0
             return out

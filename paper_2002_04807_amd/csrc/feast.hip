@@ -30,6 +30,10 @@ using namespace mf;
 namespace {
 
 constexpr double RANK_TOL = 1.0e-13;  // kept directions of the equilibrated overlap: s > RANK_TOL * max s
+// Ritz values inside the interval with a relative residual at or above this bound are
+// spurious (mixtures of weakly filtered eigenvectors from outside the interval) and
+// are not counted among the M eigenvalues found.
+constexpr double SPURIOUS_RES = 1.0e-1;
 
 enum Slot {
   S_LU, S_DINV, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
@@ -324,7 +328,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   if (f(5) == 1) MF_TRY(copy_cm_to_rm<T>(s, n, m0, Xu, ldx, Xw, m0));
   else MF_TRY(random_block<T>(s, n, m0, (uint64_t)(uint32_t)f(51), Xw, m0));
 
-  std::vector<double> lam_sorted;
+  std::vector<double> lam_cur;
+  std::vector<int> order;
   double trace_prev = 0.0;
   int info = 0;
   int M = 0;
@@ -359,8 +364,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
       for (int c = 0; c < m0; ++c) {
         if (resid) {
           const std::complex<double> zj(z[j].re, z[j].im), wj(w[j].re, w[j].im);
-          const std::complex<double> a = wj / (zj - lam_sorted[c]);
-          const std::complex<double> b = std::conj(wj) / (std::conj(zj) - lam_sorted[c]);
+          const std::complex<double> a = wj / (zj - lam_cur[c]);
+          const std::complex<double> b = std::conj(wj) / (std::conj(zj) - lam_cur[c]);
           h_cf[(size_t)j * m0 + c] = c64(a.real(), a.imag());
           h_cc[(size_t)j * m0 + c] = c64(b.real(), b.imag());
         } else {
@@ -374,7 +379,7 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
       if (resid) {
         for (int j = 0; j < ne; ++j) {
           const std::complex<double> zj(z[j].re, z[j].im), wj(w[j].re, w[j].im);
-          rho += 2.0 * (wj / (zj - lam_sorted[c])).real();
+          rho += 2.0 * (wj / (zj - lam_cur[c])).real();
         }
       }
       h_rho[c] = rho;
@@ -438,22 +443,12 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_eig += ph.stop();
     ph.start();
-    // order: inside [emin, emax] ascending, then outside ascending
-    std::vector<int> ord(kk);
-    for (int i = 0; i < kk; ++i) ord[i] = i;
-    auto inside = [&](double l) { return l >= emin && l <= emax; };
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-      const bool ia = inside(h_evals[a]), ib = inside(h_evals[b]);
-      if (ia != ib) return ia;
-      return h_evals[a] < h_evals[b];
-    });
-    M = 0;
-    lam_sorted.assign(kk, 0.0);
+    // Ritz pairs keep the eigensolver's order internally; the reported order (found
+    // pairs ascending, then the others ascending) is applied when copying out.
+    lam_cur.assign(h_evals, h_evals + kk);
     for (int i = 0; i < kk; ++i) {
-      h_perm[i] = ord[i];
-      lam_sorted[i] = h_evals[ord[i]];
-      h_lam[i] = lam_sorted[i];
-      if (inside(lam_sorted[i])) ++M;
+      h_perm[i] = i;
+      h_lam[i] = lam_cur[i];
     }
     MF_HIP_CHECK(hipMemcpyAsync(d_perm, h_perm, kk * sizeof(int), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemcpyAsync(d_lam, h_lam, kk * sizeof(double), hipMemcpyHostToDevice, s));
@@ -470,34 +465,58 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_prod += ph.stop();
     res_h.assign(m0, 0.0);
-    double maxres = 0.0;
     bool finite = true;
     for (int i = 0; i < m0; ++i) {
       res_h[i] = std::sqrt(h_rn[i]) / (alpha * std::sqrt(h_bn[i]));
       if (!std::isfinite(res_h[i])) finite = false;
-      if (i < M) maxres = std::max(maxres, res_h[i]);
     }
     if (!finite) { info = -2; break; }
-    double trace = 0.0;
-    for (int i = 0; i < M; ++i) trace += lam_sorted[i];
+    // found pairs: inside the interval with a residual below the spurious threshold
+    int n_inside = 0;
+    M = 0;
+    double maxres = 0.0, trace = 0.0;
+    for (int i = 0; i < m0; ++i) {
+      const bool in = lam_cur[i] >= emin && lam_cur[i] <= emax;
+      n_inside += in ? 1 : 0;
+      if (in && res_h[i] < SPURIOUS_RES) {
+        ++M;
+        maxres = std::max(maxres, res_h[i]);
+        trace += lam_cur[i];
+      }
+    }
+    order.resize(m0);
+    for (int i = 0; i < m0; ++i) order[i] = i;
+    auto found = [&](int i) { return lam_cur[i] >= emin && lam_cur[i] <= emax && res_h[i] < SPURIOUS_RES; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const bool fa = found(a), fb = found(b);
+      if (fa != fb) return fa;
+      return lam_cur[a] < lam_cur[b];
+    });
     const double eo = (k == 0) ? 1.0 : std::fabs(trace - trace_prev) / alpha;
     trace_prev = trace;
     *epsout = eo;
     *loop = k;
     *Mout = M;
-    if (k == 0 && M == 0) { info = 1; break; }
-    if (M >= m0) { info = 3; break; }
-    const bool conv = (f(6) == 1) ? (maxres < eps) : (eo < eps);
+    if (n_inside == 0) { info = 1; break; }
+    if (n_inside >= m0) { info = 3; break; }
+    const bool conv = M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps));
     if (conv) { info = 0; break; }
     if (k >= f(4)) { info = 2; break; }
     ++k;
   }
 
   if (info != 4 && info != -3 && info != -2) {
-    // copy eigenpairs to the caller's layout
-    MF_TRY(copy_rm_to_cm<T>(s, n, m0, Xw, m0, Xu, ldx));
-    MF_HIP_CHECK(hipMemcpyAsync(E, lam_sorted.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_HIP_CHECK(hipMemcpyAsync(res_out, res_h.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    // copy eigenpairs to the caller's layout in the reported order
+    std::vector<double> e_out(m0), r_out(m0);
+    for (int i = 0; i < m0; ++i) {
+      h_perm[i] = order[i];
+      e_out[i] = lam_cur[order[i]];
+      r_out[i] = res_h[order[i]];
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(d_perm, h_perm, m0 * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_TRY(copy_rm_to_cm<T>(s, n, m0, Xw, m0, Xu, ldx, d_perm));
+    MF_HIP_CHECK(hipMemcpyAsync(E, e_out.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     *m0p = m0;
   }

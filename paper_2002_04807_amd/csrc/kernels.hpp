@@ -86,7 +86,8 @@ template <typename T>
 int residual_norms(hipStream_t s, int64_t n, int m, const T* AX, const T* BX, const double* lam, T* R,
                    double* rnorm2, double* bnorm2, double* partial);
 template <typename T>
-int copy_rm_to_cm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
+int copy_rm_to_cm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd,
+                  const int* colmap = nullptr);
 template <typename T>
 int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
 template <typename T>

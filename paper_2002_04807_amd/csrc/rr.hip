@@ -321,14 +321,14 @@ int residual_norms(hipStream_t s, int64_t n, int m, const T* AX, const T* BX, co
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_transpose_copy(int64_t rows, int64_t cols, const T* __restrict__ src, int64_t lds,
-                                 T* __restrict__ dst, int64_t ldd) {
-  // dst[j*ldd + i] = src[i*lds + j], tiled through LDS
+                                 T* __restrict__ dst, int64_t ldd, const int* __restrict__ colmap) {
+  // dst[j*ldd + i] = src[i*lds + colmap[j]] (colmap null: identity), tiled through LDS
   __shared__ T tile[32][33];
   const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int yy = ty; yy < 32; yy += 8) {
     const int64_t i = i0 + yy, j = j0 + tx;
-    if (i < rows && j < cols) tile[yy][tx] = src[i * lds + j];
+    if (i < rows && j < cols) tile[yy][tx] = src[i * lds + (colmap ? (int64_t)colmap[j] : j)];
   }
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
@@ -338,10 +338,11 @@ __global__ void k_transpose_copy(int64_t rows, int64_t cols, const T* __restrict
 }
 
 template <typename T>
-int copy_rm_to_cm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd) {
-  // src row-major n x m  ->  dst column-major n x m
+int copy_rm_to_cm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd,
+                  const int* colmap) {
+  // src row-major n x m  ->  dst column-major n x m, column j taken from src column colmap[j]
   dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
-  hipLaunchKernelGGL((k_transpose_copy<T>), grid, dim3(256), 0, s, n, (int64_t)m, src, lds, dst, ldd);
+  hipLaunchKernelGGL((k_transpose_copy<T>), grid, dim3(256), 0, s, n, (int64_t)m, src, lds, dst, ldd, colmap);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -349,7 +350,8 @@ template <typename T>
 int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd) {
   // src column-major n x m (viewed as row-major m x n) -> dst row-major n x m
   dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
-  hipLaunchKernelGGL((k_transpose_copy<T>), grid, dim3(256), 0, s, (int64_t)m, n, src, lds, dst, ldd);
+  hipLaunchKernelGGL((k_transpose_copy<T>), grid, dim3(256), 0, s, (int64_t)m, n, src, lds, dst, ldd,
+                     (const int*)nullptr);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -393,7 +395,7 @@ int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t l
                                           int);                                                                \
   template int residual_norms<T>(hipStream_t, int64_t, int, const T*, const T*, const double*, T*, double*,    \
                                  double*, double*);                                                            \
-  template int copy_rm_to_cm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t);                    \
+  template int copy_rm_to_cm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t, const int*);        \
   template int copy_cm_to_rm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t);                    \
   template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);
 

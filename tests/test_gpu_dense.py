@@ -159,9 +159,11 @@ def test_real_generalized_odd_m0_and_trapezoid():
     n = 97
     A, lam, U = gen.prescribed_real_problem(n, rng, -3, 3)
     H = rng.standard_normal((n, n))
-    B = np.eye(n) + 0.05 * H @ H.T
+    B = np.eye(n) + 0.3 * H @ H.T / n
     emin, emax = -0.5, 0.7
-    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    lam_pencil = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(B), np.linalg.solve(
+        np.linalg.cholesky(B), A).T))
+    cnt = int(np.sum((lam_pencil >= emin) & (lam_pencil <= emax)))
     m0 = int(np.ceil(1.6 * cnt)) + 5
     m0 += 1 - (m0 % 2)  # odd M0: the Jacobi ordering pads a phantom index
     Y = oracle.initial_subspace(n, m0, 5, False)

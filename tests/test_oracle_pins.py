@@ -365,3 +365,17 @@ def test_warnings_and_reduced_errors():
     assert oracle.feast_dense(A, None, 0.0, 0.5, 20, f)["info"] == 2
     # B not positive definite -> -3
     assert oracle.feast_dense(A, -np.eye(40), 0.0, 0.5, 20)["info"] == -3
+
+
+def test_spurious_ritz_values_are_not_counted():
+    """Uniform spectrum on [-10, 10], generalized complex pencil, M0 = 1.6 * count:
+    the weakly filtered outer subspace yields Ritz values inside the interval with
+    O(1) residuals; the count must still equal the prescribed one (R-spur reading)."""
+    A, B, lam, X = gen.prescribed_complex_pencil(512, seed=0)
+    cnt = int(np.sum((lam >= -1) & (lam <= 1)))
+    r = oracle.feast_dense(A, B, -1.0, 1.0, 75, oracle.feastinit())
+    assert r["info"] == 0 and r["M"] == cnt == inertia_count(A, B, -1.0, 1.0)
+    np.testing.assert_allclose(r["E"][:cnt], lam[(lam >= -1) & (lam <= 1)], atol=1e-12)
+    # iteration 0 did see more Ritz values in the interval than eigenvalues
+    assert max(h["M"] for h in r["history"]) == cnt
+    assert np.all(r["res"][:cnt] < 1e-12)
