@@ -1,0 +1,228 @@
+"""Benchmark: Hermitian FEAST contour-integration eigensolver on one MI355X.
+
+Workload (the metric's configuration): generalized complex Hermitian pencil,
+n = 4096, B = I + 0.1 C C^H / n, A = L U diag(lambda) U^H L^H with lambda ~ U[-10, 10]
+(seed 0; 385 eigenvalues in [-1, 1]), M0 = 600, 8-node Gauss-Legendre half contour
+(ellipse ratio 0.30), convergence at relative residual <= 1e-10 (fpm(3) = 10).
+One step = one complete mfeast_zhegv call (factor all nodes, iterate the contour
+solves and Rayleigh-Ritz to convergence) on inputs already resident in HBM,
+starting from the library's seeded random block.  FP32 solves with the FP64
+residual form (fpm(42) = 1) is the reported value; the plain complex FP64 form
+(fpm(42) = 0) is timed beside it.
+
+Prints ONE JSON line (rank 0).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res≤1e-10"
+PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp64_vector": 78.6, "hbm": 8000.0}
+N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
+RES_BAR = 1e-10
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile-steps", type=int, default=0,
+                   help="only run this many FP32 steps (for rocprofv3 runs); no JSON extras")
+    return p.parse_args()
+
+
+def run_steps(mf, torch, h, At, Bt, fp32, steps, profile):
+    dt = torch.complex128
+    E = torch.zeros(M0, dtype=torch.float64, device=At.device)
+    res = torch.zeros(M0, dtype=torch.float64, device=At.device)
+    X = torch.zeros((M0, N), dtype=dt, device=At.device).mT
+    outs, times, profs = [], [], []
+    for _ in range(steps):
+        fpm = mf.mfeast_init()
+        fpm[41] = 1 if fp32 else 0   # fpm(42): FP32 solves + FP64 residual form, or plain FP64
+        fpm[2] = 10                  # fpm(3): residual tolerance 1e-10 (the metric's bar)
+        fpm[51] = 1 if profile else 0  # fpm(52): per-class device timing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = mf.mfeast_zhegv(h, "F", N, At, N, Bt, N, fpm, EMIN, EMAX, M0, E, X, N, res)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        out["E"] = E[:out["m0"]].cpu().numpy().copy()
+        out["res"] = res[:out["m0"]].cpu().numpy().copy()
+        out["timing"] = h.timing()
+        if profile:
+            profs.append(h.profile())
+        outs.append(out)
+    return outs, times, profs
+
+
+def accuracy(out, lam_in):
+    import numpy as np
+    M = out["M"]
+    cnt = lam_in.size
+    ok_count = (M == cnt)
+    res = out["res"][:M]
+    E = out["E"][:M]
+    alpha = max(abs(EMIN), abs(EMAX))
+    eig_err = float(np.max(np.abs(E - lam_in) / np.maximum(np.abs(lam_in), alpha))) if ok_count else None
+    m_conv = int(np.sum(res <= RES_BAR)) if ok_count else 0
+    return {"M": M, "exact_count": cnt, "count_exact": bool(ok_count), "max_rel_eig_err": eig_err,
+            "max_res": float(res.max()) if M else None, "converged_pairs": m_conv, "loop": out["loop"],
+            "info": out["info"]}
+
+
+def cpu_baseline(A, B, lam_in, loops):
+    """The oracle's own steps timed on a bounded sample: one node's complex128 LU, one
+    forward and one conjugate-transpose solve with M0 right-hand sides, and one
+    Rayleigh-Ritz step (A Q, B Q, Gram matrices, dense eigensolve), scaled to a whole
+    call with the same node count and loop count as the GPU FP64 run."""
+    import numpy as np
+    import scipy.linalg as sla
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    import oracle
+    from oracle.feast import rayleigh_ritz, _Factored
+    z, w = oracle.half_contour(EMIN, EMAX, NE)
+    rng = np.random.default_rng(1)
+    Y = (rng.standard_normal((N, M0)) + 1j * rng.standard_normal((N, M0)))
+    t0 = time.perf_counter()
+    fac = _Factored(z[0], A, B)
+    t_lu = time.perf_counter() - t0
+    BY = B @ Y
+    t0 = time.perf_counter()
+    fac.solve(BY)
+    fac.solve_h(BY)
+    t_solve2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rayleigh_ritz(Y, A, B)
+    t_rr = time.perf_counter() - t0
+    iters = loops + 1
+    t_est = NE * t_lu + iters * (NE * t_solve2 + t_rr)
+    m = lam_in.size
+    return {"value": m / t_est, "unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle",
+            "sample": "one node LU (complex128, n=4096) + one forward and one conjugate solve with "
+                      "600 right-hand sides + one Rayleigh-Ritz step (A Q, B Q, Grams, eigh 600), "
+                      "scaled to 8 nodes and %d loops: est. %.1f s per call "
+                      "(lu %.2f s, solves %.2f s, rr %.2f s)" % (iters, t_est, t_lu, t_solve2, t_rr)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the contour nodes would shard across GPUs with one all-reduce of Q per iteration)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2002_04807_amd as mf
+    from workloads import generators as gen
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    A, B, lam, _ = gen.prescribed_complex_pencil(N, seed=SEED)
+    lam_in = np.sort(lam[(lam >= EMIN) & (lam <= EMAX)])
+    print("bench: inputs built in %.1f s (%d eigenvalues in the interval)" % (time.perf_counter() - t0, lam_in.size),
+          file=sys.stderr, flush=True)
+    At = torch.from_numpy(np.asfortranarray(A)).to(dev)
+    Bt = torch.from_numpy(np.asfortranarray(B)).to(dev)
+    h = mf.Handle(0)
+
+    if args.profile_steps:
+        outs, times, _ = run_steps(mf, torch, h, At, Bt, True, args.profile_steps, False)
+        print("bench: profile run %s s, M=%s" % (["%.3f" % t for t in times], [o["M"] for o in outs]),
+              file=sys.stderr, flush=True)
+        return
+
+    run_steps(mf, torch, h, At, Bt, True, args.warmup, False)
+    outs, times, profs = run_steps(mf, torch, h, At, Bt, True, args.steps, True)
+    print("bench: fp32+IR steps %s s" % ["%.3f" % t for t in times], file=sys.stderr, flush=True)
+    acc = [accuracy(o, lam_in) for o in outs]
+    t_step = float(np.median(times))
+    m_conv = min(a["converged_pairs"] for a in acc)
+    value = m_conv / t_step
+
+    # contour-solve TFLOP/s from the device profile of the timed steps
+    loops = outs[-1]["loop"] + 1
+    f_alg = NE * (8.0 / 3.0) * N ** 3 + loops * (2 * NE) * 8.0 * N * N * M0
+    prof = profs[-1]
+    t_contour = sum(prof[c]["ms"] for c in ("lu_trailing_gemm", "lu_panel", "contour_solve", "other")) / 1e3
+    contour_tflops = f_alg / t_contour / 1e12 if t_contour > 0 else None
+
+    # dominant kernel class and its roofline
+    cls = max(prof, key=lambda c: prof[c]["ms"])
+    p = prof[cls]
+    if cls in ("lu_trailing_gemm", "contour_solve"):
+        bound, peak, unit = "mfma", PEAK["fp32_mfma"], "TFLOP/s"
+        achieved = p["flops"] / (p["ms"] / 1e3) / 1e12
+    elif cls == "rr_gemm":
+        bound, peak, unit = "mfma", PEAK["fp64_mfma"], "TFLOP/s"
+        achieved = p["flops"] / (p["ms"] / 1e3) / 1e12
+    elif cls == "other":
+        bound, peak, unit = "hbm", PEAK["hbm"], "GB/s"
+        achieved = p["bytes"] / (p["ms"] / 1e3) / 1e9
+    else:  # reduced eigensolver / panel: latency and vector ALU bound, no algorithmic flop count
+        bound, peak, unit = "alu", PEAK["fp64_vector"], "TFLOP/s"
+        achieved = p["flops"] / (p["ms"] / 1e3) / 1e12 if p["ms"] > 0 else 0.0
+    roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak if peak else None, "traffic": None, "kernel_class": cls,
+                "launches_per_step": p["launches"], "ms_per_step": p["ms"],
+                "classes_ms_per_step": {c: round(prof[c]["ms"], 3) for c in prof}}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 solves + f64 residual/RR", "data": "synthetic",
+        "config": {"workload": "generalized complex Hermitian n=4096, M0=600, 8-node Gauss half contour, "
+                               "interval [-1,1], res<=1e-10, FP32+IR (fpm42=1)",
+                   "n": N, "m0": M0, "nodes": NE, "seed": SEED},
+        "contour_tflops": contour_tflops,
+        "accuracy": acc[-1],
+        "roofline": roofline,
+    }
+
+    if not args.no_fp64:
+        run_steps(mf, torch, h, At, Bt, False, 1, False)
+        outs64, times64, profs64 = run_steps(mf, torch, h, At, Bt, False, max(1, args.steps), True)
+        print("bench: fp64 steps %s s" % ["%.3f" % t for t in times64], file=sys.stderr, flush=True)
+        acc64 = [accuracy(o, lam_in) for o in outs64]
+        t64 = float(np.median(times64))
+        v64 = min(a["converged_pairs"] for a in acc64) / t64
+        loops64 = outs64[-1]["loop"] + 1
+        f64_alg = NE * (8.0 / 3.0) * N ** 3 + loops64 * (2 * NE) * 8.0 * N * N * M0
+        p64 = profs64[-1]
+        t64c = sum(p64[c]["ms"] for c in ("lu_trailing_gemm", "lu_panel", "contour_solve", "other")) / 1e3
+        result["fp64_plain"] = {"value": v64, "ms_per_step": t64 * 1e3, "accuracy": acc64[-1],
+                                "contour_tflops": f64_alg / t64c / 1e12 if t64c > 0 else None,
+                                "classes_ms_per_step": {c: round(p64[c]["ms"], 3) for c in p64}}
+        result["speedup_fp32ir_vs_fp64"] = value / v64 if v64 > 0 else None
+        loops_cpu = outs64[-1]["loop"]
+    else:
+        loops_cpu = outs[-1]["loop"]
+
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        result["cpu_baseline"] = cpu_baseline(A, B, lam_in, loops_cpu)
+        print("bench: cpu baseline sample took %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    h.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

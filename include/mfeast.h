@@ -53,7 +53,8 @@ int mfeast_destroy(mfeast_handle h);
 int mfeast_set_stream(mfeast_handle h, void* hip_stream);
 
 /* Default parameters (feastinit; Table tab_fpm).  fpm: 64 int32 (host).
- * Project slot fpm(51) (reserved in the guide): seed of the random starting block. */
+ * Project slots (reserved in the guide): fpm(51) seed of the random starting block,
+ * fpm(52) = 1 records per-class kernel timings for mfeast_get_profile. */
 void mfeast_init(int32_t* fpm);
 
 /* Half-contour nodes and weights (zfeast_contour; Section 4.2 "Search contour",
@@ -102,9 +103,20 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
                  double* epsout, int32_t* loop, const double* zne, const double* wne);
 
-/* Timing of the last call, seconds (Fact, Solve, Ax/Bx/RR products, reduced eig, Misc,
- * Total, iterations, FP64 residual).  out: host, 8 doubles. */
+/* Timing of the last call in seconds, host clock around synchronized phases (the
+ * guide's "FEAST-RCI timing" split, Section 2.4): out[0] factorization, [1] contour
+ * solves, [2] Rayleigh-Ritz products and residuals, [3] reduced eigensolver, [4] other,
+ * [5] total, [6] number of subspace iterations, [7] reserved.  out: host, 8 doubles. */
 int mfeast_get_timing(mfeast_handle h, double* out);
+
+/* Device timing by kernel class of the last call, recorded with HIP events on the
+ * handle's stream when fpm(52)=1 was set for that call (project slot, reserved in the
+ * guide).  For class c: out[4c+0] launches (or launch groups), [4c+1] milliseconds,
+ * [4c+2] algorithmic flops (8 per complex multiply-add), [4c+3] algorithmic bytes.
+ * Classes: 0 LU trailing update, 1 LU panel, 2 contour solves (per direction),
+ * 3 FP64 Rayleigh-Ritz products, 4 reduced eigensolver, 5 other kernels.
+ * out: host, `count` doubles (24 cover all classes). */
+int mfeast_get_profile(mfeast_handle h, double* out, int32_t count);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ _lib_error = None
 
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_contour",
-    "mfeast_dsygv", "mfeast_zhegv", "mfeast_get_timing",
+    "mfeast_dsygv", "mfeast_zhegv", "mfeast_get_timing", "mfeast_get_profile",
 )
 
 
@@ -55,6 +55,8 @@ def _load():
         fn.restype = c_int
     lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_get_timing.restype = c_int
+    lib.mfeast_get_profile.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    lib.mfeast_get_profile.restype = c_int
     _lib = lib
     return lib
 
@@ -131,6 +133,15 @@ class Handle:
         _load().mfeast_get_timing(self.ptr, out)
         return list(out)
 
+    PROFILE_CLASSES = ("lu_trailing_gemm", "lu_panel", "contour_solve", "rr_gemm", "reduced_eig", "other")
+
+    def profile(self):
+        """Per-class device timing of the last call made with fpm[51] = 1."""
+        out = (ctypes.c_double * 24)()
+        _load().mfeast_get_profile(self.ptr, out, 24)
+        return {name: {"launches": out[4 * i], "ms": out[4 * i + 1], "flops": out[4 * i + 2],
+                       "bytes": out[4 * i + 3]} for i, name in enumerate(self.PROFILE_CLASSES)}
+
 
 def _dense_call(name, h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
     lib = _load()
@@ -202,6 +213,8 @@ def feast(A, B, emin, emax, m0, fpm=None, X0=None, uplo="F", handle=None, zne=No
         fn = mfeast_zhegv if cplx else mfeast_dsygv
         out = fn(h, uplo, n, A_, lda, B_, ldb, fpm, emin, emax, m0, E, X, n, res, zne, wne)
         out["timing"] = h.timing()
+        if fpm[51] == 1:
+            out["profile"] = h.profile()
     finally:
         if own:
             h.close()

@@ -60,6 +60,7 @@ struct mfeast_ctx {
   char* pinned = nullptr;
   size_t pinned_cap = 0;
   double timing[8] = {};
+  double prof[K_NCLASS * 4] = {};
 
   void* ws(Slot s, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -181,7 +182,20 @@ static int rm_gemm(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, 
   g.B = B; g.ldb = ldb; g.b_bs = 0;
   g.C = C; g.ldc = ldc; g.c_bs = 0;
   g.alpha = alpha; g.beta = beta;
-  return gemmT<T>(s, a_mcontig, conj_a, g);
+  const int tok = prof_begin(s);
+  const int rc = gemmT<T>(s, a_mcontig, conj_a, g);
+  const double fl = (is_cplx<T>::value ? 8.0 : 2.0) * (double)M * N * K;
+  prof_end(tok, s, K_RR_GEMM, fl, (double)sizeof(T) * ((double)M * K + (double)K * N + 2.0 * M * N));
+  return rc;
+}
+
+// reduced eigensolver call, timed as its own class
+template <typename T>
+static int eig_timed(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps, double* work) {
+  const int tok = prof_begin(s);
+  const int rc = jacobi_eigh<T>(s, m, H, V, evals, sweeps, work);
+  prof_end(tok, s, K_EIG, 0.0, 0.0);
+  return rc;
 }
 
 #define MF_TRY(...)                      \
@@ -201,6 +215,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   hipStream_t s = h->stream;
   if (hipSetDevice(h->device) != hipSuccess) return -900;
   auto f = [&](int i) { return fpm[i - 1]; };
+  prof_enable(f(52) == 1);
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
   const int ne = f(2);
   int m0 = *m0p;
   const double alpha = std::max(std::fabs(emin), std::fabs(emax));
@@ -244,7 +260,7 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   T* Hw = (T*)h->ws(S_HW, sq);
   T* V = (T*)h->ws(S_V, sq);
   T* G = (T*)h->ws(S_G, sq);
-  T* TG = (T*)h->ws(S_TG, sq);
+  T* TG = (T*)h->ws(S_TG, std::max(3 * sq, (size_t)m0 * 32 * szT));  // also Cholesky / Newton-Schulz work
   T* Cm = (T*)h->ws(S_C, sq);
   T* Zm = (T*)h->ws(S_Z2, sq);
   T* GZ = (T*)h->ws(S_GZ, sq);
@@ -315,7 +331,11 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   ph.start();
   MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
   MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
-  MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
+  {
+    const int tok = prof_begin(s);
+    MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
+    prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((B ? 2.0 : 1.0) * sizeof(T) + ne * sizeof(C)));
+  }
   MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
   std::vector<int> hinfo(ne);
   MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
@@ -330,6 +350,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
 
   std::vector<double> lam_cur;
   std::vector<int> order;
+  int last_sweeps = 0;
+  double last_dev = 0.0;
   double trace_prev = 0.0;
   int info = 0;
   int M = 0;
@@ -390,9 +412,17 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipMemcpyAsync(d_rho, h_rho, m0 * sizeof(double), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemcpyAsync(d_cf, h_cf, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemcpyAsync(d_cc, h_cc, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
-    MF_TRY(rhs_prepare<T, C>(s, n, m0, rhs, m0, d_cs, ne, perm, Wf, Wc));
-    MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Dinv, Wf, Wc));
-    MF_TRY(accumulate<T, C>(s, n, m0, ne, Wf, Wc, pinv, d_cf, d_cc, d_rho, d_us, Xw, Q, resid ? 1 : 0));
+    {
+      const double nb = (double)n * m0;
+      const int dirs = CPLX ? 2 : 1;
+      int tok = prof_begin(s);
+      MF_TRY(rhs_prepare<T, C>(s, n, m0, rhs, m0, d_cs, ne, perm, Wf, Wc));
+      prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
+      MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Dinv, Wf, Wc));
+      tok = prof_begin(s);
+      MF_TRY(accumulate<T, C>(s, n, m0, ne, Wf, Wc, pinv, d_cf, d_cc, d_rho, d_us, Xw, Q, resid ? 1 : 0));
+      prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));
+    }
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_solve += ph.stop();
 
@@ -407,59 +437,103 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
       break;
     }
 
-    // ---- Rayleigh-Ritz
+    // ---- Rayleigh-Ritz on span(Q) in an explicitly B-orthonormal basis (two passes)
     ph.start();
     MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Af, ldaf, true, false, Q, m0, AQ, m0));
-    if (B) MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Q, m0, BQ, m0));
-    MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, BQ, m0, Sm, m0));
-    MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, AQ, m0, Tm, m0));
+    T* BQp = Q;
+    if (B) {
+      MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Q, m0, BQ, m0));
+      BQp = BQ;
+    }
+    MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, BQp, m0, Sm, m0));
     MF_HIP_CHECK(hipMemsetAsync(dflag, 0, 16, s));
     MF_TRY(gram_equilibrate<T>(s, m0, Sm, Tm, d_dscale, dflag));
-    MF_HIP_CHECK(hipStreamSynchronize(s));
-    t_prod += ph.stop();
-    ph.start();
-    MF_TRY(jacobi_eigh<T>(s, m0, Sm, V, d_evals, d_sweeps, (double*)Hw));
-    MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    // pass 1: Cholesky of the equilibrated overlap with column dropping (d_perm = keep mask)
+    const double tau = 32.0 * m0 * 2.220446049250313e-16;
+    MF_TRY(chol_drop<T>(s, m0, Sm, Hw, d_perm, tau, TG));
+    MF_HIP_CHECK(hipMemcpyAsync(h_perm, d_perm, m0 * sizeof(int), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipMemcpyAsync(h_flag, dflag, 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     if (h_flag[0] != 0) { info = -3; break; }
-    double smax = 0.0;
-    for (int i = 0; i < m0; ++i) smax = std::max(smax, h_evals[i]);
     int kk = 0;
     for (int i = 0; i < m0; ++i)
-      if (smax > 0.0 && h_evals[i] > RANK_TOL * smax) {
-        h_idx[kk] = i;
-        h_gs[kk] = 1.0 / std::sqrt(h_evals[i]);
-        ++kk;
-      }
+      if (h_perm[i]) h_idx[kk++] = i;
     if (kk == 0) { info = -3; break; }
     MF_HIP_CHECK(hipMemcpyAsync(d_idx, h_idx, kk * sizeof(int), hipMemcpyHostToDevice, s));
-    MF_HIP_CHECK(hipMemcpyAsync(d_gs, h_gs, kk * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_TRY(gather_scale_cols<T>(s, m0, kk, V, m0, d_idx, d_gs, G, kk));
-    MF_TRY(rm_gemm<T>(s, m0, kk, m0, Tm, m0, false, false, G, kk, TG, kk));
-    MF_TRY(rm_gemm<T>(s, kk, kk, m0, G, kk, true, true, TG, kk, Cm, kk));
-    MF_TRY(jacobi_eigh<T>(s, kk, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
-    MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_TRY(build_h1<T>(s, m0, kk, Hw, d_dscale, d_idx, G));
+    // Q1 = Q H1, A Q1 = (A Q) H1, B Q1 = (B Q) H1  (no new product with A or B)
+    T* Q1 = R;
+    T* AQ1 = AX;
+    T* BQ1 = B ? BX : Q1;
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, G, kk, Q1, kk));
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, G, kk, AQ1, kk));
+    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQp, m0, false, false, G, kk, BQ1, kk));
+    // pass 2: S1 = Q1^H B Q1 = I + F, T1 = Q1^H A Q1
+    MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, BQ1, kk, Sm, kk));
+    MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, AQ1, kk, Tm, kk));
+    MF_TRY(hermitian_part<T>(s, kk, Sm));
+    MF_TRY(hermitian_part<T>(s, kk, Tm));
+    MF_TRY(dev_from_identity<T>(s, kk, Sm, part, d_bn));
+    double dev_f = 0.0;
+    MF_HIP_CHECK(hipMemcpyAsync(&h_bn[0], d_bn, sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
+    dev_f = h_bn[0];
+    if (!std::isfinite(dev_f)) { info = -2; break; }
+    t_prod += ph.stop();
+    ph.start();
+    int kk2 = kk;
+    T* G2 = V;
+    if (dev_f < 0.5) {
+      int iters = 1;
+      for (double e = dev_f; e > 1e-18 && iters < 12; ++iters) e = 0.75 * e * e + 1e-300;
+      MF_TRY(ns_invsqrt<T>(s, kk, Sm, V, iters, TG));
+      MF_TRY(hermitian_part<T>(s, kk, V));
+    } else {
+      // far from orthonormal: eigen-decompose S1 and drop its weak directions
+      MF_TRY(eig_timed<T>(s, kk, Sm, Zm, d_evals, d_sweeps, (double*)Hw));
+      MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk * sizeof(double), hipMemcpyDeviceToHost, s));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      double smax = 0.0;
+      for (int i = 0; i < kk; ++i) smax = std::max(smax, h_evals[i]);
+      kk2 = 0;
+      for (int i = 0; i < kk; ++i)
+        if (smax > 0.0 && h_evals[i] > RANK_TOL * smax) {
+          h_idx[kk2] = i;
+          h_gs[kk2] = 1.0 / std::sqrt(h_evals[i]);
+          ++kk2;
+        }
+      if (kk2 == 0) { info = -3; break; }
+      MF_HIP_CHECK(hipMemcpyAsync(d_idx, h_idx, kk2 * sizeof(int), hipMemcpyHostToDevice, s));
+      MF_HIP_CHECK(hipMemcpyAsync(d_gs, h_gs, kk2 * sizeof(double), hipMemcpyHostToDevice, s));
+      MF_TRY(gather_scale_cols<T>(s, kk, kk2, Zm, kk, d_idx, d_gs, V, kk2));
+    }
+    // C = G2^H T1 G2, eigenpairs of C
+    MF_TRY(rm_gemm<T>(s, kk, kk2, kk, Tm, kk, false, false, G2, kk2, TG, kk2));
+    MF_TRY(rm_gemm<T>(s, kk2, kk2, kk, G2, kk2, true, true, TG, kk2, Cm, kk2));
+    MF_TRY(hermitian_part<T>(s, kk2, Cm));
+    MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
+    int sweeps = 0;
+    MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(&sweeps, d_sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    last_sweeps = sweeps;
+    last_dev = dev_f;
     t_eig += ph.stop();
     ph.start();
     // Ritz pairs keep the eigensolver's order internally; the reported order (found
     // pairs ascending, then the others ascending) is applied when copying out.
-    lam_cur.assign(h_evals, h_evals + kk);
-    for (int i = 0; i < kk; ++i) {
-      h_perm[i] = i;
-      h_lam[i] = lam_cur[i];
-    }
-    MF_HIP_CHECK(hipMemcpyAsync(d_perm, h_perm, kk * sizeof(int), hipMemcpyHostToDevice, s));
-    MF_HIP_CHECK(hipMemcpyAsync(d_lam, h_lam, kk * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_TRY(rm_gemm<T>(s, m0, kk, kk, G, kk, false, false, Zm, kk, GZ, kk));
-    MF_TRY(scale_rows_permute_cols<T>(s, m0, kk, GZ, kk, d_dscale, d_perm, W, kk));
-    // X = Q W, AX = (AQ) W, BX = (BQ) W; the new blocks are n x kk with leading dimension kk
-    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, W, kk, Xw, kk));
-    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, W, kk, AX, kk));
-    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQ, m0, false, false, W, kk, BX, kk));
-    m0 = kk;
-    MF_TRY(residual_norms<T>(s, n, m0, AX, BX, d_lam, R, d_rn, d_bn, part));
+    lam_cur.assign(h_evals, h_evals + kk2);
+    for (int i = 0; i < kk2; ++i) h_lam[i] = lam_cur[i];
+    MF_HIP_CHECK(hipMemcpyAsync(d_lam, h_lam, kk2 * sizeof(double), hipMemcpyHostToDevice, s));
+    // W = G2 U;  X = Q1 W, AX = (A Q1) W, BX = (B Q1) W  (n x kk2, leading dimension kk2)
+    MF_TRY(rm_gemm<T>(s, kk, kk2, kk2, G2, kk2, false, false, Zm, kk2, W, kk2));
+    T* AXn = AQ;
+    T* BXn = B ? BQ : Xw;
+    MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, Q1, kk, false, false, W, kk2, Xw, kk2));
+    MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, AQ1, kk, false, false, W, kk2, AXn, kk2));
+    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, BQ1, kk, false, false, W, kk2, BXn, kk2));
+    m0 = kk2;
+    MF_TRY(residual_norms<T>(s, n, m0, AXn, BXn, d_lam, R, d_rn, d_bn, part));
     MF_HIP_CHECK(hipMemcpyAsync(h_rn, d_rn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipMemcpyAsync(h_bn, d_bn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -499,6 +573,12 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     *Mout = M;
     if (n_inside == 0) { info = 1; break; }
     if (n_inside >= m0) { info = 3; break; }
+    if (f(1) != 0) {
+      // runtime comments (fpm(1)): iteration, #eigenvalues, trace, relative trace change,
+      // largest residual of the found pairs, subspace size, spurious count
+      fprintf(stderr, "%3d %6d  %24.16E  %24.16E  %24.16E  m0=%d spurious=%d |S1-I|=%.1e sweeps=%d\n", k, M,
+              trace, eo, maxres, m0, n_inside - M, last_dev, last_sweeps);
+    }
     const bool conv = M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps));
     if (conv) { info = 0; break; }
     if (k >= f(4)) { info = 2; break; }
@@ -519,6 +599,11 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     *m0p = m0;
+  }
+  if (prof_on()) {
+    (void)hipStreamSynchronize(s);
+    prof_collect(h->prof);
+    prof_enable(false);
   }
   h->timing[0] = t_fact;
   h->timing[1] = t_solve;
@@ -620,6 +705,7 @@ void mfeast_init(int32_t* fpm) {
   fpm[44] = 1;   // fpm(45) BiCGStab accuracy 1e-1
   fpm[45] = 40;  // fpm(46) BiCGStab iterations
   fpm[50] = 0;   // fpm(51) seed of the random starting block
+  fpm[51] = 0;   // fpm(52) per-class kernel timing (mfeast_get_profile) off
 }
 
 int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct, double* zne, double* wne) {
@@ -652,6 +738,13 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
   return dense_entry<c64>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, zne,
                           wne);
+}
+
+int mfeast_get_profile(mfeast_handle h, double* out, int32_t count) {
+  if (h == nullptr) return -101;
+  if (out == nullptr) return -102;
+  for (int i = 0; i < count && i < K_NCLASS * 4; ++i) out[i] = h->prof[i];
+  return 0;
 }
 
 int mfeast_get_timing(mfeast_handle h, double* out) {

@@ -4,7 +4,9 @@
 //
 // op(A) is M x K and is read either K-contiguous (row-major, element (i,k) at
 // A[i*lda + k]) or M-contiguous (column-major / a transposed view, element (i,k)
-// at A[i + k*lda]), optionally conjugated.  B (K x N) and C (M x N) are row-major.
+// at A[i + k*lda]), optionally conjugated.  op(B) (K x N) is read N-contiguous
+// (element (k,j) at B[k*ldb + j]) or K-contiguous (B[k + j*ldb]), optionally
+// conjugated.  C (M x N) is row-major.
 // Complex operands are interleaved (re, im) in memory and planar in LDS; a
 // complex product is four real MFMAs (re*re - im*im, re*im + im*re), so the
 // flop count is 8 per complex multiply-add as in the algorithmic count.
@@ -34,7 +36,8 @@ template <> struct mfma_op<double> {
   __device__ static inline int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, int BM, int BN, int BK>
+template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
+          int TAG>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
@@ -55,7 +58,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int m0 = blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
   const int64_t bz = blockIdx.z;
-  const R* __restrict__ A = static_cast<const R*>(g.A) + bz * g.a_bs * ES;
+  const R* A = static_cast<const R*>(g.A) + bz * g.a_bs * ES;
   const R* B = static_cast<const R*>(g.B) + bz * g.b_bs * ES;
   R* C = static_cast<R*>(g.C) + bz * g.c_bs * ES;
   const int M = g.M, N = g.N, K = g.K;
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
     }
     // ---- B tile -> LDS [k][n]
-    {
+    if constexpr (!B_KCONTIG) {
       constexpr int KS = NT / BN;
 #pragma unroll
       for (int kk = tid / BN; kk < BK; kk += KS) {
@@ -117,7 +120,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           if constexpr (CPLX) im = B[off + 1];
         }
         Bs[0][kk][j] = re;
-        if constexpr (CPLX) Bs[1][kk][j] = im;
+        if constexpr (CPLX) Bs[1][kk][j] = CONJ_B ? -im : im;
+      }
+    } else {
+      constexpr int JS = NT / BK;
+#pragma unroll
+      for (int j = tid / BK; j < BN; j += JS) {
+        const int kk = tid % BK;
+        const int gj = n0 + j, gk = k0 + kk;
+        R re = R(0), im = R(0);
+        if (gj < N && gk < K) {
+          const int64_t off = ((int64_t)gk + (int64_t)gj * g.ldb) * ES;
+          re = B[off];
+          if constexpr (CPLX) im = B[off + 1];
+        }
+        Bs[0][kk][j] = re;
+        if constexpr (CPLX) Bs[1][kk][j] = CONJ_B ? -im : im;
       }
     }
     __syncthreads();
@@ -175,29 +193,48 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-template <typename R, bool CPLX, bool AM, bool CJ>
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
 static void launch(const GemmArgs& g, int batch, hipStream_t s) {
   constexpr int BM = 64, BN = 64, BK = 16;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
-  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BM, BN, BK>), grid, dim3(256), 0, s, g);
+  if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
+    if (g.tag == 1) {
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 1>), grid, dim3(256), 0, s, g);
+      return;
+    }
+    if (g.tag == 2) {
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 2>), grid, dim3(256), 0, s, g);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0>), grid, dim3(256), 0, s, g);
+}
+
+template <typename R, bool CPLX, bool AM, bool CJ>
+static void launch_b(GemmOp opb, const GemmArgs& g, int batch, hipStream_t s) {
+  if (opb == OP_N) launch<R, CPLX, AM, CJ, false, false>(g, batch, s);
+  else if (opb == OP_T || !CPLX) launch<R, CPLX, AM, CJ, true, false>(g, batch, s);
+  else launch<R, CPLX, AM, CJ, true, CPLX>(g, batch, s);
+}
+
+template <typename R, bool CPLX>
+int gemm_op(hipStream_t s, GemmOp opa, GemmOp opb, const GemmArgs& g, int batch) {
+  if (g.M <= 0 || g.N <= 0 || batch <= 0) return 0;
+  if (opa == OP_N) launch_b<R, CPLX, false, false>(opb, g, batch, s);
+  else if (opa == OP_T || !CPLX) launch_b<R, CPLX, true, false>(opb, g, batch, s);
+  else launch_b<R, CPLX, true, CPLX>(opb, g, batch, s);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 template <typename R, bool CPLX>
 int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batch) {
-  if (g.M <= 0 || g.N <= 0 || batch <= 0) return 0;
-  if (g.K <= 0) {
-    // C = beta * C only; route through the kernel with K = 0 (acc stays zero)
-  }
-  if (a_mcontig) {
-    if (conj_a && CPLX) launch<R, CPLX, true, true>(g, batch, s);
-    else launch<R, CPLX, true, false>(g, batch, s);
-  } else {
-    if (conj_a && CPLX) launch<R, CPLX, false, true>(g, batch, s);
-    else launch<R, CPLX, false, false>(g, batch, s);
-  }
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  const GemmOp opa = !a_mcontig ? OP_N : (conj_a ? OP_C : OP_T);
+  return gemm_op<R, CPLX>(s, opa, OP_N, g, batch);
 }
 
+template int gemm_op<float, true>(hipStream_t, GemmOp, GemmOp, const GemmArgs&, int);
+template int gemm_op<double, true>(hipStream_t, GemmOp, GemmOp, const GemmArgs&, int);
+template int gemm_op<double, false>(hipStream_t, GemmOp, GemmOp, const GemmArgs&, int);
 template int gemm<float, true>(hipStream_t, bool, bool, const GemmArgs&, int);
 template int gemm<double, true>(hipStream_t, bool, bool, const GemmArgs&, int);
 template int gemm<double, false>(hipStream_t, bool, bool, const GemmArgs&, int);

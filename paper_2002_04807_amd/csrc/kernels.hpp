@@ -10,6 +10,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace mf {
 
@@ -23,7 +24,13 @@ struct GemmArgs {
   void* C;
   int64_t ldc, c_bs;  // element (i,j) of C: C[i*ldc+j]
   double alpha, beta;
+  int tag;  // 1: LU trailing update, 2: contour-solve update (distinct kernel names), else 0
 };
+// operand forms: OP_N as stored (A K-contiguous, B N-contiguous), OP_T transposed view,
+// OP_C conjugate-transposed view
+enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2 };
+template <typename R, bool CPLX>
+int gemm_op(hipStream_t s, GemmOp opa, GemmOp opb, const GemmArgs& g, int batch);
 template <typename R, bool CPLX>
 int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batch);
 
@@ -92,5 +99,22 @@ template <typename T>
 int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
 template <typename T>
 int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld);
+
+// ------------------------------------------------------------------ B-orthonormalization (orth.hip)
+// Cholesky with column dropping of a Hermitian m x m row-major A (lower part): L in place,
+// Linv = pseudo-inverse of L, keep[j] = 1 for kept columns.  work >= 32 m entries.
+template <typename T>
+int chol_drop(hipStream_t s, int m, T* A, T* Linv, int* keep, double tau, T* work);
+// H1 (m x k) = D Linv^H on the kept columns idx
+template <typename T>
+int build_h1(hipStream_t s, int m, int k, const T* Linv, const double* d, const int* idx, T* H1);
+// out = ||S - I||_F (S k x k row-major); part >= k doubles
+template <typename T>
+int dev_from_identity(hipStream_t s, int k, const T* S, double* part, double* out);
+// Z = S^-1/2 (Newton-Schulz, `iters` steps); work >= 3 k^2 entries
+template <typename T>
+int ns_invsqrt(hipStream_t s, int k, const T* S, T* Z, int iters, T* work);
+template <typename T>
+int hermitian_part(hipStream_t s, int m, T* H);
 
 }  // namespace mf

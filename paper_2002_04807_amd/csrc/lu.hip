@@ -418,7 +418,10 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
   using R = typename real_of<C>::type;
   for (int64_t k = 0; k < n; k += LU_NB) {
     const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
+    int tok = prof_begin(s);
     if (launch_panel<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
+    // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
+    prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);
     hipLaunchKernelGGL((k_invert_diag<C>), dim3(1, ne), dim3(256), 0, s, n, (int)k, 1, LU, Dinv);
     hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, (int)k, nbc, LU, ipiv);
     const int64_t rest = n - k - nbc;
@@ -439,7 +442,11 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
       t.B = LU + k * n + k + nbc; t.ldb = n; t.b_bs = n * n;
       t.C = LU + (k + nbc) * n + k + nbc; t.ldc = n; t.c_bs = n * n;
       t.alpha = -1.0; t.beta = 1.0;
+      t.tag = 1;
+      tok = prof_begin(s);
       if (gemm<R, true>(s, false, false, t, ne)) return -2;
+      prof_end(tok, s, K_LU_GEMM, 8.0 * (double)rest * rest * nbc * ne,
+               (double)sizeof(C) * ne * (2.0 * rest * rest + 2.0 * rest * nbc));
     }
   }
   hipLaunchKernelGGL(k_perm_inverse, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ne, perm, perm_inv);

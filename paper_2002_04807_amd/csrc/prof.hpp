@@ -1,0 +1,31 @@
+// Optional per-class kernel timing with HIP events (enabled per call by the caller).
+//
+// Each instrumented launch records an event pair on the stream it is issued on and
+// the algorithmic work it performs (flops counted as 8 per complex multiply-add,
+// bytes as the compulsory HBM traffic).  Elapsed times are read after the call has
+// synchronized, so the timing does not add host synchronizations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mf {
+
+enum KClass {
+  K_LU_GEMM = 0,   // trailing update A22 -= L21 U12 of the blocked LU
+  K_LU_PANEL = 1,  // panel factorization
+  K_SOLVE_GEMM = 2,  // block updates of the contour solves
+  K_RR_GEMM = 3,   // FP64 Rayleigh-Ritz products
+  K_EIG = 4,       // reduced eigensolver
+  K_OTHER = 5,     // shift-form, right-hand sides, quadrature sum, small kernels
+  K_NCLASS = 6
+};
+
+bool prof_on();
+void prof_enable(bool on);
+// begin/end around one or more launches on stream s
+int prof_begin(hipStream_t s);
+void prof_end(int token, hipStream_t s, int cls, double flops, double bytes);
+// after the stream has synchronized: out[c*4 + {0,1,2,3}] += launches, ms, flops, bytes
+void prof_collect(double* out);
+
+}  // namespace mf

@@ -83,6 +83,24 @@ __global__ void k_sym_scale(int m, T* S, T* Tm, const double* __restrict__ d) {
 }
 
 template <typename T>
+__global__ void k_herm_part(int m, T* H) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= m || j < i) return;
+  const int64_t a = (int64_t)i * m + j, b = (int64_t)j * m + i;
+  T v = 0.5 * (H[a] + conj(H[b]));
+  if (i == j) v = T(real_part(v));
+  H[a] = v;
+  H[b] = conj(v);
+}
+
+template <typename T>
+int hermitian_part(hipStream_t s, int m, T* H) {
+  hipLaunchKernelGGL((k_herm_part<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, H);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
 int gram_equilibrate(hipStream_t s, int m, T* S, T* Tm, double* d, int* flag) {
   hipLaunchKernelGGL(k_diag_scale, dim3((m + 255) / 256), dim3(256), 0, s, m, (const void*)S,
                      (int)is_cplx<T>::value, d, flag);
@@ -126,6 +144,11 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, T* Ha, T* Hb, T* V, doubl
   for (int64_t e = gtid; e < mm; e += gsz) V[e] = (e / m == e % m) ? T(1.0) : T(0.0);
   T* src = Ha;
   T* dst = Hb;
+  // absolute floor for rotations: off-diagonal entries below 2 eps max|h_ii| carry
+  // no information beyond rounding
+  double dmax = 0.0;
+  for (int i = 0; i < m; ++i) dmax = fmax(dmax, fabs(real_part(Ha[(int64_t)i * m + i])));
+  const double abs_floor = 4.440892098500626e-16 * dmax + 1e-300;
   grid.sync();
 
   int sweep = 0;
@@ -145,7 +168,7 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, T* Ha, T* Hb, T* V, doubl
           const double aqq = real_part(src[(int64_t)q * m + q]);
           const T apq = src[(int64_t)p * m + q];
           const double ab = absval(apq);
-          if (ab > tol * sqrt(fabs(app * aqq)) && ab > 1e-300) {
+          if (ab > tol * sqrt(fabs(app * aqq)) && ab > abs_floor) {
             const T ph = phase_of<T>(apq, ab);
             const double tau = (aqq - app) / (2.0 * ab);
             double t;
@@ -397,7 +420,8 @@ int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t l
                                  double*, double*);                                                            \
   template int copy_rm_to_cm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t, const int*);        \
   template int copy_cm_to_rm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t);                    \
-  template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);
+  template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);                            \
+  template int hermitian_part<T>(hipStream_t, int, T*);
 
 MF_RR_INST(double)
 MF_RR_INST(c64)

@@ -62,7 +62,11 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv
     // herm: apply the conjugate transpose of the stored inverse (M-contiguous + conj)
     return gemm<R, true>(s, herm, herm, g, ne);
   };
+  // algorithmic work of one direction: 8 n^2 m flops per node (L and U sweeps)
+  const double dir_flops = 8.0 * (double)n * n * m * ne;
+  const double dir_bytes = (double)sizeof(C) * ne * ((double)n * n + 2.0 * n * m);
   // forward direction:  L then U
+  int tok = prof_begin(s);
   for (int64_t kb = 0; kb < nblk; ++kb) {
     const int64_t k = kb * LU_NB;
     const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
@@ -92,8 +96,10 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv
       if (gemm<R, true>(s, false, false, g, ne)) return -2;
     }
   }
+  prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   if (Wc == nullptr) return 0;
   // conjugate-transpose direction: U^H (lower) then L^H (unit upper)
+  tok = prof_begin(s);
   for (int64_t kb = 0; kb < nblk; ++kb) {
     const int64_t k = kb * LU_NB;
     const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
@@ -125,6 +131,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv
       if (gemm<R, true>(s, true, true, g, ne)) return -2;
     }
   }
+  prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   return 0;
 }
 
