@@ -1,0 +1,325 @@
+// Block two-sided Jacobi eigensolver for the reduced Hermitian problem (gfx950).
+//
+// The m x m matrix (m up to 1024) is split into blocks of JB = 32 indices.  Every
+// round pairs the blocks with the round-robin (circle) ordering; each pair (P, Q)
+// forms a 64 x 64 Hermitian subproblem [H_PP H_PQ; H_QP H_QQ] that one workgroup
+// diagonalizes in LDS with cyclic Jacobi sweeps (its own round-robin ordering of
+// the 64 local indices), giving a unitary U_PQ.  A second launch then applies all
+// the rounds' U's at once: every 64 x 64 super-block H[I_i, I_j] becomes
+// U_i^H H[I_i, I_j] U_j (the pairs of a round are disjoint, so the super-blocks
+// update independently) and V[:, I_j] becomes V[:, I_j] U_j.  A sweep covers every
+// block pair once; sweeps stop when no subproblem needed a rotation.
+#include <cstdlib>
+
+#include "kernels.hpp"
+
+namespace mf {
+
+constexpr int JT = 256;      // threads per workgroup
+
+template <typename T> __device__ inline double absv(T a);
+template <> __device__ inline double absv<double>(double a) { return fabs(a); }
+template <> __device__ inline double absv<c64>(c64 a) { return sqrt(a.re * a.re + a.im * a.im); }
+
+template <typename T>
+__device__ inline T sgn_phase(T b, double ab);
+template <> __device__ inline double sgn_phase<double>(double b, double ab) { return b >= 0 ? 1.0 : -1.0; }
+template <> __device__ inline c64 sgn_phase<c64>(c64 b, double ab) { return c64(b.re / ab, b.im / ab); }
+
+// block pair of round r, circle method over nbp (even) block indices
+__device__ inline void block_pair(int i, int r, int nbp, int& P, int& Q) {
+  const int a = (i == 0) ? 0 : 1 + (i - 1 + r) % (nbp - 1);
+  const int b = 1 + (nbp - 2 - i + r) % (nbp - 1);
+  P = min(a, b);
+  Q = max(a, b);
+}
+
+// global index of local index l (0..2 JB - 1) of the subproblem of blocks (P, Q)
+template <int JB>
+__device__ inline int gidx(int l, int P, int Q) { return l < JB ? P * JB + l : Q * JB + (l - JB); }
+
+// ---------------------------------------------------------------------------
+template <typename T, int JB>
+__global__ __launch_bounds__(JT) void k_bj_sub(int m, int nbp, int round, const T* __restrict__ H,
+                                               T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol,
+                                               int inner_sweeps) {
+  constexpr int JS = 2 * JB;
+  __shared__ T S[JS][JS + 1];
+  __shared__ T U[JS][JS + 1];
+  __shared__ double rc[JS / 2];
+  __shared__ T rs[JS / 2];
+  __shared__ int rp[JS / 2], rq[JS / 2], rf[JS / 2];
+  __shared__ int s_total;
+  __shared__ double s_dmax;
+  const int tid = threadIdx.x;
+  int P, Q;
+  block_pair(blockIdx.x, round, nbp, P, Q);
+  for (int e = tid; e < JS * JS; e += JT) {
+    const int a = e / JS, c = e % JS;
+    const int ga = gidx<JB>(a, P, Q), gc = gidx<JB>(c, P, Q);
+    S[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
+    U[a][c] = (a == c) ? T(1.0) : T(0.0);
+  }
+  if (tid == 0) s_total = 0;
+  __syncthreads();
+  if (tid == 0) {
+    double d = 0.0;
+    for (int a = 0; a < JS; ++a) d = fmax(d, fabs(real_part(S[a][a])));
+    s_dmax = d;
+  }
+  __syncthreads();
+  const double abs_floor = 4.440892098500626e-16 * s_dmax + 1e-300;
+  for (int sw = 0; sw < inner_sweeps; ++sw) {
+    int sweep_cnt = 0;
+    for (int r = 0; r < JS - 1; ++r) {
+      // rotation of each local pair from the current 2 x 2 diagonal blocks
+      if (tid < JS / 2) {
+        const int a = (tid == 0) ? 0 : 1 + (tid - 1 + r) % (JS - 1);
+        const int b = 1 + (JS - 2 - tid + r) % (JS - 1);
+        const int p = min(a, b), q = max(a, b);
+        double c = 1.0;
+        T sg = T(0.0);
+        int f = 0;
+        const double app = real_part(S[p][p]), aqq = real_part(S[q][q]);
+        const T apq = S[p][q];
+        const double ab = absv<T>(apq);
+        if (ab > tol * sqrt(fabs(app * aqq)) && ab > abs_floor) {
+          const T ph = sgn_phase<T>(apq, ab);
+          const double tau = (aqq - app) / (2.0 * ab);
+          double t;
+          if (fabs(tau) > 1e150) t = 0.5 / tau;
+          else t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sg = (t * c) * ph;
+          f = 1;
+        }
+        rc[tid] = c;
+        rs[tid] = sg;
+        rp[tid] = p;
+        rq[tid] = q;
+        rf[tid] = f;
+      }
+      __syncthreads();
+      int cnt = 0;
+      for (int i = 0; i < JS / 2; ++i) cnt += rf[i];
+      sweep_cnt += cnt;  // uniform: every thread read the same flags
+      if (cnt == 0) {
+        __syncthreads();  // the flags are rewritten next round
+        continue;
+      }
+      // S <- J^H S J on the 32 x 32 grid of 2 x 2 blocks, U <- U J
+      for (int e = tid; e < (JS / 2) * (JS / 2); e += JT) {
+        const int Pi = e / (JS / 2), Qi = e % (JS / 2);
+        if (!rf[Pi] && !rf[Qi]) continue;
+        const int p1 = rp[Pi], q1 = rq[Pi], p2 = rp[Qi], q2 = rq[Qi];
+        const double cP = rc[Pi], cQ = rc[Qi];
+        const T sP = rs[Pi], sQ = rs[Qi];
+        const T h11 = S[p1][p2], h12 = S[p1][q2], h21 = S[q1][p2], h22 = S[q1][q2];
+        const T t11 = cQ * h11 - h12 * conj(sQ);
+        const T t12 = h11 * sQ + cQ * h12;
+        const T t21 = cQ * h21 - h22 * conj(sQ);
+        const T t22 = h21 * sQ + cQ * h22;
+        S[p1][p2] = cP * t11 - sP * t21;
+        S[p1][q2] = cP * t12 - sP * t22;
+        S[q1][p2] = conj(sP) * t11 + cP * t21;
+        S[q1][q2] = conj(sP) * t12 + cP * t22;
+      }
+      for (int e = tid; e < JS * (JS / 2); e += JT) {
+        const int x = e / (JS / 2), Qi = e % (JS / 2);
+        if (!rf[Qi]) continue;
+        const int p2 = rp[Qi], q2 = rq[Qi];
+        const double cQ = rc[Qi];
+        const T sQ = rs[Qi];
+        const T a = U[x][p2], b = U[x][q2];
+        U[x][p2] = cQ * a - b * conj(sQ);
+        U[x][q2] = a * sQ + cQ * b;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) s_total += sweep_cnt;
+    if (sweep_cnt == 0) break;  // uniform
+  }
+  __syncthreads();
+  T* Uo = Ubuf + (int64_t)blockIdx.x * JS * JS;
+  for (int e = tid; e < JS * JS; e += JT) Uo[e] = U[e / JS][e % JS];
+  if (tid == 0 && s_total > 0) atomicAdd(rotcount, s_total);
+}
+
+// ---------------------------------------------------------------------------
+// Apply the round's U's.  Blocks [0, npr*(npr+1)/2): H super-block pairs i <= j
+// (the (j, i) block is written as the conjugate transpose).  Blocks after that:
+// V row-block x pair j.
+template <typename T, int JB>
+__global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __restrict__ H, T* __restrict__ V,
+                                               const T* __restrict__ Ubuf) {
+  constexpr int JS = 2 * JB;
+  constexpr int RW = JS / 16;  // rows (and columns) of the result per thread: 16 x 16 threads
+  __shared__ T X[JS][JS + 1];
+  __shared__ T Um[JS][JS + 1];
+  const int tid = threadIdx.x;
+  const int npr = nbp / 2;
+  const int nh = npr * (npr + 1) / 2;
+  int bid = blockIdx.x;
+  // each thread owns an RW x RW tile of the JS x JS result
+  const int r0 = (tid >> 4) * RW, c0 = (tid & 15) * RW;
+  T acc[RW][RW];
+  if (bid < nh) {
+    // (i, j) with i <= j from the linear index
+    int i = 0;
+    while (bid >= npr - i) {
+      bid -= npr - i;
+      ++i;
+    }
+    const int j = i + bid;
+    int Pi, Qi, Pj, Qj;
+    block_pair(i, round, nbp, Pi, Qi);
+    block_pair(j, round, nbp, Pj, Qj);
+    const T* Ui = Ubuf + (int64_t)i * JS * JS;
+    const T* Uj = Ubuf + (int64_t)j * JS * JS;
+    for (int e = tid; e < JS * JS; e += JT) {
+      const int a = e / JS, c = e % JS;
+      const int ga = gidx<JB>(a, Pi, Qi), gc = gidx<JB>(c, Pj, Qj);
+      X[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
+      Um[a][c] = Uj[e];
+    }
+    __syncthreads();
+    // T = X Uj
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T xa[RW], ub[RW];
+      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
+      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
+    }
+    __syncthreads();
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) X[r0 + a][c0 + c] = acc[a][c];
+    for (int e = tid; e < JS * JS; e += JT) Um[e / JS][e % JS] = Ui[e];
+    __syncthreads();
+    // out = Ui^H T
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T ua[RW], xb[RW];
+      for (int a = 0; a < RW; ++a) ua[a] = conj(Um[k][r0 + a]);
+      for (int c = 0; c < RW; ++c) xb[c] = X[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + ua[a] * xb[c];
+    }
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) {
+        const int ga = gidx<JB>(r0 + a, Pi, Qi), gc = gidx<JB>(c0 + c, Pj, Qj);
+        if (ga < m && gc < m) {
+          H[(int64_t)ga * m + gc] = acc[a][c];
+          if (i != j) H[(int64_t)gc * m + ga] = conj(acc[a][c]);
+        }
+      }
+  } else {
+    bid -= nh;
+    const int j = bid % npr;
+    const int xb = bid / npr;  // row block of 64 rows of V
+    int Pj, Qj;
+    block_pair(j, round, nbp, Pj, Qj);
+    const T* Uj = Ubuf + (int64_t)j * JS * JS;
+    for (int e = tid; e < JS * JS; e += JT) {
+      const int a = e / JS, c = e % JS;
+      const int ga = xb * JS + a, gc = gidx<JB>(c, Pj, Qj);
+      X[a][c] = (ga < m && gc < m) ? V[(int64_t)ga * m + gc] : T(0.0);
+      Um[a][c] = Uj[e];
+    }
+    __syncthreads();
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T xa[RW], ub[RW];
+      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
+      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
+    }
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) {
+        const int ga = xb * JS + r0 + a, gc = gidx<JB>(c0 + c, Pj, Qj);
+        if (ga < m && gc < m) V[(int64_t)ga * m + gc] = acc[a][c];
+      }
+  }
+}
+
+template <typename T>
+__global__ void k_identity(int m, T* V) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j < m) V[(int64_t)i * m + j] = (i == j) ? T(1.0) : T(0.0);
+}
+
+template <typename T>
+__global__ void k_diag_out(int m, const T* __restrict__ H, double* evals, int* counter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) evals[i] = real_part(H[(int64_t)i * m + i]);
+  if (i == 0) counter[0] = 0;
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// H (m x m) destroyed; V receives the eigenvectors (columns), evals the eigenvalues
+// (unsorted).  ubuf: (2 JB)^2 (nbp/2) entries of T for the round's unitaries; counter:
+// 2 ints.
+template <typename T, int JB>
+static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
+                           int max_sweeps) {
+  constexpr int JS = 2 * JB;
+  static const int inner_sweeps = getenv("MFEAST_BJ_INNER") ? atoi(getenv("MFEAST_BJ_INNER")) : 1;
+  const int nb = (m + JB - 1) / JB;
+  const int nbp = nb + (nb & 1);
+  const int npr = nbp / 2;
+  const int nh = npr * (npr + 1) / 2;
+  const int nvrow = (m + JS - 1) / JS;
+  hipLaunchKernelGGL((k_identity<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, V);
+  int sweep = 0;
+  int hcount = 1;
+  for (; sweep < max_sweeps; ++sweep) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
+    for (int r = 0; r < nbp - 1; ++r) {
+      hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr), dim3(JT), 0, s, m, nbp, r, H, ubuf, counter, 1.0e-15,
+                         inner_sweeps);
+      hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(nh + nvrow * npr), dim3(JT), 0, s, m, nbp, r, H, V, ubuf);
+    }
+    if (hipMemcpyAsync(&hcount, counter, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
+    if (hipStreamSynchronize(s) != hipSuccess) return -2;
+    if (hcount == 0) break;
+  }
+  hipLaunchKernelGGL((k_diag_out<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, H, evals, counter + 1);
+  int sw = sweep + 1;
+  if (hipMemcpyAsync(sweeps_out, &sw, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
+  if (hipStreamSynchronize(s) != hipSuccess) return -2;
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+static int bj_width() {
+  static const int w = getenv("MFEAST_BJ_WIDTH") ? atoi(getenv("MFEAST_BJ_WIDTH")) : 16;
+  return w == 32 ? 32 : 16;
+}
+
+template <typename T>
+int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
+                 int max_sweeps) {
+  if (bj_width() == 32) return block_jacobi_jb<T, 32>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
+  return block_jacobi_jb<T, 16>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
+}
+
+size_t block_jacobi_work_bytes(int m, size_t elem) {
+  // sized for the widest block choice
+  const int JB = 32, JS = 64;
+  const int nb = (m + JB - 1) / JB;
+  const int nbp16 = ((m + 15) / 16) + (((m + 15) / 16) & 1);
+  const size_t a = (size_t)JS * JS * ((nb + (nb & 1)) / 2) * elem;
+  const size_t b = (size_t)32 * 32 * (nbp16 / 2) * elem;
+  return (a > b ? a : b) + 64;
+}
+
+template int block_jacobi<double>(hipStream_t, int, double*, double*, double*, int*, double*, int*, int);
+template int block_jacobi<c64>(hipStream_t, int, c64*, c64*, double*, int*, c64*, int*, int);
+
+}  // namespace mf

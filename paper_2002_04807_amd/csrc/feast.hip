@@ -257,7 +257,7 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   const size_t sq = (size_t)m0 * m0 * szT;
   T* Sm = (T*)h->ws(S_S, sq);
   T* Tm = (T*)h->ws(S_T, sq);
-  T* Hw = (T*)h->ws(S_HW, sq);
+  T* Hw = (T*)h->ws(S_HW, std::max(sq, jacobi_work_bytes(m0, szT)));
   T* V = (T*)h->ws(S_V, sq);
   T* G = (T*)h->ws(S_G, sq);
   T* TG = (T*)h->ws(S_TG, std::max(3 * sq, (size_t)m0 * 32 * szT));  // also Cholesky / Newton-Schulz work

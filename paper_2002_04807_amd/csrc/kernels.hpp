@@ -81,8 +81,19 @@ template <typename T>
 int col_absmax(hipStream_t s, int64_t n, int m, const T* X, int64_t ld, double* out);  // out[c] = max_r |X[r][c]|
 template <typename T>
 int gram_equilibrate(hipStream_t s, int m, T* S, T* Tm, double* d, int* flag);
+// Hermitian eigensolver of the m x m row-major H (destroyed): V eigenvectors (columns),
+// evals unsorted.  m <= 64: one cooperative scalar Jacobi launch; larger m: block
+// Jacobi.  work: jacobi_work_bytes(m, sizeof(T)) bytes.
 template <typename T>
 int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work);
+template <typename T>
+int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
+                 int max_sweeps);
+size_t block_jacobi_work_bytes(int m, size_t elem);
+inline size_t jacobi_work_bytes(int m, size_t elem) {
+  const size_t a = (size_t)m * m * elem, b = block_jacobi_work_bytes(m, elem);
+  return a > b ? a : b;
+}
 template <typename T>
 int gather_scale_cols(hipStream_t s, int rows, int k, const T* V, int ldv, const int* idx,
                       const double* scale, T* G, int ldg);

@@ -243,6 +243,12 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, T* Ha, T* Hb, T* V, doubl
 template <typename T>
 int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work) {
   if (m > 2 * JAC_MAXPAIR) return -2;
+  if (m > 64) {
+    // block Jacobi (eig.hip); work holds the round's unitaries, then a counter
+    T* ubuf = reinterpret_cast<T*>(work);
+    int* counter = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + block_jacobi_work_bytes(m, sizeof(T)) - 64);
+    return block_jacobi<T>(s, m, H, V, evals, sweeps_out, ubuf, counter, 40);
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -2;
   int ncu = 0, per_cu = 0;
