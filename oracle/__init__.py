@@ -18,6 +18,7 @@ Readings taken where the guide is silent are listed in each module header.
 
 from .contour import half_contour, rational_filter, gauss_legendre_rule
 from .splitmix import splitmix64_uniform, initial_subspace
+from .ifeast import bicgstab_block, feast_csr, ifeastinit
 from .feast import (
     feastinit,
     expand_uplo,
@@ -37,4 +38,7 @@ __all__ = [
     "feast_dense",
     "rayleigh_ritz",
     "validate",
+    "bicgstab_block",
+    "feast_csr",
+    "ifeastinit",
 ]

@@ -247,31 +247,50 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
     fpm(14) = 1 it returns Q after one contour in X and info = 4.
     """
     fpm = feastinit() if fpm is None else np.asarray(fpm, dtype=np.int64)
-    f = lambda i: int(fpm[i - 1])  # noqa: E731
     A = np.asarray(A)
     n = A.shape[0]
-    out = {"info": 0, "E": None, "X": None, "M": 0, "res": None, "epsout": 1.0,
-           "loop": 0, "m0": m0, "history": []}
     info = validate(n, m0, emin, emax, fpm, have_expert_contour=zne is not None)
     if info:
-        out["info"] = info
-        return out
+        return _empty(info, m0)
     real_problem = not (np.iscomplexobj(A) or (B is not None and np.iscomplexobj(B)))
     dt = np.float64 if real_problem else np.complex128
     A = expand_uplo(A, uplo).astype(dt)
     if B is not None:
         B = expand_uplo(np.asarray(B), uplo).astype(dt)
+    z, w = _nodes(emin, emax, fpm, zne, wne)
+    facts = [_Factored(zj, A, B) for zj in z]
+    return iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, facts, form)
+
+
+def _empty(info, m0):
+    return {"info": info, "E": None, "X": None, "M": 0, "res": None, "epsout": 1.0,
+            "loop": 0, "m0": m0, "history": []}
+
+
+def _nodes(emin, emax, fpm, zne, wne):
+    f = lambda i: int(fpm[i - 1])  # noqa: E731
     if zne is None:
-        z, w = half_contour(emin, emax, f(2), rule=f(16), ratio_pct=f(18))
-    else:
-        z, w = np.asarray(zne, np.complex128), np.asarray(wne, np.complex128)
+        return half_contour(emin, emax, f(2), rule=f(16), ratio_pct=f(18))
+    return np.asarray(zne, np.complex128), np.asarray(wne, np.complex128)
+
+
+def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form="residual"):
+    """The subspace iteration shared by the dense and the sparse drivers.
+
+    A, B: objects supporting ``@`` with an n x m block (B None means identity).
+    solvers[j]: object with solve(rhs) for (z_j B - A)^-1 rhs and, for complex
+    Hermitian problems, solve_h(rhs) for (z_j B - A)^-H rhs.
+    """
+    f = lambda i: int(fpm[i - 1])  # noqa: E731
+    dt = np.float64 if real_problem else np.complex128
+    out = _empty(0, m0)
     alpha = max(abs(emin), abs(emax))
     eps = 10.0 ** (-f(3))
     if f(5) == 1:
         Y = np.asarray(X0, dtype=dt)[:, :m0].copy()
     else:
         Y = initial_subspace(n, m0, f(51), not real_problem).astype(dt)
-    facts = [_Factored(zj, A, B) for zj in z]
+    facts = solvers
 
     trace_prev = None
     X = Y

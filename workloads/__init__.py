@@ -13,6 +13,8 @@ from .generators import (
     prescribed_real_problem,
     batched_real_problems,
     column_major,
+    laplacian_3d_csr,
+    laplacian_3d_eigs,
 )
 
 __all__ = [
@@ -23,4 +25,6 @@ __all__ = [
     "prescribed_real_problem",
     "batched_real_problems",
     "column_major",
+    "laplacian_3d_csr",
+    "laplacian_3d_eigs",
 ]

@@ -102,3 +102,41 @@ def batched_real_problems(nprob, seed, n_lo=256, n_hi=2048, c_lo=24, c_hi=48):
         probs.append({"A": A, "lam": lam, "U": U, "emin": emin, "emax": emax,
                       "count": c, "m0": int(np.ceil(1.5 * c)), "start": s})
     return probs
+
+
+def laplacian_3d_csr(nx, ny=None, nz=None):
+    """7-point Laplacian (6 on the diagonal, -1 to each grid neighbour, Dirichlet) on an
+    nx x ny x nz grid, natural ordering i + nx (j + ny k); CSR arrays (0-based):
+    (values float64, column indices int32, row pointers int32), full storage."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    n = nx * ny * nz
+    idx = np.arange(n)
+    i = idx % nx
+    j = (idx // nx) % ny
+    k = idx // (nx * ny)
+    rows, cols, vals = [idx], [idx], [np.full(n, 6.0)]
+    for di, dj, dk, stride in ((1, 0, 0, 1), (0, 1, 0, nx), (0, 0, 1, nx * ny)):
+        ok_p = (i + di < nx) & (j + dj < ny) & (k + dk < nz)
+        rows += [idx[ok_p], idx[ok_p] + stride]
+        cols += [idx[ok_p] + stride, idx[ok_p]]
+        vals += [np.full(int(ok_p.sum()), -1.0)] * 2
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(indptr, r + 1, 1)
+    indptr = np.cumsum(indptr)
+    return v.astype(np.float64), c.astype(np.int32), indptr.astype(np.int32)
+
+
+def laplacian_3d_eigs(nx, ny=None, nz=None):
+    """All eigenvalues sum_d 2 - 2 cos(k_d pi / (n_d + 1)), ascending (closed form)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    ex = 2.0 - 2.0 * np.cos(np.arange(1, nx + 1) * np.pi / (nx + 1))
+    ey = 2.0 - 2.0 * np.cos(np.arange(1, ny + 1) * np.pi / (ny + 1))
+    ez = 2.0 - 2.0 * np.cos(np.arange(1, nz + 1) * np.pi / (nz + 1))
+    return np.sort((ex[:, None, None] + ey[None, :, None] + ez[None, None, :]).ravel())
