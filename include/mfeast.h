@@ -103,6 +103,40 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
                  double* epsout, int32_t* loop, const double* zne, const double* wne);
 
+/* IFEAST defaults (Section 3.5, Table tab_fpm "using IFEAST"): mfeast_init, then
+ * fpm(2)=4 nodes, fpm(4)=50 loops, fpm(16)=1 trapezoidal rule, fpm(18)=100 (circle).
+ * BiCGSTAB accuracy fpm(45)=1 (10^-1) and fpm(46)=40 iterations are the common defaults. */
+void mfeast_init_ifeast(int32_t* fpm);
+
+/* Sparse real symmetric problem in CSR storage, solved without factorization
+ * (difeast_scsrgv / difeast_scsrev; Section 3.5 "IFEAST"; CSR arguments as in
+ * Table tab-spec1 for sparse storage).  Every shifted system z_j B - A is solved
+ * inexactly by BiCGSTAB, to ||r|| <= 10^-fpm(45) ||b|| or fpm(46) iterations per
+ * column; all quadrature nodes and right-hand sides run as one batch (split into node
+ * groups only when device memory is short).  The subspace iteration, Rayleigh-Ritz,
+ * residuals, outputs and info codes are those of mfeast_dsygv.
+ *  uplo        'F': full storage; 'L' / 'U': only the lower / upper triangle is stored
+ *              (entries of the other triangle are ignored)
+ *  n           order (n < 2^31 - 1)
+ *  a, ia, ja   device: values (double), row pointers (n+1 int32), column indices (int32)
+ *              of A; after expansion of a triangle at most 2^31 - 1 entries
+ *  index_base  0 or 1: base of ia and ja (the guide's examples are 1-based)
+ *  b, ib, jb   device: CSR of B with the same base and uplo, or b = NULL for B = I
+ *  other arguments as for mfeast_dsygv (argument positions shift accordingly)
+ * fpm(42)=1 (default) runs BiCGSTAB in complex FP32 (values of A and B rounded to FP32);
+ * fpm(42)=0 in complex FP64.  The outer products A Q, B Q and the residuals are FP64.
+ * On return fpm(60) holds the total number of BiCGSTAB iterations: for every contour
+ * and node, the largest iteration count among the node's columns, summed.
+ * Errors: -105 (row pointers not monotone, ia(1) != base, or ia(n+1) - base < 0),
+ * -106 (column index outside 1..n), -104 (more than 2^31 - 1 stored entries after
+ * expansion), -109 / -110 / -108 the same for B; 145 fpm(45) outside 0..16,
+ * 146 fpm(46) < 1.  The CSR arrays are checked on the device before any iteration. */
+int mfeast_dcsrgv(mfeast_handle h, char uplo, int64_t n, const double* a, const int32_t* ia,
+                  const int32_t* ja, int32_t index_base, const double* b, const int32_t* ib,
+                  const int32_t* jb, int32_t* fpm, double emin, double emax, int32_t* m0,
+                  double* E, double* X, int64_t ldx, int32_t* M, double* res, double* epsout,
+                  int32_t* loop, const double* zne, const double* wne);
+
 /* Timing of the last call in seconds, host clock around synchronized phases (the
  * guide's "FEAST-RCI timing" split, Section 2.4): out[0] factorization, [1] contour
  * solves, [2] Rayleigh-Ritz products and residuals, [3] reduced eigensolver, [4] other,
@@ -114,8 +148,9 @@ int mfeast_get_timing(mfeast_handle h, double* out);
  * guide).  For class c: out[4c+0] launches (or launch groups), [4c+1] milliseconds,
  * [4c+2] algorithmic flops (8 per complex multiply-add), [4c+3] algorithmic bytes.
  * Classes: 0 LU trailing update, 1 LU panel, 2 contour solves (per direction),
- * 3 FP64 Rayleigh-Ritz products, 4 reduced eigensolver, 5 other kernels.
- * out: host, `count` doubles (24 cover all classes). */
+ * 3 FP64 Rayleigh-Ritz products, 4 reduced eigensolver, 5 other kernels,
+ * 6 sparse shifted products inside BiCGSTAB, 7 BiCGSTAB vector updates and reductions.
+ * out: host, `count` doubles (32 cover all classes). */
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count);
 
 #ifdef __cplusplus

@@ -21,8 +21,9 @@ _lib = None
 _lib_error = None
 
 EXPORTED = (
-    "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_contour",
-    "mfeast_dsygv", "mfeast_zhegv", "mfeast_get_timing", "mfeast_get_profile",
+    "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
+    "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_get_timing",
+    "mfeast_get_profile",
 )
 
 
@@ -44,6 +45,8 @@ def _load():
     lib.mfeast_set_stream.restype = c_int
     lib.mfeast_init.argtypes = [c_i32p]
     lib.mfeast_init.restype = None
+    lib.mfeast_init_ifeast.argtypes = [c_i32p]
+    lib.mfeast_init_ifeast.restype = None
     lib.mfeast_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, c_dp, c_dp]
     lib.mfeast_contour.restype = c_int
@@ -53,6 +56,10 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = dense
         fn.restype = c_int
+    lib.mfeast_dcsrgv.argtypes = [c_vp, ctypes.c_char, i64, c_dp, c_vp, c_vp, ctypes.c_int32, c_dp, c_vp, c_vp,
+                                  c_i32p, ctypes.c_double, ctypes.c_double, c_i32p, c_dp, c_dp, i64, c_i32p, c_dp,
+                                  ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
+    lib.mfeast_dcsrgv.restype = c_int
     lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_get_timing.restype = c_int
     lib.mfeast_get_profile.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
@@ -88,6 +95,13 @@ def mfeast_init():
     """Default fpm[64] (feastinit) as an int32 numpy array."""
     fpm = np.zeros(64, dtype=np.int32)
     _load().mfeast_init(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return fpm
+
+
+def mfeast_init_ifeast():
+    """IFEAST defaults of fpm[64] as an int32 numpy array."""
+    fpm = np.zeros(64, dtype=np.int32)
+    _load().mfeast_init_ifeast(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return fpm
 
 
@@ -133,12 +147,14 @@ class Handle:
         _load().mfeast_get_timing(self.ptr, out)
         return list(out)
 
-    PROFILE_CLASSES = ("lu_trailing_gemm", "lu_panel", "contour_solve", "rr_gemm", "reduced_eig", "other")
+    PROFILE_CLASSES = ("lu_trailing_gemm", "lu_panel", "contour_solve", "rr_gemm", "reduced_eig", "other",
+                       "bicgstab_spmv", "bicgstab_vector")
 
     def profile(self):
         """Per-class device timing of the last call made with fpm[51] = 1."""
-        out = (ctypes.c_double * 24)()
-        _load().mfeast_get_profile(self.ptr, out, 24)
+        k = 4 * len(self.PROFILE_CLASSES)
+        out = (ctypes.c_double * k)()
+        _load().mfeast_get_profile(self.ptr, out, k)
         return {name: {"launches": out[4 * i], "ms": out[4 * i + 1], "flops": out[4 * i + 2],
                        "bytes": out[4 * i + 3]} for i, name in enumerate(self.PROFILE_CLASSES)}
 
@@ -174,6 +190,32 @@ def mfeast_dsygv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res
 def mfeast_zhegv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
     """C mfeast_zhegv; complex128 device tensors (interleaved re, im)."""
     return _dense_call("mfeast_zhegv", h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne, wne)
+
+
+def mfeast_dcsrgv(h, uplo, n, a, ia, ja, index_base, b, ib, jb, fpm, emin, emax, m0, E, X, ldx, res,
+                  zne=None, wne=None):
+    """C mfeast_dcsrgv; a, ia, ja (and b, ib, jb or None) are device tensors (float64, int32)."""
+    lib = _load()
+    fpm_a = _fpm_array(fpm)
+    m0_c = ctypes.c_int32(int(m0))
+    M_c = ctypes.c_int32(0)
+    eps_c = ctypes.c_double(0.0)
+    loop_c = ctypes.c_int32(0)
+    zb = wb = None
+    if zne is not None:
+        zb = np.ascontiguousarray(np.asarray(zne, dtype=np.complex128)).view(np.float64)
+        wb = np.ascontiguousarray(np.asarray(wne, dtype=np.complex128)).view(np.float64)
+    hp = h.ptr if isinstance(h, Handle) else h
+    info = lib.mfeast_dcsrgv(
+        hp, uplo.encode() if isinstance(uplo, str) else uplo, int(n), _ptr(a), _ptr(ia), _ptr(ja),
+        int(index_base), _ptr(b), _ptr(ib), _ptr(jb), fpm_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        float(emin), float(emax), ctypes.byref(m0_c), _ptr(E), _ptr(X), int(ldx), ctypes.byref(M_c), _ptr(res),
+        ctypes.byref(eps_c), ctypes.byref(loop_c), None if zb is None else zb.ctypes.data,
+        None if wb is None else wb.ctypes.data)
+    if isinstance(fpm, np.ndarray) and fpm.dtype == np.int32 and fpm.size == 64:
+        fpm[:] = fpm_a
+    return {"info": int(info), "m0": int(m0_c.value), "M": int(M_c.value), "epsout": float(eps_c.value),
+            "loop": int(loop_c.value), "fpm60": int(fpm_a[59])}
 
 
 def colmajor(t):
@@ -212,6 +254,48 @@ def feast(A, B, emin, emax, m0, fpm=None, X0=None, uplo="F", handle=None, zne=No
     try:
         fn = mfeast_zhegv if cplx else mfeast_dsygv
         out = fn(h, uplo, n, A_, lda, B_, ldb, fpm, emin, emax, m0, E, X, n, res, zne, wne)
+        out["timing"] = h.timing()
+        if fpm[51] == 1:
+            out["profile"] = h.profile()
+    finally:
+        if own:
+            h.close()
+    m = out["m0"]
+    out.update(E=E[:m], X=X[:, :m], res=res[:m], fpm=fpm)
+    return out
+
+
+def feast_csr(csr, emin, emax, m0, fpm=None, B=None, X0=None, uplo="F", index_base=0, handle=None,
+              zne=None, wne=None, device=0):
+    """IFEAST on a real symmetric CSR matrix: csr = (values, row pointers, column indices)
+    as numpy arrays or device tensors (float64, int32, int32); B likewise or None.
+
+    Returns the dict of mfeast_dcsrgv plus E, X (n x M0 column-major tensor), res, fpm.
+    fpm defaults to mfeast_init_ifeast().
+    """
+    import torch
+    dev = torch.device("cuda", device)
+
+    def dev_arr(x, dt):
+        return x.to(dev, dt) if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x), dtype=dt, device=dev)
+
+    a, ia, ja = dev_arr(csr[0], torch.float64), dev_arr(csr[1], torch.int32), dev_arr(csr[2], torch.int32)
+    n = ia.numel() - 1
+    b = ib = jb = None
+    if B is not None:
+        b, ib, jb = dev_arr(B[0], torch.float64), dev_arr(B[1], torch.int32), dev_arr(B[2], torch.int32)
+    fpm = mfeast_init_ifeast() if fpm is None else _fpm_array(fpm).copy()
+    X = torch.zeros((m0, n), dtype=torch.float64, device=dev).mT
+    if X0 is not None:
+        X.copy_(X0.to(torch.float64))
+        fpm[4] = 1
+    E = torch.zeros(m0, dtype=torch.float64, device=dev)
+    res = torch.zeros(m0, dtype=torch.float64, device=dev)
+    own = handle is None
+    h = Handle(device) if own else handle
+    try:
+        out = mfeast_dcsrgv(h, uplo, n, a, ia, ja, index_base, b, ib, jb, fpm, emin, emax, m0, E, X, n, res,
+                            zne, wne)
         out["timing"] = h.timing()
         if fpm[51] == 1:
             out["profile"] = h.profile()

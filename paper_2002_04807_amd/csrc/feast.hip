@@ -1,9 +1,14 @@
 // Host side of the Hermitian FEAST contour-integration subspace iteration (C interface).
 //
-// One call runs the whole method of the FEAST v4.0 guide for a dense Hermitian
-// (real symmetric) pencil, every numerical step in the HIP kernels of this library:
-//   factor    Az_j = z_j B - A for every node, blocked LU with partial pivoting,
-//             factors kept for all iterations (RCI case 10, fpm(10)=1)
+// One call runs the whole method of the FEAST v4.0 guide for a Hermitian (real
+// symmetric) pencil, every numerical step in the HIP kernels of this library.  The
+// subspace loop (feast_loop) is shared by two matrix formats, each an Operator:
+//   dense     Az_j = z_j B - A for every node, blocked LU with partial pivoting,
+//             factors kept for all iterations (RCI case 10, fpm(10)=1); solves by
+//             blocked triangular products (cases 11 and 21)
+//   CSR       no factorization (IFEAST, Section 3.5): every shifted system solved
+//             inexactly by BiCGSTAB, all nodes and right-hand sides batched
+// The loop:
 //   contour   iteration 0: solve Az_j Q_j = B Y for the starting block Y (case 11,
 //             and case 21 with Az_j^H for complex Hermitian problems);
 //             iteration k > 0: residual inverse iteration (v4.0, Section 1.2 and the
@@ -39,7 +44,9 @@ enum Slot {
   S_LU, S_DINV, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
   S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
   S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
-  S_SMALL, S_PART, S_FLAG, S_NSLOTS
+  S_SMALL, S_PART, S_FLAG,
+  S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF,
+  S_NSLOTS
 };
 
 struct Timer {
@@ -59,6 +66,9 @@ struct mfeast_ctx {
   size_t cap[S_NSLOTS] = {};
   char* pinned = nullptr;
   size_t pinned_cap = 0;
+  int* pinned_i = nullptr;  // column states of the batched BiCGSTAB
+  size_t pinned_i_cap = 0;
+  mf::CsrWork csrA, csrB;
   double timing[8] = {};
   double prof[K_NCLASS * 4] = {};
 
@@ -82,6 +92,17 @@ struct mfeast_ctx {
       pinned_cap = bytes;
     }
     return pinned;
+  }
+  int* host_ints(size_t count) {
+    const size_t bytes = count * sizeof(int) + 64;
+    if (pinned_i_cap < bytes) {
+      if (pinned_i) (void)hipHostFree(pinned_i);
+      pinned_i = nullptr;
+      pinned_i_cap = 0;
+      if (hipHostMalloc((void**)&pinned_i, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      pinned_i_cap = bytes;
+    }
+    return pinned_i;
   }
 };
 
@@ -203,57 +224,272 @@ static int eig_timed(hipStream_t s, int m, T* H, T* V, double* evals, int* sweep
     if ((__VA_ARGS__) != 0) return -2;   \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// What the subspace loop needs from a matrix format.  All blocks are row-major
+// n x m FP64 (T) with leading dimension m.
+struct Coef {
+  const double* cs;  // column scales applied to the right-hand side before the solves
+  const double* us;  // their inverses, applied to the quadrature sum
+  const double* rho; // rational filter at the current Ritz values (residual form)
+  const c64* cf;     // per node and column: w_j / (z_j - lambda_c) (residual) or w_j (classic)
+  const c64* cc;     // the same for the conjugate node (complex Hermitian)
+};
+
+template <typename T>
+struct Operator {
+  bool hasB = false;
+  virtual ~Operator() = default;
+  // once per call, before the loop (factorization / format conversion); returns info
+  virtual int prepare(hipStream_t s) = 0;
+  virtual int apply_A(hipStream_t s, int m, const T* X, T* Y) = 0;
+  virtual int apply_B(hipStream_t s, int m, const T* X, T* Y) = 0;
+  // Q = [resid: X diag(rho)] + sum over the nodes of the weighted solves with rhs
+  virtual int contour(hipStream_t s, int m, const T* rhs, const Coef& k, const T* X, T* Q, bool resid) = 0;
+};
+
+// dense storage: LU of every shifted matrix, blocked triangular solves
 template <typename T, typename C>
-static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
-                       int32_t* fpm, double emin, double emax, int32_t* m0p, double* E, T* Xu, int64_t ldx,
-                       int32_t* Mout, double* res_out, double* epsout, int32_t* loop, const double* zne,
-                       const double* wne) {
+struct DenseOp : Operator<T> {
+  mfeast_ctx* h;
+  char uplo;
+  int64_t n;
+  const T *A, *B;
+  int64_t lda, ldb;
+  const std::vector<c64>& z;
+  int ne, m0max;
+  const T* Af = nullptr;
+  const T* Bf = nullptr;
+  int64_t ldaf = 0, ldbf = 0;
+  C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr;
+  int *ipiv = nullptr, *perm = nullptr, *pinv = nullptr, *linfo = nullptr;
+  c64* zdev = nullptr;
+
+  DenseOp(mfeast_ctx* h_, char uplo_, int64_t n_, const T* A_, int64_t lda_, const T* B_, int64_t ldb_,
+          const std::vector<c64>& z_, int m0_)
+      : h(h_), uplo(uplo_), n(n_), A(A_), B(B_), lda(lda_), ldb(ldb_), z(z_), ne((int)z_.size()), m0max(m0_) {
+    this->hasB = B_ != nullptr;
+  }
+
+  int prepare(hipStream_t s) override {
+    constexpr bool CPLX = is_cplx<T>::value;
+    const int64_t nblk = (n + LU_NB - 1) / LU_NB;
+    const size_t szT = sizeof(T), szC = sizeof(C);
+    LU = (C*)h->ws(S_LU, (size_t)ne * n * n * szC);
+    Dinv = (C*)h->ws(S_DINV, (size_t)ne * nblk * 2 * LU_NB * LU_NB * szC);
+    ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
+    perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);
+    pinv = (int*)h->ws(S_PINV, (size_t)ne * n * 4);
+    linfo = (int*)h->ws(S_INFO, (size_t)ne * 4 + 64);
+    zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
+    Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0max * szC);
+    Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0max * szC) : nullptr;
+    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc)) return -2;
+    // full storage if a triangle was given
+    Af = A;
+    ldaf = lda;
+    Bf = B;
+    ldbf = ldb;
+    if (uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u') {
+      T* a2 = (T*)h->ws(S_AF, (size_t)n * n * szT);
+      if (!a2) return -2;
+      MF_TRY(expand_full<T>(s, uplo, n, A, lda, a2));
+      Af = a2;
+      ldaf = n;
+      if (B) {
+        T* b2 = (T*)h->ws(S_BF, (size_t)n * n * szT);
+        if (!b2) return -2;
+        MF_TRY(expand_full<T>(s, uplo, n, B, ldb, b2));
+        Bf = b2;
+        ldbf = n;
+      }
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
+    {
+      const int tok = prof_begin(s);
+      MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((B ? 2.0 : 1.0) * sizeof(T) + ne * sizeof(C)));
+    }
+    MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
+    std::vector<int> hinfo(ne);
+    MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < ne; ++j)
+      if (hinfo[j] != 0) return -2;
+    return 0;
+  }
+
+  int apply_A(hipStream_t s, int m, const T* X, T* Y) override {
+    return rm_gemm<T>(s, (int)n, m, (int)n, Af, ldaf, true, false, X, m, Y, m);
+  }
+  int apply_B(hipStream_t s, int m, const T* X, T* Y) override {
+    return rm_gemm<T>(s, (int)n, m, (int)n, Bf, ldbf, true, false, X, m, Y, m);
+  }
+
+  int contour(hipStream_t s, int m, const T* rhs, const Coef& k, const T* X, T* Q, bool resid) override {
+    constexpr bool CPLX = is_cplx<T>::value;
+    const double nb = (double)n * m;
+    const int dirs = CPLX ? 2 : 1;
+    int tok = prof_begin(s);
+    MF_TRY(rhs_prepare<T, C>(s, n, m, rhs, m, k.cs, ne, perm, Wf, Wc));
+    prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
+    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Dinv, Wf, Wc));
+    tok = prof_begin(s);
+    MF_TRY(accumulate<T, C>(s, n, m, ne, Wf, Wc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0));
+    prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));
+    return 0;
+  }
+};
+
+// CSR storage, real symmetric: BiCGSTAB on every shifted system (IFEAST)
+template <typename C>
+struct CsrOp : Operator<double> {
+  using R = typename real_of<C>::type;
+  mfeast_ctx* h;
+  char uplo;
+  int64_t n;
+  const double *a, *b;
+  const int32_t *ia, *ja, *ib, *jb;
+  int base;
+  const std::vector<c64>& z;
+  int ne, m0max, maxit;
+  double tol;
+  CsrMat<R> MA, MB;
+  int group = 0;  // nodes per BiCGSTAB batch (bounded by device memory)
+  c64* zdev = nullptr;
+  R* bh = nullptr;
+  C* vec = nullptr;
+  BiCol* col = nullptr;
+  int* tiles = nullptr;
+  double* part = nullptr;
+  int* dbuf = nullptr;
+  int* hbuf = nullptr;
+  int64_t iterations = 0;  // fpm(60): sum over solves of the largest column count per node
+
+  CsrOp(mfeast_ctx* h_, char uplo_, int64_t n_, const double* a_, const int32_t* ia_, const int32_t* ja_,
+        int base_, const double* b_, const int32_t* ib_, const int32_t* jb_, const std::vector<c64>& z_, int m0_,
+        int maxit_, double tol_)
+      : h(h_), uplo(uplo_), n(n_), a(a_), b(b_), ia(ia_), ja(ja_), ib(ib_), jb(jb_), base(base_), z(z_),
+        ne((int)z_.size()), m0max(m0_), maxit(maxit_), tol(tol_) {
+    this->hasB = b_ != nullptr;
+  }
+
+  int prepare(hipStream_t s) override {
+    int err = 0;
+    MF_TRY(csr_full<R>(s, n, a, ia, ja, base, uplo, h->csrA, MA, &err));
+    if (err) {
+      return err == 1 ? -105 : err == 2 ? -106 : -104;
+    }
+    if (b) {
+      MF_TRY(csr_full<R>(s, n, b, ib, jb, base, uplo, h->csrB, MB, &err));
+      if (err) {
+        return err == 1 ? -109 : err == 2 ? -110 : -108;
+      }
+    }
+    // nodes per batch: six n x (nodes * m0) vectors must fit in device memory
+    const int64_t nrb = (n + 255) / 256;
+    const double per_node = 6.0 * (double)n * m0max * sizeof(C) + 4.0 * nrb * m0max * 8.0 + m0max * sizeof(BiCol);
+    size_t fr = 0, tot = 0;
+    MF_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    const double avail = 0.85 * ((double)fr + (double)h->cap[S_BI_VEC] + (double)h->cap[S_BI_PART]);
+    group = (int)std::min<double>(ne, std::floor(avail / per_node));
+    group = std::min(group, (int)(65535LL * 64 / std::max(1, m0max)));
+    if (group < 1) return -2;
+    const size_t ncolmax = (size_t)group * m0max;
+    const size_t blk = (size_t)n * ncolmax;
+    zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
+    bh = (R*)h->ws(S_BI_BH, (size_t)n * m0max * sizeof(R));
+    vec = (C*)h->ws(S_BI_VEC, 6 * blk * sizeof(C));
+    col = (BiCol*)h->ws(S_BI_COL, ncolmax * sizeof(BiCol));
+    tiles = (int*)h->ws(S_BI_TILES, ((ncolmax + 63) / 64) * sizeof(int));
+    part = (double*)h->ws(S_BI_PART, 4 * (size_t)nrb * ncolmax * sizeof(double));
+    dbuf = (int*)h->ws(S_BI_BUF, ncolmax * sizeof(int));
+    hbuf = h->host_ints(ncolmax);
+    if (!zdev || !bh || !vec || !col || !tiles || !part || !dbuf || !hbuf) return -2;
+    MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+    return 0;
+  }
+
+  int apply_A(hipStream_t s, int m, const double* X, double* Y) override {
+    const int tok = prof_begin(s);
+    MF_TRY(spmm_rm(s, MA, m, X, m, Y, m));
+    prof_end(tok, s, K_OTHER, 2.0 * MA.nnz * m, (double)m * n * 16.0 + MA.nnz * 12.0);
+    return 0;
+  }
+  int apply_B(hipStream_t s, int m, const double* X, double* Y) override {
+    const int tok = prof_begin(s);
+    MF_TRY(spmm_rm(s, MB, m, X, m, Y, m));
+    prof_end(tok, s, K_OTHER, 2.0 * MB.nnz * m, (double)m * n * 16.0 + MB.nnz * 12.0);
+    return 0;
+  }
+
+  int contour(hipStream_t s, int m, const double* rhs, const Coef& k, const double* X, double* Q,
+              bool resid) override {
+    MF_TRY(bi_rhs<R>(s, n, m, rhs, k.cs, bh));
+    const size_t blk = (size_t)n * group * m;
+    std::vector<int> its;
+    for (int j0 = 0; j0 < ne; j0 += group) {
+      const int nj = std::min(group, ne - j0);
+      BiSys<C> sys;
+      sys.n = n;
+      sys.ncol = nj * m;
+      sys.m0 = m;
+      sys.A = &MA;
+      sys.B = b ? &MB : nullptr;
+      sys.zn = zdev + j0;
+      sys.bh = bh;
+      sys.x = vec;
+      sys.r = vec + blk;
+      sys.p = vec + 2 * blk;
+      sys.v = vec + 3 * blk;
+      sys.s = vec + 4 * blk;
+      sys.t = vec + 5 * blk;
+      sys.col = col;
+      sys.tiles = tiles;
+      sys.part = part;
+      MF_TRY(bicgstab_batched<C>(s, sys, maxit, tol, its, dbuf, hbuf));
+      for (int j = 0; j < nj; ++j) {
+        int mx = 0;
+        for (int q = 0; q < m; ++q) mx = std::max(mx, its[(size_t)j * m + q]);
+        iterations += mx;
+      }
+      const int tok = prof_begin(s);
+      MF_TRY(bi_accumulate<C>(s, n, m, nj, j0, sys.x, sys.ncol, k.cf, k.rho, k.us, X, Q,
+                              j0 == 0 ? (resid ? 1 : 0) : 2));
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * m * (nj * sizeof(C) + (resid ? 2.0 : 1.0) * 8.0));
+    }
+    return 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The subspace iteration, shared by every storage format.
+template <typename T>
+static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, double emin, double emax,
+                      int32_t* m0p, double* E, T* Xu, int64_t ldx, int32_t* Mout, double* res_out,
+                      double* epsout, int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w) {
   constexpr bool CPLX = is_cplx<T>::value;
   Timer total_t, ph;
   total_t.start();
   double t_fact = 0, t_solve = 0, t_prod = 0, t_eig = 0;
   hipStream_t s = h->stream;
-  if (hipSetDevice(h->device) != hipSuccess) return -900;
   auto f = [&](int i) { return fpm[i - 1]; };
-  prof_enable(f(52) == 1);
-  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
-  const int ne = f(2);
+  const int ne = (int)z.size();
   int m0 = *m0p;
   const double alpha = std::max(std::fabs(emin), std::fabs(emax));
   const double eps = std::pow(10.0, -f(3));
+  const bool hasB = op.hasB;
 
-  std::vector<c64> z, w;
-  if (zne != nullptr) {
-    z.resize(ne);
-    w.resize(ne);
-    for (int j = 0; j < ne; ++j) {
-      z[j] = c64(zne[2 * j], zne[2 * j + 1]);
-      w[j] = c64(wne[2 * j], wne[2 * j + 1]);
-    }
-  } else {
-    make_contour(emin, emax, ne, f(16), f(18), z, w);
-  }
-
-  // ---------------- workspace
-  const int64_t nblk = (n + LU_NB - 1) / LU_NB;
-  const size_t szT = sizeof(T), szC = sizeof(C);
-  C* LU = (C*)h->ws(S_LU, (size_t)ne * n * n * szC);
-  C* Dinv = (C*)h->ws(S_DINV, (size_t)ne * nblk * 2 * LU_NB * LU_NB * szC);
-  int* ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
-  int* perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);
-  int* pinv = (int*)h->ws(S_PINV, (size_t)ne * n * 4);
-  int* linfo = (int*)h->ws(S_INFO, (size_t)ne * 4 + 64);
-  c64* zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
-  C* Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0 * szC);
-  C* Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0 * szC) : nullptr;
+  // ---------------- workspace of the loop
+  const size_t szT = sizeof(T);
   const size_t blk = (size_t)n * m0 * szT;
   T* Xw = (T*)h->ws(S_X, blk);
   T* Q = (T*)h->ws(S_Q, blk);
   T* R = (T*)h->ws(S_R, blk);
   T* AQ = (T*)h->ws(S_AQ, blk);
-  T* BQ = B ? (T*)h->ws(S_BQ, blk) : Q;
+  T* BQ = hasB ? (T*)h->ws(S_BQ, blk) : Q;
   T* AX = (T*)h->ws(S_AX, blk);
-  T* BX = B ? (T*)h->ws(S_BX, blk) : Xw;
+  T* BX = hasB ? (T*)h->ws(S_BX, blk) : Xw;
   const size_t sq = (size_t)m0 * m0 * szT;
   T* Sm = (T*)h->ws(S_S, sq);
   T* Tm = (T*)h->ws(S_T, sq);
@@ -272,9 +508,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   double* part = (double*)h->ws(S_PART, (size_t)nchunk * m0 * 2 * sizeof(double));
   int* dflag = (int*)h->ws(S_FLAG, 256);
   char* hp = h->host(nsmall * sizeof(double) + 4096);
-  if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Xw || !Q || !R ||
-      !AQ || !BQ || !AX || !BX || !Sm || !Tm || !Hw || !V || !G || !TG || !Cm || !Zm || !GZ || !W || !small ||
-      !part || !dflag || !hp)
+  if (!Xw || !Q || !R || !AQ || !BQ || !AX || !BX || !Sm || !Tm || !Hw || !V || !G || !TG || !Cm || !Zm || !GZ ||
+      !W || !small || !part || !dflag || !hp)
     return -2;
   double* d_absmax = small;             // m0
   double* d_cs = small + m0;            // m0
@@ -307,42 +542,14 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
   c64* h_cc = h_cf + (size_t)ne * m0;
   int* h_flag = (int*)(h_absmax + 12 * m0 + 4 * (size_t)ne * m0);
 
-  // ---------------- full storage if a triangle was given
-  const T* Af = A;
-  int64_t ldaf = lda;
-  const T* Bf = B;
-  int64_t ldbf = ldb;
-  if (uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u') {
-    T* a2 = (T*)h->ws(S_AF, (size_t)n * n * szT);
-    if (!a2) return -2;
-    MF_TRY(expand_full<T>(s, uplo, n, A, lda, a2));
-    Af = a2;
-    ldaf = n;
-    if (B) {
-      T* b2 = (T*)h->ws(S_BF, (size_t)n * n * szT);
-      if (!b2) return -2;
-      MF_TRY(expand_full<T>(s, uplo, n, B, ldb, b2));
-      Bf = b2;
-      ldbf = n;
-    }
-  }
-
-  // ---------------- factor every shifted matrix
+  // ---------------- factor (dense) or convert (sparse)
   ph.start();
-  MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
-  MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
   {
-    const int tok = prof_begin(s);
-    MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
-    prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((B ? 2.0 : 1.0) * sizeof(T) + ne * sizeof(C)));
+    const int rc = op.prepare(s);
+    if (rc != 0) return rc;
   }
-  MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
-  std::vector<int> hinfo(ne);
-  MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
   MF_HIP_CHECK(hipStreamSynchronize(s));
   t_fact += ph.stop();
-  for (int j = 0; j < ne; ++j)
-    if (hinfo[j] != 0) return -2;
 
   // ---------------- starting block
   if (f(5) == 1) MF_TRY(copy_cm_to_rm<T>(s, n, m0, Xu, ldx, Xw, m0));
@@ -363,8 +570,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     const bool resid = (k > 0);
     const T* rhs;
     if (!resid) {
-      if (B) {
-        MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Xw, m0, R, m0));
+      if (hasB) {
+        MF_TRY(op.apply_B(s, m0, Xw, R));
         rhs = R;
       } else {
         rhs = Xw;
@@ -413,15 +620,8 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipMemcpyAsync(d_cf, h_cf, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemcpyAsync(d_cc, h_cc, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
     {
-      const double nb = (double)n * m0;
-      const int dirs = CPLX ? 2 : 1;
-      int tok = prof_begin(s);
-      MF_TRY(rhs_prepare<T, C>(s, n, m0, rhs, m0, d_cs, ne, perm, Wf, Wc));
-      prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
-      MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Dinv, Wf, Wc));
-      tok = prof_begin(s);
-      MF_TRY(accumulate<T, C>(s, n, m0, ne, Wf, Wc, pinv, d_cf, d_cc, d_rho, d_us, Xw, Q, resid ? 1 : 0));
-      prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));
+      const Coef kc{d_cs, d_us, d_rho, d_cf, d_cc};
+      MF_TRY(op.contour(s, m0, rhs, kc, Xw, Q, resid));
     }
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_solve += ph.stop();
@@ -439,10 +639,10 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
 
     // ---- Rayleigh-Ritz on span(Q) in an explicitly B-orthonormal basis (two passes)
     ph.start();
-    MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Af, ldaf, true, false, Q, m0, AQ, m0));
+    MF_TRY(op.apply_A(s, m0, Q, AQ));
     T* BQp = Q;
-    if (B) {
-      MF_TRY(rm_gemm<T>(s, (int)n, m0, (int)n, Bf, ldbf, true, false, Q, m0, BQ, m0));
+    if (hasB) {
+      MF_TRY(op.apply_B(s, m0, Q, BQ));
       BQp = BQ;
     }
     MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, BQp, m0, Sm, m0));
@@ -464,10 +664,10 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     // Q1 = Q H1, A Q1 = (A Q) H1, B Q1 = (B Q) H1  (no new product with A or B)
     T* Q1 = R;
     T* AQ1 = AX;
-    T* BQ1 = B ? BX : Q1;
+    T* BQ1 = hasB ? BX : Q1;
     MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, G, kk, Q1, kk));
     MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, G, kk, AQ1, kk));
-    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQp, m0, false, false, G, kk, BQ1, kk));
+    if (hasB) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQp, m0, false, false, G, kk, BQ1, kk));
     // pass 2: S1 = Q1^H B Q1 = I + F, T1 = Q1^H A Q1
     MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, BQ1, kk, Sm, kk));
     MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, AQ1, kk, Tm, kk));
@@ -528,10 +728,10 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     // W = G2 U;  X = Q1 W, AX = (A Q1) W, BX = (B Q1) W  (n x kk2, leading dimension kk2)
     MF_TRY(rm_gemm<T>(s, kk, kk2, kk2, G2, kk2, false, false, Zm, kk2, W, kk2));
     T* AXn = AQ;
-    T* BXn = B ? BQ : Xw;
+    T* BXn = hasB ? BQ : Xw;
     MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, Q1, kk, false, false, W, kk2, Xw, kk2));
     MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, AQ1, kk, false, false, W, kk2, AXn, kk2));
-    if (B) MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, BQ1, kk, false, false, W, kk2, BXn, kk2));
+    if (hasB) MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, BQ1, kk, false, false, W, kk2, BXn, kk2));
     m0 = kk2;
     MF_TRY(residual_norms<T>(s, n, m0, AXn, BXn, d_lam, R, d_rn, d_bn, part));
     MF_HIP_CHECK(hipMemcpyAsync(h_rn, d_rn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -600,11 +800,6 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
     MF_HIP_CHECK(hipStreamSynchronize(s));
     *m0p = m0;
   }
-  if (prof_on()) {
-    (void)hipStreamSynchronize(s);
-    prof_collect(h->prof);
-    prof_enable(false);
-  }
   h->timing[0] = t_fact;
   h->timing[1] = t_solve;
   h->timing[2] = t_prod;
@@ -617,6 +812,38 @@ static int feast_dense(mfeast_ctx* h, char uplo, int64_t n, const T* A, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// nodes from fpm(2), fpm(16), fpm(18), or the caller's expert contour
+static void nodes_for(const int32_t* fpm, double emin, double emax, const double* zne, const double* wne,
+                      std::vector<c64>& z, std::vector<c64>& w) {
+  const int ne = fpm[1];
+  if (zne != nullptr) {
+    z.resize(ne);
+    w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+      z[j] = c64(zne[2 * j], zne[2 * j + 1]);
+      w[j] = c64(wne[2 * j], wne[2 * j + 1]);
+    }
+  } else {
+    make_contour(emin, emax, ne, fpm[15], fpm[17], z, w);
+  }
+}
+
+// per-call set-up around the loop: device, optional kernel timing
+template <typename T>
+static int run_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, double emin, double emax,
+                    int32_t* m0, double* E, T* X, int64_t ldx, int32_t* M, double* res, double* epsout,
+                    int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w) {
+  prof_enable(fpm[51] == 1);
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
+  const int info = feast_loop<T>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+  if (prof_on()) {
+    (void)hipStreamSynchronize(h->stream);
+    prof_collect(h->prof);
+    prof_enable(false);
+  }
+  return info;
+}
+
 template <typename T>
 static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
                        int64_t ldb, int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X,
@@ -643,14 +870,68 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   if (res == nullptr) return -116;
   if (epsout == nullptr) return -117;
   if (loop == nullptr) return -118;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
   const T* At = reinterpret_cast<const T*>(A);
   const T* Bt = reinterpret_cast<const T*>(B);
   T* Xt = reinterpret_cast<T*>(X);
-  if (fpm[41] == 1)
-    return feast_dense<T, c32>(h, uplo, n, At, lda, Bt, ldb, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop,
-                               zne, wne);
-  return feast_dense<T, c64>(h, uplo, n, At, lda, Bt, ldb, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop,
-                             zne, wne);
+  std::vector<c64> z, w;
+  nodes_for(fpm, emin, emax, zne, wne, z, w);
+  if (fpm[41] == 1) {
+    DenseOp<T, c32> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
+    return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w);
+  }
+  DenseOp<T, c64> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
+  return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w);
+}
+
+static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, const int32_t* ia, const int32_t* ja,
+                     int32_t base, const double* b, const int32_t* ib, const int32_t* jb, int32_t* fpm, double emin,
+                     double emax, int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
+                     double* epsout, int32_t* loop, const double* zne, const double* wne) {
+  if (n < 1) return 202;
+  if (m0 == nullptr) return -114;
+  if (*m0 < 1 || *m0 > n) return 201;
+  if (!(emin < emax)) return 200;
+  if (fpm == nullptr) return -111;
+  if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -122 : -123;
+  const int fi = check_fpm(fpm, zne != nullptr);
+  if (fi) return fi;
+  if (fpm[44] < 0 || fpm[44] > 16) return 145;
+  if (fpm[45] < 1) return 146;
+  if (h == nullptr) return -101;
+  if (!(uplo == 'F' || uplo == 'f' || uplo == 'L' || uplo == 'l' || uplo == 'U' || uplo == 'u')) return -102;
+  if (n > (int64_t)INT32_MAX - 1) return -103;
+  if (a == nullptr) return -104;
+  if (ia == nullptr) return -105;
+  if (ja == nullptr) return -106;
+  if (base != 0 && base != 1) return -107;
+  if (b != nullptr && ib == nullptr) return -109;
+  if (b != nullptr && jb == nullptr) return -110;
+  if (E == nullptr) return -115;
+  if (X == nullptr) return -116;
+  if (ldx < n) return -117;
+  if (M == nullptr) return -118;
+  if (res == nullptr) return -119;
+  if (epsout == nullptr) return -120;
+  if (loop == nullptr) return -121;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  std::vector<c64> z, w;
+  nodes_for(fpm, emin, emax, zne, wne, z, w);
+  const double tol = std::pow(10.0, -fpm[44]);
+  fpm[59] = 0;
+  int info;
+  int64_t its;
+  if (fpm[41] == 1) {
+    CsrOp<c32> op(h, uplo, n, a, ia, ja, base, b, ib, jb, z, *m0, fpm[45], tol);
+    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+    its = op.iterations;
+  } else {
+    CsrOp<c64> op(h, uplo, n, a, ia, ja, base, b, ib, jb, z, *m0, fpm[45], tol);
+    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+    its = op.iterations;
+  }
+  fpm[59] = (int32_t)std::min<int64_t>(its, INT32_MAX);
+  return info;
 }
 
 extern "C" {
@@ -674,7 +955,10 @@ int mfeast_destroy(mfeast_handle h) {
   (void)hipDeviceSynchronize();
   for (int i = 0; i < S_NSLOTS; ++i)
     if (h->buf[i]) (void)hipFree(h->buf[i]);
+  h->csrA.release();
+  h->csrB.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->pinned_i) (void)hipHostFree(h->pinned_i);
   delete h;
   return 0;
 }
@@ -738,6 +1022,23 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
   return dense_entry<c64>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, zne,
                           wne);
+}
+
+int mfeast_dcsrgv(mfeast_handle h, char uplo, int64_t n, const double* a, const int32_t* ia, const int32_t* ja,
+                  int32_t index_base, const double* b, const int32_t* ib, const int32_t* jb, int32_t* fpm,
+                  double emin, double emax, int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M,
+                  double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
+  return csr_entry(h, uplo, n, a, ia, ja, index_base, b, ib, jb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout,
+                   loop, zne, wne);
+}
+
+void mfeast_init_ifeast(int32_t* fpm) {
+  if (fpm == nullptr) return;
+  mfeast_init(fpm);
+  fpm[1] = 4;     // fpm(2)  half-contour nodes
+  fpm[3] = 50;    // fpm(4)  refinement loops
+  fpm[15] = 1;    // fpm(16) trapezoidal rule
+  fpm[17] = 100;  // fpm(18) circle
 }
 
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count) {

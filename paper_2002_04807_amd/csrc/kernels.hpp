@@ -9,6 +9,8 @@
 //  * complex values are interleaved (re, im).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 #include "prof.hpp"
 
@@ -127,5 +129,68 @@ template <typename T>
 int ns_invsqrt(hipStream_t s, int k, const T* S, T* Z, int iters, T* work);
 template <typename T>
 int hermitian_part(hipStream_t s, int m, T* H);
+
+// ------------------------------------------------------------------ sparse path (sparse.hip)
+// Workspace of one CSR conversion (grown on demand, freed by release()).
+struct CsrWork {
+  static constexpr int NBUF = 9;
+  void* buf[NBUF] = {};
+  size_t cap[NBUF] = {};
+  void* get(int k, size_t bytes);
+  void release();
+};
+// 0-based full-storage CSR, columns sorted within each row; values in FP64 (vd) and in
+// the BiCGSTAB precision R (vr).  Arrays live in the CsrWork it was built in.
+template <typename R>
+struct CsrMat {
+  int64_t n = 0, nnz = 0;
+  int32_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  double* vd = nullptr;
+  R* vr = nullptr;
+};
+// From the caller's CSR (base 0 or 1; uplo 'F', or 'L'/'U' for one triangle of a symmetric
+// matrix).  *err: 0 ok, 1 bad row pointers, 2 column index out of range, 3 too many entries.
+template <typename R>
+int csr_full(hipStream_t s, int64_t n, const double* a, const int32_t* ia, const int32_t* ja, int base, char uplo,
+             CsrWork& w, CsrMat<R>& out, int* err);
+// Y = M X, X and Y row-major n x m FP64 blocks
+int spmm_rm(hipStream_t s, const CsrMat<float>& M, int m, const double* X, int64_t ldx, double* Y, int64_t ldy);
+int spmm_rm(hipStream_t s, const CsrMat<double>& M, int m, const double* X, int64_t ldx, double* Y, int64_t ldy);
+
+// per-column BiCGSTAB scalars (FP64)
+struct BiCol {
+  c64 rho, alpha, omega, beta;
+  double bn2;
+  int state, its;
+};
+// One batch of shifted systems (z_j B - A) x = b: columns c = j * m0 + q of row-major
+// n x ncol blocks, node j's shift zn[j], right-hand side column q of bh (n x m0).
+template <typename C>
+struct BiSys {
+  using R = typename real_of<C>::type;
+  int64_t n = 0;
+  int ncol = 0, m0 = 0;
+  const CsrMat<R>* A = nullptr;
+  const CsrMat<R>* B = nullptr;  // nullptr: identity
+  const c64* zn = nullptr;
+  const R* bh = nullptr;
+  C *x = nullptr, *r = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+  BiCol* col = nullptr;   // ncol
+  int* tiles = nullptr;   // ceil(ncol / 64)
+  double* part = nullptr; // 4 * ceil(n / 256) * ncol
+};
+// BiCGSTAB on every column to ||r|| <= tol ||b|| or maxit iterations; its[c] = iterations
+// of column c.  d_buf, h_buf (pinned): ncol ints of scratch each.
+template <typename C>
+int bicgstab_batched(hipStream_t s, const BiSys<C>& sys, int maxit, double tol, std::vector<int>& its, int* d_buf,
+                     int* h_buf);
+// bh = rhs .* colscale (row-major n x m0), in the BiCGSTAB precision
+template <typename R>
+int bi_rhs(hipStream_t s, int64_t n, int m0, const double* rhs, const double* cs, R* bh);
+// quadrature sum of the sparse path, see sparse.hip (mode 0: set, 1: set + rho X, 2: add)
+template <typename C>
+int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, int ncol, const c64* cf,
+                  const double* rho, const double* us, const double* X, double* Q, int mode);
 
 }  // namespace mf

@@ -17,7 +17,9 @@ enum KClass {
   K_RR_GEMM = 3,   // FP64 Rayleigh-Ritz products
   K_EIG = 4,       // reduced eigensolver
   K_OTHER = 5,     // shift-form, right-hand sides, quadrature sum, small kernels
-  K_NCLASS = 6
+  K_SPMV = 6,      // sparse shifted products inside BiCGSTAB
+  K_BICG = 7,      // BiCGSTAB vector updates and reductions
+  K_NCLASS = 8
 };
 
 bool prof_on();

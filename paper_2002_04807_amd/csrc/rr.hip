@@ -398,8 +398,9 @@ __device__ inline double splitmix_uniform(uint64_t seed, uint64_t t) {
 
 template <typename T>
 __global__ void k_random_block(int64_t n, int m, uint64_t seed, T* __restrict__ Y, int64_t ld) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i = blockIdx.y;
+  // rows on grid x (no 16-bit limit for tall blocks), 256-column chunks on grid y
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.x;
   if (j >= m) return;
   const uint64_t t = (uint64_t)i + (uint64_t)j * (uint64_t)n;
   if constexpr (is_cplx<T>::value) {
@@ -411,7 +412,7 @@ __global__ void k_random_block(int64_t n, int m, uint64_t seed, T* __restrict__ 
 
 template <typename T>
 int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld) {
-  hipLaunchKernelGGL((k_random_block<T>), dim3((m + 255) / 256, (unsigned)n), dim3(256), 0, s, n, m, seed, Y, ld);
+  hipLaunchKernelGGL((k_random_block<T>), dim3((unsigned)n, (m + 255) / 256), dim3(256), 0, s, n, m, seed, Y, ld);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

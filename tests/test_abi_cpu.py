@@ -97,3 +97,45 @@ def test_create_without_device_reports_minus_900():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert mf.library().mfeast_create(ctypes.byref(h), 0, None) == -900
+
+
+def test_ifeast_defaults_match_oracle():
+    got = mf.mfeast_init_ifeast()
+    np.testing.assert_array_equal(got.astype(np.int64), oracle.ifeastinit())
+
+
+def _csr_call(n=10, m0=4, emin=0.0, emax=1.0, fpm=None, handle=None, **kw):
+    """mfeast_dcsrgv with host dummies: only the host-side argument checks run."""
+    fpm = oracle.ifeastinit().astype(np.int32) if fpm is None else fpm
+    dummy = np.zeros(8)
+    idx = np.zeros(8, dtype=np.int32)
+    args = dict(uplo="F", a=dummy, ia=idx, ja=idx, base=0, b=None, ib=None, jb=None, E=dummy, X=dummy,
+                ldx=max(n, 1), res=dummy)
+    args.update(kw)
+    out = mf.mfeast_dcsrgv(handle, args["uplo"], n, args["a"], args["ia"], args["ja"], args["base"], args["b"],
+                           args["ib"], args["jb"], fpm, emin, emax, m0, args["E"], args["X"], args["ldx"],
+                           args["res"])
+    return out["info"]
+
+
+def test_csr_argument_checks_in_table_order():
+    assert _csr_call(n=0) == 202
+    assert _csr_call(m0=0) == 201
+    assert _csr_call(emin=2.0, emax=1.0) == 200
+    for idx, val, code in [(1, 0, 102), (2, 17, 103), (15, 3, 116), (44, -1, 145), (44, 17, 145), (45, 0, 146)]:
+        f = oracle.ifeastinit().astype(np.int32)
+        f[idx] = val
+        assert _csr_call(fpm=f) == code, (idx, val)
+    assert _csr_call() == -101
+    h = ctypes.c_void_p(1)
+    assert _csr_call(handle=h, uplo="Q") == -102
+    assert _csr_call(handle=h, a=None) == -104
+    assert _csr_call(handle=h, ia=None) == -105
+    assert _csr_call(handle=h, ja=None) == -106
+    assert _csr_call(handle=h, base=2) == -107
+    assert _csr_call(handle=h, b=np.zeros(4)) == -109
+    assert _csr_call(handle=h, b=np.zeros(4), ib=np.zeros(4, dtype=np.int32)) == -110
+    assert _csr_call(handle=h, E=None) == -115
+    assert _csr_call(handle=h, X=None) == -116
+    assert _csr_call(handle=h, ldx=3) == -117
+    assert _csr_call(handle=h, res=None) == -119

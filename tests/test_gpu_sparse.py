@@ -1,0 +1,210 @@
+"""GPU parity of the sparse IFEAST path (CSR, batched BiCGSTAB) against the FP64 oracle.
+
+Inputs are the seeded CSR matrices of workloads/; the GPU and the oracle each draw
+their own starting block from the same counter-based generator (fpm(51) seed), so the
+two runs share nothing but the matrix.  The bar is the dense one: exact count,
+eigenvalues within 1e-10 * max(|lambda|, alpha), cluster subspace angles within 1e-8,
+residuals of the reported pairs below the requested tolerance.  The 3-D Laplacian
+cases are also held to their closed form (eigenvalues and tensor-product sine
+eigenvectors), which the oracle cannot reach at full size.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle
+from workloads import generators as gen
+
+from parity import clusters, compare_eigenpairs, subspace_sin
+
+torch = pytest.importorskip("torch")
+mf = pytest.importorskip("paper_2002_04807_amd")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _laplacian(nx, ny=None, nz=None):
+    v, c, p = gen.laplacian_3d_csr(nx, ny, nz)
+    return v, p, c
+
+
+def _modes(nx, ny, nz):
+    out = []
+    for k1 in range(1, nx + 1):
+        for k2 in range(1, ny + 1):
+            for k3 in range(1, nz + 1):
+                lam = sum(2.0 - 2.0 * np.cos(k * np.pi / (m + 1)) for k, m in ((k1, nx), (k2, ny), (k3, nz)))
+                out.append((lam, k1, k2, k3))
+    out.sort()
+    return out
+
+
+def _mode_vector(nx, ny, nz, k1, k2, k3):
+    sx = np.sin(np.arange(1, nx + 1) * k1 * np.pi / (nx + 1))
+    sy = np.sin(np.arange(1, ny + 1) * k2 * np.pi / (ny + 1))
+    sz = np.sin(np.arange(1, nz + 1) * k3 * np.pi / (nz + 1))
+    v = (sz[:, None, None] * sy[None, :, None] * sx[None, None, :]).ravel()
+    return v / np.linalg.norm(v)
+
+
+def _fpm(nodes=None, tol_exp=None, maxit=None, fp32=True, extra=None, oracle_side=False):
+    f = oracle.ifeastinit() if oracle_side else mf.mfeast_init_ifeast()
+    if nodes is not None:
+        f[1] = nodes
+    if tol_exp is not None:
+        f[44] = tol_exp
+    if maxit is not None:
+        f[45] = maxit
+    if not oracle_side:
+        f[41] = 1 if fp32 else 0
+    for k, v in (extra or {}).items():
+        f[k] = v
+    return f
+
+
+def _closed_form_check(out, nx, ny, nz, emin, emax, count):
+    modes = _modes(nx, ny, nz)
+    lam = np.array([m[0] for m in modes])
+    assert out["M"] == count
+    E = out["E"].cpu().numpy()[:count]
+    alpha = max(abs(emin), abs(emax))
+    err = np.max(np.abs(E - lam[:count]) / np.maximum(np.abs(lam[:count]), alpha))
+    assert err <= 1e-10, err
+    X = out["X"].cpu().numpy()[:, :count]
+    worst = 0.0
+    for g in clusters(lam[:count], 1e-4 * alpha):
+        Xref = np.stack([_mode_vector(nx, ny, nz, *modes[i][1:]) for i in g], axis=1)
+        worst = max(worst, subspace_sin(X[:, g], Xref))
+    assert worst <= 1e-8, worst
+    return err, worst
+
+
+def test_helloworld_csr_one_based():
+    """The guide's IFEAST example: 1-based CSR, IFEAST defaults, M0 = 3 on [3, 5]."""
+    _say("ifeast helloworld")
+    g = json.load(open(os.path.join(GOLDEN, "helloworld.json")))
+    p = g["ifeast_printed"]
+    out = mf.feast_csr((np.array(p["csr_values"], float), np.array(p["csr_ia_1based"], np.int32),
+                        np.array(p["csr_ja_1based"], np.int32)), g["emin"], g["emax"], g["m0"], index_base=1)
+    torch.cuda.synchronize()
+    assert out["info"] == 0 and out["M"] == p["M"]
+    np.testing.assert_allclose(out["E"].cpu().numpy()[:2], [4.0, 4.0], atol=1e-12)
+    nsolve = 4 * (out["loop"] + 1)
+    assert nsolve <= out["fpm60"] <= 40 * nsolve
+    ref = oracle.feast_csr(sp.csr_matrix(np.array(g["A"], float)), None, g["emin"], g["emax"], g["m0"])
+    compare_eigenpairs(out["E"].cpu().numpy(), out["X"].cpu().numpy(), ref["E"], ref["X"], 2, 3.0, 5.0)
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_laplacian_3d_against_oracle_and_closed_form(fp32):
+    """9 x 10 x 11 grid (n = 990: four 256-row blocks with a ragged tail), 12 eigenvalues,
+    16 trapezoidal nodes on a circle, BiCGSTAB to 1e-4; 320 batched columns (5 tiles)."""
+    nx, ny, nz = 9, 10, 11
+    _say("ifeast laplacian %dx%dx%d fp32=%s" % (nx, ny, nz, fp32))
+    lam = np.array([m[0] for m in _modes(nx, ny, nz)])
+    cnt = 12
+    emax = 0.5 * (lam[cnt - 1] + lam[cnt])
+    v, p, c = _laplacian(nx, ny, nz)
+    out = mf.feast_csr((v, p, c), 0.0, emax, 20, fpm=_fpm(16, 4, 1000, fp32))
+    torch.cuda.synchronize()
+    assert out["info"] == 0, out["info"]
+    ref = oracle.feast_csr(sp.csr_matrix((v, c, p)), None, 0.0, emax, 20,
+                           _fpm(16, 4, 1000, oracle_side=True))
+    assert ref["info"] == 0 and out["M"] == ref["M"] == cnt
+    compare_eigenpairs(out["E"].cpu().numpy(), out["X"].cpu().numpy(), ref["E"], ref["X"], cnt, 0.0, emax)
+    _closed_form_check(out, nx, ny, nz, 0.0, emax, cnt)
+    assert np.all(out["res"].cpu().numpy()[:cnt] < 1e-12)
+    assert out["fpm60"] > 0
+
+
+@pytest.mark.parametrize("uplo,base", [("L", 0), ("U", 1), ("F", 1)])
+def test_triangle_storage_and_base(uplo, base):
+    nx, ny, nz = 7, 8, 6
+    _say("ifeast uplo=%s base=%d" % (uplo, base))
+    v, p, c = _laplacian(nx, ny, nz)
+    A = sp.csr_matrix((v, c, p))
+    T = A if uplo == "F" else (sp.tril(A) if uplo == "L" else sp.triu(A)).tocsr()
+    T.sort_indices()
+    lam = np.array([m[0] for m in _modes(nx, ny, nz)])
+    cnt = 8                                     # gap 0.094 to the ninth eigenvalue
+    emax = 0.5 * (lam[cnt - 1] + lam[cnt])
+    out = mf.feast_csr((T.data, T.indptr.astype(np.int32) + base, T.indices.astype(np.int32) + base), 0.0, emax,
+                       cnt + 6, fpm=_fpm(12, 5, 1000), uplo=uplo, index_base=base)
+    torch.cuda.synchronize()
+    assert out["info"] == 0
+    _closed_form_check(out, nx, ny, nz, 0.0, emax, cnt)
+
+
+def test_generalized_pencil_against_dense_eigh():
+    """B sparse SPD with off-diagonal entries on A's pattern: B = I + 0.05 A / 6 with A
+    the 3-D Laplacian (strictly diagonally dominant, so positive definite)."""
+    nx, ny, nz = 6, 7, 8
+    _say("ifeast generalized")
+    v, p, c = _laplacian(nx, ny, nz)
+    A = sp.csr_matrix((v, c, p))
+    n = A.shape[0]
+    Bm = (sp.identity(n) + 0.05 * A / 6.0).tocsr()
+    Bm.sort_indices()
+    lam = sla.eigh(A.toarray(), Bm.toarray(), eigvals_only=True)
+    gaps = np.diff(lam[:30])
+    cnt = 5 + int(np.argmax(gaps[4:])) + 1
+    emin, emax = lam[0] - 0.1, 0.5 * (lam[cnt - 1] + lam[cnt])
+    out = mf.feast_csr((v, p, c), emin, emax, cnt + 8, fpm=_fpm(12, 5, 2000),
+                       B=(Bm.data, Bm.indptr.astype(np.int32), Bm.indices.astype(np.int32)))
+    torch.cuda.synchronize()
+    assert out["info"] == 0 and out["M"] == cnt
+    ref = oracle.feast_csr(A, Bm, emin, emax, cnt + 8, _fpm(12, 5, 2000, oracle_side=True))
+    assert ref["M"] == cnt
+    compare_eigenpairs(out["E"].cpu().numpy(), out["X"].cpu().numpy(), ref["E"], ref["X"], cnt, emin, emax,
+                       B=Bm.toarray())
+    E = out["E"].cpu().numpy()[:cnt]
+    assert np.max(np.abs(E - lam[:cnt])) <= 1e-10 * max(abs(emin), abs(emax))
+
+
+def test_first_contour_of_diagonal_pencil_is_filter_times_block():
+    """fpm(14) = 1 on A = diag(a), B = diag(d): Q = diag(rho(a / d)) Y with the GPU's own
+    starting block Y; FP64 BiCGSTAB to 1e-13 (fpm(42) = 0)."""
+    _say("ifeast diagonal pencil")
+    rng = np.random.default_rng(3)
+    n, m0 = 300, 6
+    a = rng.uniform(-2.0, 3.0, n)
+    d = rng.uniform(0.5, 2.0, n)
+    ia = np.arange(n + 1, dtype=np.int32)
+    ja = np.arange(n, dtype=np.int32)
+    out = mf.feast_csr((a, ia, ja), -0.5, 1.0, m0, fpm=_fpm(6, 13, 3000, fp32=False, extra={13: 1}),
+                       B=(d, ia, ja))
+    torch.cuda.synchronize()
+    assert out["info"] == 4
+    Y = oracle.initial_subspace(n, m0, 0, False)
+    z, w = oracle.half_contour(-0.5, 1.0, 6, rule=1, ratio_pct=100)
+    want = oracle.rational_filter(a / d, z, w)[:, None] * Y
+    got = out["X"].cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_invalid_csr_is_rejected_on_device():
+    _say("ifeast invalid csr")
+    v, p, c = _laplacian(4)
+    bad_col = c.copy()
+    bad_col[5] = 64
+    out = mf.feast_csr((v, p, bad_col), 0.0, 1.0, 8)
+    assert out["info"] == -106
+    bad_ptr = p.copy()
+    bad_ptr[10] = bad_ptr[11] + 1
+    out = mf.feast_csr((v, bad_ptr, c), 0.0, 1.0, 8)
+    assert out["info"] == -105
+    out = mf.feast_csr((v, p + 1, c), 0.0, 1.0, 8, index_base=0)
+    assert out["info"] == -105
