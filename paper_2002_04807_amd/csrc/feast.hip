@@ -386,25 +386,26 @@ struct CsrOp : Operator<double> {
         return err == 1 ? -109 : err == 2 ? -110 : -108;
       }
     }
-    // nodes per batch: six n x (nodes * m0) vectors must fit in device memory
+    // nodes per batch: five n x (nodes * m0) vectors must fit in device memory
     const int64_t nrb = (n + 255) / 256;
-    const double per_node = 6.0 * (double)n * m0max * sizeof(C) + 4.0 * nrb * m0max * 8.0 + m0max * sizeof(BiCol);
+    const double per_node =
+        5.0 * (double)n * m0max * sizeof(C) + 8.0 * (nrb + 32.0) * m0max * 8.0 + m0max * sizeof(BiCol);
     size_t fr = 0, tot = 0;
     MF_HIP_CHECK(hipMemGetInfo(&fr, &tot));
     const double avail = 0.85 * ((double)fr + (double)h->cap[S_BI_VEC] + (double)h->cap[S_BI_PART]);
     group = (int)std::min<double>(ne, std::floor(avail / per_node));
     group = std::min(group, (int)(65535LL * 64 / std::max(1, m0max)));
     if (group < 1) return -2;
-    const size_t ncolmax = (size_t)group * m0max;
+    const size_t ncolmax = ((size_t)group * m0max + 63) / 64 * 64;  // whole 64-column tiles
     const size_t blk = (size_t)n * ncolmax;
     zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
     bh = (R*)h->ws(S_BI_BH, (size_t)n * m0max * sizeof(R));
-    vec = (C*)h->ws(S_BI_VEC, 6 * blk * sizeof(C));
+    vec = (C*)h->ws(S_BI_VEC, 5 * blk * sizeof(C));
     col = (BiCol*)h->ws(S_BI_COL, ncolmax * sizeof(BiCol));
     tiles = (int*)h->ws(S_BI_TILES, ((ncolmax + 63) / 64) * sizeof(int));
-    part = (double*)h->ws(S_BI_PART, 4 * (size_t)nrb * ncolmax * sizeof(double));
-    dbuf = (int*)h->ws(S_BI_BUF, ncolmax * sizeof(int));
-    hbuf = h->host_ints(ncolmax);
+    part = (double*)h->ws(S_BI_PART, 8 * ((size_t)nrb + 32) * ncolmax * sizeof(double));
+    dbuf = (int*)h->ws(S_BI_BUF, (ncolmax + 64) * sizeof(int));
+    hbuf = h->host_ints(ncolmax + 64);
     if (!zdev || !bh || !vec || !col || !tiles || !part || !dbuf || !hbuf) return -2;
     MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
     return 0;
@@ -426,7 +427,7 @@ struct CsrOp : Operator<double> {
   int contour(hipStream_t s, int m, const double* rhs, const Coef& k, const double* X, double* Q,
               bool resid) override {
     MF_TRY(bi_rhs<R>(s, n, m, rhs, k.cs, bh));
-    const size_t blk = (size_t)n * group * m;
+    const size_t blk = (size_t)n * (((size_t)group * m0max + 63) / 64 * 64);
     std::vector<int> its;
     for (int j0 = 0; j0 < ne; j0 += group) {
       const int nj = std::min(group, ne - j0);
@@ -442,8 +443,7 @@ struct CsrOp : Operator<double> {
       sys.r = vec + blk;
       sys.p = vec + 2 * blk;
       sys.v = vec + 3 * blk;
-      sys.s = vec + 4 * blk;
-      sys.t = vec + 5 * blk;
+      sys.t = vec + 4 * blk;
       sys.col = col;
       sys.tiles = tiles;
       sys.part = part;
@@ -454,8 +454,7 @@ struct CsrOp : Operator<double> {
         iterations += mx;
       }
       const int tok = prof_begin(s);
-      MF_TRY(bi_accumulate<C>(s, n, m, nj, j0, sys.x, sys.ncol, k.cf, k.rho, k.us, X, Q,
-                              j0 == 0 ? (resid ? 1 : 0) : 2));
+      MF_TRY(bi_accumulate<C>(s, n, m, nj, j0, sys.x, k.cf, k.rho, k.us, X, Q, j0 == 0 ? (resid ? 1 : 0) : 2));
       prof_end(tok, s, K_OTHER, 0.0, (double)n * m * (nj * sizeof(C) + (resid ? 2.0 : 1.0) * 8.0));
     }
     return 0;

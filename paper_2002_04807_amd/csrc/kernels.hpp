@@ -164,8 +164,9 @@ struct BiCol {
   double bn2;
   int state, its;
 };
-// One batch of shifted systems (z_j B - A) x = b: columns c = j * m0 + q of row-major
-// n x ncol blocks, node j's shift zn[j], right-hand side column q of bh (n x m0).
+// One batch of shifted systems (z_j B - A) x = b: columns c = j * m0 + q, node j's shift
+// zn[j], right-hand side column q of bh (n x m0 row-major).  Vectors are tile-major:
+// element (i, c) at ((c / 64) * n + i) * 64 + c % 64, n x ceil(ncol / 64) * 64 entries.
 template <typename C>
 struct BiSys {
   using R = typename real_of<C>::type;
@@ -175,13 +176,13 @@ struct BiSys {
   const CsrMat<R>* B = nullptr;  // nullptr: identity
   const c64* zn = nullptr;
   const R* bh = nullptr;
-  C *x = nullptr, *r = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+  C *x = nullptr, *r = nullptr, *p = nullptr, *v = nullptr, *t = nullptr;
   BiCol* col = nullptr;   // ncol
   int* tiles = nullptr;   // ceil(ncol / 64)
-  double* part = nullptr; // 4 * ceil(n / 256) * ncol
+  double* part = nullptr; // 8 * (ceil(n / 256) + 32) * ceil(ncol / 64) * 64
 };
 // BiCGSTAB on every column to ||r|| <= tol ||b|| or maxit iterations; its[c] = iterations
-// of column c.  d_buf, h_buf (pinned): ncol ints of scratch each.
+// of column c.  d_buf, h_buf (pinned): ncol + 64 ints of scratch each.
 template <typename C>
 int bicgstab_batched(hipStream_t s, const BiSys<C>& sys, int maxit, double tol, std::vector<int>& its, int* d_buf,
                      int* h_buf);
@@ -190,7 +191,7 @@ template <typename R>
 int bi_rhs(hipStream_t s, int64_t n, int m0, const double* rhs, const double* cs, R* bh);
 // quadrature sum of the sparse path, see sparse.hip (mode 0: set, 1: set + rho X, 2: add)
 template <typename C>
-int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, int ncol, const c64* cf,
-                  const double* rho, const double* us, const double* X, double* Q, int mode);
+int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, const c64* cf, const double* rho,
+                  const double* us, const double* X, double* Q, int mode);
 
 }  // namespace mf

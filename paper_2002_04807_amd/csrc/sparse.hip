@@ -7,12 +7,15 @@
 //  * bicgstab_batched: BiCGSTAB (van der Vorst 1992) on all shifted systems
 //    (z_j B - A) x = b at once: one column per (node j, right-hand side q).  Every
 //    node shares the same right-hand side block b (n x m0, real), so the shadow residual
-//    r_hat = r_0 = b is stored once.  Vectors are row-major n x ncol blocks
-//    (ncol = nodes * m0, column c = j * m0 + q) so that a sparse row touches
-//    contiguous memory across all columns; per-column inner products are reduced in
-//    FP64, deterministically (per-workgroup partials, then a fixed-order sum).
-//    Converged columns stop: the host rebuilds the list of 64-column tiles that
-//    still hold an active column after every iteration and launches only those.
+//    r_hat = r_0 = b is stored once.  Columns c = j * m0 + q (ncol = nodes * m0) are
+//    grouped in tiles of 64; a vector is stored tile-major, element (i, c) at
+//    ((c / 64) * n + i) * 64 + c % 64, so one tile is a contiguous n x 64 block
+//    (a wave reads 512 contiguous bytes per row, consecutive rows are adjacent, and
+//    the few tiles still active late in the solve spread over every memory channel).
+//    Per-column inner products are reduced in FP64, deterministically: one partial
+//    per column and 256-row block, then a fixed-order sum by one workgroup per tile.
+//    Converged columns stop: a device-side list of the tiles that still hold an
+//    active column drives every kernel.
 #include <algorithm>
 #include <vector>
 
@@ -274,14 +277,29 @@ int spmm_rm(hipStream_t s, const CsrMat<double>& M, int m, const double* X, int6
 // ===========================================================================
 // Batched BiCGSTAB
 // ===========================================================================
+// One iteration is three sweeps over the vectors plus three per-column scalar steps:
+//   A  v = (z B - A) p,                       partial r_hat^H v
+//      alpha = rho / r_hat^H v
+//   B  t = (z B - A) s with s = r - alpha v formed on the fly (s is never stored),
+//      partials r_hat^H s, r_hat^H t, t^H s, t^H t, s^H s
+//      half-step test on ||s||; omega = t^H s / t^H t;
+//      rho' = r_hat^H r' = r_hat^H s - omega r_hat^H t, beta = (rho' / rho)(alpha / omega)
+//   C  x += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v),  ||r'||^2
+//      final test on ||r'||
+// rho' is the textbook r_hat^H r' written through the two inner products of B (the
+// same quantity; it only lets the p update join the x and r updates in one sweep).
+// Every sweep reads its own rows plus, in A and B, the sparse neighbours (through the
+// caches); the per-iteration HBM traffic is 13 vector passes (A 2, B 3, C 8).
 namespace {
 
 constexpr int BI_TILE = 64;                // columns per tile: one lane per column
 constexpr int BI_WAVES = 4;                // waves per workgroup, each on its own rows
 constexpr int BI_RB = 256;                 // rows per workgroup
 constexpr int BI_RW = BI_RB / BI_WAVES;    // rows per wave
+constexpr int BI_NQ = 8;                   // partial sums per column (largest sweep)
+constexpr int BI_NSPLIT = 32;              // first-stage groups of row blocks
 
-enum { ST_ACTIVE = 0, ST_HALF = 1, ST_DONE = 2 };
+enum { ST_ACTIVE = 0, ST_HALF = 1, ST_DONE = 2, ST_LAST = 3 };
 
 template <typename C>
 struct BiK {
@@ -294,15 +312,19 @@ struct BiK {
   const R* vb;
   const c64* zn;  // shift of each node in this batch
   const R* bh;    // right-hand side b = shadow residual, n x m0 real
-  C *x, *r, *p, *v, *s, *t;
+  C *x, *r, *p, *v, *t;  // tile-major
   BiCol* col;
   const int* tiles;
-  double* part;  // [quantity][row block][column]
+  const int* ntile;  // number of valid entries of tiles (device)
+  double* part;      // [quantity][row block][column], ncol rounded up to whole tiles
+  double* part2;     // [quantity][split][column]: sums over groups of row blocks
+  int ldp;           // that rounded column count
+  int nsplit;        // number of row-block groups
 };
 
 // sum the per-lane partials of the 4 waves and store them as one partial per column
 template <int NQ>
-__device__ inline void bi_store_partials(double (&acc)[NQ], double* part, int nrb, int ncol, int c) {
+__device__ inline void bi_store_partials(const double (&acc)[NQ], double* part, int nrb, int ncol, int c) {
   __shared__ double red[NQ][BI_WAVES][BI_TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -317,60 +339,76 @@ __device__ inline void bi_store_partials(double (&acc)[NQ], double* part, int nr
   }
 }
 
-// x = 0, r = b; partial b^T b
+// rows of this wave
+struct RowRange {
+  int64_t r0, r1;
+};
+__device__ inline RowRange bi_rows(int64_t n) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
+  return {r0, (r0 + BI_RW < n) ? r0 + BI_RW : n};
+}
+
+// sum_k M(i, k) in(k) over one sparse row, eight entries in flight at a time; `get`
+// returns the operand of column c at row k
+template <typename C, typename R, typename Get>
+__device__ inline C bi_row_dot(const int32_t* __restrict__ ci, const R* __restrict__ va, int kb, int ke, Get get) {
+  C acc(R(0), R(0));
+  for (int k0 = kb; k0 < ke; k0 += 8) {
+    C xv[8];
+    R av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u < ke) {
+        av[u] = va[k0 + u];
+        xv[u] = get((int64_t)ci[k0 + u]);
+      } else {
+        av[u] = R(0);
+        xv[u] = C(R(0), R(0));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc.re += av[u] * xv[u].re;
+      acc.im += av[u] * xv[u].im;
+    }
+  }
+  return acc;
+}
+
+// x = 0, r = p = b; partial b^T b
 template <typename C>
 __global__ __launch_bounds__(256) void k_bi_init(BiK<C> a) {
   using R = typename real_of<C>::type;
   const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = a.tiles[blockIdx.y] * BI_TILE + lane;
+  const int tile = a.tiles[blockIdx.y];
+  const int c = tile * BI_TILE + lane;
   const bool in = c < a.ncol;
   const int q = in ? c % a.m0 : 0;
   double acc[1] = {0.0};
-  const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
-  const int64_t r1 = (r0 + BI_RW < a.n) ? r0 + BI_RW : a.n;
+  const RowRange rr = bi_rows(a.n);
+  const int64_t tb = (int64_t)tile * a.n * BI_TILE + lane;
   if (in) {
-    for (int64_t i = r0; i < r1; ++i) {
+    for (int64_t i = rr.r0; i < rr.r1; ++i) {
       const R b = a.bh[i * a.m0 + q];
-      a.r[i * a.ncol + c] = C(b, R(0));
-      a.x[i * a.ncol + c] = C(R(0), R(0));
+      const int64_t o = tb + i * BI_TILE;
+      a.r[o] = C(b, R(0));
+      a.p[o] = C(b, R(0));
+      a.x[o] = C(R(0), R(0));
       acc[0] += (double)b * (double)b;
     }
   }
-  bi_store_partials<1>(acc, a.part, a.nrb, a.ncol, in ? c : -1);
+  bi_store_partials<1>(acc, a.part, a.nrb, a.ldp, in ? c : -1);
 }
 
-// p = r (first iteration) or p = r + beta (p - omega v)
+// sweep A: v = z_j (B p) - A p; partial r_hat^H v
 template <typename C>
-__global__ __launch_bounds__(256) void k_bi_p(BiK<C> a, int first) {
+__global__ __launch_bounds__(256) void k_bi_sweep_a(BiK<C> a) {
   using R = typename real_of<C>::type;
+  if ((int)blockIdx.y >= *a.ntile) return;
   const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = a.tiles[blockIdx.y] * BI_TILE + lane;
-  if (c >= a.ncol || a.col[c].state != ST_ACTIVE) return;
-  const C be = convert<C, c64>(a.col[c].beta), om = convert<C, c64>(a.col[c].omega);
-  const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
-  const int64_t r1 = (r0 + BI_RW < a.n) ? r0 + BI_RW : a.n;
-  for (int64_t i = r0; i < r1; ++i) {
-    const int64_t o = i * a.ncol + c;
-    const C rv = a.r[o];
-    if (first) {
-      a.p[o] = rv;
-    } else {
-      a.p[o] = rv + be * (a.p[o] - om * a.v[o]);
-    }
-  }
-}
-
-// out = z_j (B in) - A in for the active columns, with per-column partial sums:
-// MODE 0: r_hat^H out (2 values); MODE 1: out^H in (2), ||out||^2, ||in||^2
-template <typename C, int MODE>
-__global__ __launch_bounds__(256) void k_bi_spmv(BiK<C> a, const C* __restrict__ in, C* __restrict__ out) {
-  using R = typename real_of<C>::type;
-  constexpr int NQ = MODE == 0 ? 2 : 4;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = a.tiles[blockIdx.y] * BI_TILE + lane;
+  const int tile = a.tiles[blockIdx.y];
+  const int c = tile * BI_TILE + lane;
   const bool act = c < a.ncol && a.col[c].state == ST_ACTIVE;
   C z(R(0), R(0));
   int q = 0;
@@ -378,118 +416,158 @@ __global__ __launch_bounds__(256) void k_bi_spmv(BiK<C> a, const C* __restrict__
     z = convert<C, c64>(a.zn[c / a.m0]);
     q = c % a.m0;
   }
-  double acc[NQ];
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
-  const int64_t r1 = (r0 + BI_RW < a.n) ? r0 + BI_RW : a.n;
-  const int64_t ld = a.ncol;
-  for (int64_t i = r0; i < r1; ++i) {
+  double acc[2] = {0.0, 0.0};
+  const RowRange rr = bi_rows(a.n);
+  const int64_t tb = (int64_t)tile * a.n * BI_TILE + lane;
+  const C* __restrict__ p = a.p + tb;
+  C* __restrict__ v = a.v + tb;
+  auto get = [&](int64_t k) { return p[k * BI_TILE]; };
+  for (int64_t i = rr.r0; i < rr.r1; ++i) {
     const int kb = a.rp[i], ke = a.rp[i + 1];
     if (!act) continue;
-    C sa(R(0), R(0));
-    for (int k = kb; k < ke; ++k) {
-      const R av = a.va[k];
-      const C xv = in[(int64_t)a.ci[k] * ld + c];
-      sa.re += av * xv.re;
-      sa.im += av * xv.im;
-    }
-    const C xi = in[i * ld + c];
-    C sb = xi;
-    if (a.rpb != nullptr) {
-      sb = C(R(0), R(0));
-      const int bb = a.rpb[i], be = a.rpb[i + 1];
-      for (int k = bb; k < be; ++k) {
-        const R bv = a.vb[k];
-        const C xv = in[(int64_t)a.cib[k] * ld + c];
-        sb.re += bv * xv.re;
-        sb.im += bv * xv.im;
-      }
-    }
+    const C sa = bi_row_dot<C, R>(a.ci, a.va, kb, ke, get);
+    const C sb = (a.rpb == nullptr) ? get(i) : bi_row_dot<C, R>(a.cib, a.vb, a.rpb[i], a.rpb[i + 1], get);
     const C o = z * sb - sa;
-    out[i * ld + c] = o;
-    if constexpr (MODE == 0) {
-      const double h = (double)a.bh[i * a.m0 + q];
-      acc[0] += h * (double)o.re;
-      acc[1] += h * (double)o.im;
-    } else {
-      const double ore = o.re, oim = o.im, sre = xi.re, sim = xi.im;
-      acc[0] += ore * sre + oim * sim;  // conj(t) s
-      acc[1] += ore * sim - oim * sre;
-      acc[2] += ore * ore + oim * oim;
-      acc[3] += sre * sre + sim * sim;
-    }
+    v[i * BI_TILE] = o;
+    const double h = (double)a.bh[i * a.m0 + q];
+    acc[0] += h * (double)o.re;
+    acc[1] += h * (double)o.im;
   }
-  bi_store_partials<NQ>(acc, a.part, a.nrb, a.ncol, act ? c : -1);
+  bi_store_partials<2>(acc, a.part, a.nrb, a.ldp, act ? c : -1);
 }
 
-// s = r - alpha v
+// sweep B: s = r - alpha v (not stored), t = z_j (B s) - A s;
+// partials r_hat^H s (2), r_hat^H t (2), t^H s (2), t^H t, s^H s
 template <typename C>
-__global__ __launch_bounds__(256) void k_bi_s(BiK<C> a) {
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = a.tiles[blockIdx.y] * BI_TILE + lane;
-  if (c >= a.ncol || a.col[c].state != ST_ACTIVE) return;
-  const C al = convert<C, c64>(a.col[c].alpha);
-  const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
-  const int64_t r1 = (r0 + BI_RW < a.n) ? r0 + BI_RW : a.n;
-  for (int64_t i = r0; i < r1; ++i) {
-    const int64_t o = i * a.ncol + c;
-    a.s[o] = a.r[o] - al * a.v[o];
-  }
-}
-
-// x += alpha p + omega s, r = s - omega t (active); x += alpha p (converged at the half
-// step); partial r_hat^H r (2), ||r||^2
-template <typename C>
-__global__ __launch_bounds__(256) void k_bi_update(BiK<C> a) {
+__global__ __launch_bounds__(256) void k_bi_sweep_b(BiK<C> a) {
   using R = typename real_of<C>::type;
+  if ((int)blockIdx.y >= *a.ntile) return;
   const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = a.tiles[blockIdx.y] * BI_TILE + lane;
+  const int tile = a.tiles[blockIdx.y];
+  const int c = tile * BI_TILE + lane;
+  const bool act = c < a.ncol && a.col[c].state == ST_ACTIVE;
+  C z(R(0), R(0)), al(R(0), R(0));
+  int q = 0;
+  if (act) {
+    z = convert<C, c64>(a.zn[c / a.m0]);
+    al = convert<C, c64>(a.col[c].alpha);
+    q = c % a.m0;
+  }
+  double acc[BI_NQ];
+#pragma unroll
+  for (int k = 0; k < BI_NQ; ++k) acc[k] = 0.0;
+  const RowRange rr = bi_rows(a.n);
+  const int64_t tb = (int64_t)tile * a.n * BI_TILE + lane;
+  const C* __restrict__ r = a.r + tb;
+  const C* __restrict__ v = a.v + tb;
+  C* __restrict__ t = a.t + tb;
+  auto get = [&](int64_t k) { return r[k * BI_TILE] - al * v[k * BI_TILE]; };
+  for (int64_t i = rr.r0; i < rr.r1; ++i) {
+    const int kb = a.rp[i], ke = a.rp[i + 1];
+    if (!act) continue;
+    const C sa = bi_row_dot<C, R>(a.ci, a.va, kb, ke, get);
+    const C si = get(i);
+    const C sb = (a.rpb == nullptr) ? si : bi_row_dot<C, R>(a.cib, a.vb, a.rpb[i], a.rpb[i + 1], get);
+    const C o = z * sb - sa;
+    t[i * BI_TILE] = o;
+    const double h = (double)a.bh[i * a.m0 + q];
+    const double sre = si.re, sim = si.im, tre = o.re, tim = o.im;
+    acc[0] += h * sre;
+    acc[1] += h * sim;
+    acc[2] += h * tre;
+    acc[3] += h * tim;
+    acc[4] += tre * sre + tim * sim;  // conj(t) s
+    acc[5] += tre * sim - tim * sre;
+    acc[6] += tre * tre + tim * tim;
+    acc[7] += sre * sre + sim * sim;
+  }
+  bi_store_partials<BI_NQ>(acc, a.part, a.nrb, a.ldp, act ? c : -1);
+}
+
+// sweep C: x += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v);
+// x += alpha p only for a column that converged at the half step; partial ||r'||^2
+template <typename C>
+__global__ __launch_bounds__(256) void k_bi_sweep_c(BiK<C> a) {
+  if ((int)blockIdx.y >= *a.ntile) return;
+  const int lane = threadIdx.x & 63;
+  const int tile = a.tiles[blockIdx.y];
+  const int c = tile * BI_TILE + lane;
   const int st = (c < a.ncol) ? a.col[c].state : ST_DONE;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[1] = {0.0};
   if (st != ST_DONE) {
-    const C al = convert<C, c64>(a.col[c].alpha), om = convert<C, c64>(a.col[c].omega);
-    const int q = c % a.m0;
-    const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
-    const int64_t r1 = (r0 + BI_RW < a.n) ? r0 + BI_RW : a.n;
-    for (int64_t i = r0; i < r1; ++i) {
-      const int64_t o = i * a.ncol + c;
-      if (st == ST_HALF) {
+    const C al = convert<C, c64>(a.col[c].alpha), om = convert<C, c64>(a.col[c].omega),
+            be = convert<C, c64>(a.col[c].beta);
+    const RowRange rr = bi_rows(a.n);
+    const int64_t tb = (int64_t)tile * a.n * BI_TILE + lane;
+    if (st == ST_HALF) {
+      for (int64_t i = rr.r0; i < rr.r1; ++i) {
+        const int64_t o = tb + i * BI_TILE;
         a.x[o] = a.x[o] + al * a.p[o];
-      } else {
-        const C sv = a.s[o];
-        a.x[o] = a.x[o] + al * a.p[o] + om * sv;
-        const C rv = sv - om * a.t[o];
+      }
+    } else {
+#pragma unroll 2
+      for (int64_t i = rr.r0; i < rr.r1; ++i) {
+        const int64_t o = tb + i * BI_TILE;
+        const C pv = a.p[o], vv = a.v[o], sv = a.r[o] - al * vv, tv = a.t[o];
+        a.x[o] = a.x[o] + al * pv + om * sv;
+        const C rv = sv - om * tv;
         a.r[o] = rv;
-        const double h = (double)a.bh[i * a.m0 + q];
-        acc[0] += h * (double)rv.re;
-        acc[1] += h * (double)rv.im;
-        acc[2] += (double)rv.re * rv.re + (double)rv.im * rv.im;
+        a.p[o] = rv + be * (pv - om * vv);
+        acc[0] += (double)rv.re * rv.re + (double)rv.im * rv.im;
       }
     }
   }
-  bi_store_partials<3>(acc, a.part, a.nrb, a.ncol, (st == ST_ACTIVE) ? c : -1);
+  bi_store_partials<1>(acc, a.part, a.nrb, a.ldp, (st == ST_ACTIVE || st == ST_LAST) ? c : -1);
 }
 
-// per-column scalar step after each reduction (one thread per column, fixed-order sums)
-// MODE 0: init, 1: alpha, 2: omega and the half-step test, 3: rho, beta and the final test
-template <typename C, int MODE>
-__global__ void k_bi_scalar(BiK<C> a, int it, int maxit, double tol2) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.ncol) return;
-  BiCol& cs = a.col[c];
-  constexpr int NQ = MODE == 0 ? 1 : MODE == 1 ? 2 : MODE == 2 ? 4 : 3;
-  if constexpr (MODE != 0) {
-    if (MODE == 3 ? cs.state == ST_DONE : cs.state != ST_ACTIVE) return;
-  }
+// First stage of the column sums: workgroup (tile, split) adds the partials of row
+// blocks split, split + nsplit, ... (lane = column, the 4 waves interleaved), in a
+// fixed order.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_bi_reduce(const int* __restrict__ tiles, const int* __restrict__ ntile,
+                                                   const double* __restrict__ part, double* __restrict__ part2,
+                                                   int nrb, int ldp, int nsplit) {
+  __shared__ double red[NQ][BI_WAVES][BI_TILE];
+  if ((int)blockIdx.x >= *ntile) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = tiles[blockIdx.x] * BI_TILE + lane;
+  const int sp = blockIdx.y;
   double sum[NQ];
+#pragma unroll
   for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
-  if (MODE != 3 || cs.state == ST_ACTIVE) {
-    for (int b = 0; b < a.nrb; ++b)
-      for (int q = 0; q < NQ; ++q) sum[q] += a.part[((int64_t)q * a.nrb + b) * a.ncol + c];
+#pragma unroll 4
+  for (int b = sp + w * nsplit; b < nrb; b += BI_WAVES * nsplit) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sum[q] += part[((int64_t)q * nrb + b) * ldp + c];
   }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][w][lane] = sum[q];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      part2[((int64_t)q * nsplit + sp) * ldp + c] = red[q][0][lane] + red[q][1][lane] + red[q][2][lane] + red[q][3][lane];
+  }
+}
+
+// per-column scalar step after each sweep: one wave per listed tile adds the nsplit
+// first-stage sums in a fixed order and updates its columns.
+// MODE 0: init, 1: alpha, 2: half-step test, omega, rho', beta, 3: final test
+template <typename C, int MODE>
+__global__ __launch_bounds__(64) void k_bi_scalar(BiK<C> a, int it, int maxit, double tol2) {
+  constexpr int NQ = MODE == 0 ? 1 : MODE == 1 ? 2 : MODE == 2 ? BI_NQ : 1;
+  if ((int)blockIdx.x >= *a.ntile) return;
+  const int c = a.tiles[blockIdx.x] * BI_TILE + (int)threadIdx.x;
+  if (c >= a.ncol) return;
+  double sum[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
+#pragma unroll 8
+  for (int sp = 0; sp < a.nsplit; ++sp) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sum[q] += a.part2[((int64_t)q * a.nsplit + sp) * a.ldp + c];
+  }
+  BiCol& cs = a.col[c];
   if constexpr (MODE == 0) {
     cs.bn2 = sum[0];
     cs.rho = c64(sum[0], 0.0);
@@ -499,44 +577,74 @@ __global__ void k_bi_scalar(BiK<C> a, int it, int maxit, double tol2) {
     cs.its = 0;
     cs.state = sum[0] > 0.0 ? ST_ACTIVE : ST_DONE;
   } else if constexpr (MODE == 1) {
+    if (cs.state != ST_ACTIVE) return;
     const c64 den(sum[0], sum[1]);
     if (den.re == 0.0 && den.im == 0.0) {
-      cs.state = ST_DONE;
+      cs.state = ST_DONE;  // breakdown: x stays as it is
       cs.its = it;
     } else {
       cs.alpha = cdiv(cs.rho, den);
     }
   } else if constexpr (MODE == 2) {
-    if (sum[3] <= tol2 * cs.bn2) {
+    if (cs.state != ST_ACTIVE) return;
+    if (sum[7] <= tol2 * cs.bn2) {
       cs.state = ST_HALF;
+      return;
+    }
+    const c64 om = sum[6] != 0.0 ? c64(sum[4] / sum[6], sum[5] / sum[6]) : c64(0.0, 0.0);
+    const c64 rho_new = c64(sum[0], sum[1]) - om * c64(sum[2], sum[3]);
+    cs.omega = om;
+    if ((om.re == 0.0 && om.im == 0.0) || (rho_new.re == 0.0 && rho_new.im == 0.0)) {
+      cs.state = ST_LAST;  // breakdown at the next step: finish this update, then stop
+      cs.beta = c64(0.0, 0.0);
     } else {
-      cs.omega = sum[2] != 0.0 ? c64(sum[0] / sum[2], sum[1] / sum[2]) : c64(0.0, 0.0);
+      cs.beta = cdiv(rho_new, cs.rho) * cdiv(cs.alpha, om);
     }
-  } else {
-    cs.its = it;
-    if (cs.state == ST_HALF) {
-      cs.state = ST_DONE;
-      return;
-    }
-    const c64 rho_new(sum[0], sum[1]);
-    if (sum[2] <= tol2 * cs.bn2 || (rho_new.re == 0.0 && rho_new.im == 0.0) ||
-        (cs.omega.re == 0.0 && cs.omega.im == 0.0) || it >= maxit) {
-      cs.state = ST_DONE;
-      return;
-    }
-    cs.beta = cdiv(rho_new, cs.rho) * cdiv(cs.alpha, cs.omega);
     cs.rho = rho_new;
+  } else {
+    if (cs.state == ST_DONE) return;
+    cs.its = it;
+    if (cs.state == ST_HALF || cs.state == ST_LAST || sum[0] <= tol2 * cs.bn2 || it >= maxit) cs.state = ST_DONE;
   }
 }
 
-}  // namespace
-
-namespace {
-// states (which = 0) or iteration counts (which = 1) of every column, packed
-__global__ void k_bi_gather(int ncol, const BiCol* __restrict__ col, int which, int* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncol) out[c] = which == 0 ? col[c].state : col[c].its;
+// list of 64-column tiles that still hold an active column (one workgroup)
+__global__ void k_bi_compact(int ncol, const BiCol* __restrict__ col, int* __restrict__ tiles,
+                             int* __restrict__ ntile) {
+  __shared__ int scan[256];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  const int nt = (ncol + BI_TILE - 1) / BI_TILE;
+  for (int t0 = 0; t0 < nt; t0 += 256) {
+    const int t = t0 + (int)threadIdx.x;
+    int flag = 0;
+    if (t < nt) {
+      const int c1 = (t + 1) * BI_TILE < ncol ? (t + 1) * BI_TILE : ncol;
+      for (int c = t * BI_TILE; c < c1 && !flag; ++c) flag = col[c].state == ST_ACTIVE;
+    }
+    scan[threadIdx.x] = flag;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int add = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (flag) tiles[base + scan[threadIdx.x] - 1] = t;
+    __syncthreads();
+    if (threadIdx.x == 255) base += scan[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ntile = base;
 }
+
+// iteration counts of every column, packed
+__global__ void k_bi_its(int ncol, const BiCol* __restrict__ col, int* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncol) out[c] = col[c].its;
+}
+
 }  // namespace
 
 template <typename C>
@@ -559,68 +667,81 @@ int bicgstab_batched(hipStream_t s, const BiSys<C>& sys, int maxit, double tol, 
   a.r = sys.r;
   a.p = sys.p;
   a.v = sys.v;
-  a.s = sys.s;
   a.t = sys.t;
   a.col = sys.col;
   a.tiles = sys.tiles;
+  a.ntile = d_buf;  // d_buf[0]: tile count; d_buf + 64: iteration counts
   a.part = sys.part;
   const int ntile_all = (sys.ncol + BI_TILE - 1) / BI_TILE;
+  a.ldp = ntile_all * BI_TILE;
+  a.nsplit = std::min(a.nrb, BI_NSPLIT);
+  a.part2 = sys.part + (size_t)BI_NQ * a.nrb * a.ldp;
   std::vector<int> tl(ntile_all);
   for (int i = 0; i < ntile_all; ++i) tl[i] = i;
-  int* d_tiles = sys.tiles;
-  MF_HIP_CHECK(hipMemcpyAsync(d_tiles, tl.data(), ntile_all * sizeof(int), hipMemcpyHostToDevice, s));
-  int ntile = ntile_all;
+  MF_HIP_CHECK(hipMemcpyAsync(sys.tiles, tl.data(), ntile_all * sizeof(int), hipMemcpyHostToDevice, s));
+  h_buf[0] = ntile_all;
+  MF_HIP_CHECK(hipMemcpyAsync(d_buf, h_buf, sizeof(int), hipMemcpyHostToDevice, s));
   const unsigned gs = (unsigned)((sys.ncol + 255) / 256);
+  const dim3 sb(64);
+  // column sums of NQ quantities over the listed tiles (first stage)
+  auto reduce = [&](int nq, int nt) {
+    const dim3 g(nt, a.nsplit);
+    if (nq == 1)
+      hipLaunchKernelGGL(k_bi_reduce<1>, g, dim3(256), 0, s, a.tiles, a.ntile, a.part, a.part2, a.nrb, a.ldp,
+                         a.nsplit);
+    else if (nq == 2)
+      hipLaunchKernelGGL(k_bi_reduce<2>, g, dim3(256), 0, s, a.tiles, a.ntile, a.part, a.part2, a.nrb, a.ldp,
+                         a.nsplit);
+    else
+      hipLaunchKernelGGL(k_bi_reduce<BI_NQ>, g, dim3(256), 0, s, a.tiles, a.ntile, a.part, a.part2, a.nrb, a.ldp,
+                         a.nsplit);
+  };
   const double tol2 = tol * tol;
   const double nb = (double)sys.n * sizeof(C);
+  const double nnzA = (double)sys.A->nnz, nnzB = sys.B ? (double)sys.B->nnz : 0.0;
   {
     const int tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_init<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_bi_scalar<C, 0>), dim3(gs), dim3(256), 0, s, a, 0, maxit, tol2);
-    prof_end(tok, s, K_BICG, 0.0, (double)sys.ncol * nb * 2.0);
+    hipLaunchKernelGGL((k_bi_init<C>), dim3(a.nrb, ntile_all), dim3(256), 0, s, a);
+    reduce(1, ntile_all);
+    hipLaunchKernelGGL((k_bi_scalar<C, 0>), dim3(ntile_all), sb, 0, s, a, 0, maxit, tol2);
+    prof_end(tok, s, K_BICG, 0.0, (double)sys.ncol * nb * 3.0);
   }
-  std::vector<int> st(sys.ncol);
+  // the launch grid follows the tile count read back every CHECK iterations; in
+  // between, workgroups beyond the device-side count exit at once
+  constexpr int CHECK = 4;
+  int ntile = ntile_all;
   for (int it = 1; it <= maxit && ntile > 0; ++it) {
-    const double cols = (double)ntile * BI_TILE;
-    const double nnzA = (double)sys.A->nnz, nnzB = sys.B ? (double)sys.B->nnz : 0.0;
+    const double cols = (double)ntile * BI_TILE;  // upper bound of the active columns
     int tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_p<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a, it == 1 ? 1 : 0);
-    prof_end(tok, s, K_BICG, 0.0, cols * nb * (it == 1 ? 2.0 : 4.0));
-    tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_spmv<C, 0>), dim3(a.nrb, ntile), dim3(256), 0, s, a, (const C*)a.p, a.v);
+    hipLaunchKernelGGL((k_bi_sweep_a<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
     prof_end(tok, s, K_SPMV, cols * 8.0 * (nnzA + nnzB + sys.n), cols * nb * 2.0);
     tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_scalar<C, 1>), dim3(gs), dim3(256), 0, s, a, it, maxit, tol2);
-    hipLaunchKernelGGL((k_bi_s<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
-    prof_end(tok, s, K_BICG, 0.0, cols * nb * 3.0);
+    reduce(2, ntile);
+    hipLaunchKernelGGL((k_bi_scalar<C, 1>), dim3(ntile), sb, 0, s, a, it, maxit, tol2);
+    prof_end(tok, s, K_BICG, 0.0, 0.0);
     tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_spmv<C, 1>), dim3(a.nrb, ntile), dim3(256), 0, s, a, (const C*)a.s, a.t);
-    prof_end(tok, s, K_SPMV, cols * 8.0 * (nnzA + nnzB + sys.n), cols * nb * 2.0);
+    hipLaunchKernelGGL((k_bi_sweep_b<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
+    prof_end(tok, s, K_SPMV, cols * 8.0 * (nnzA + nnzB + sys.n), cols * nb * 3.0);
     tok = prof_begin(s);
-    hipLaunchKernelGGL((k_bi_scalar<C, 2>), dim3(gs), dim3(256), 0, s, a, it, maxit, tol2);
-    hipLaunchKernelGGL((k_bi_update<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_bi_scalar<C, 3>), dim3(gs), dim3(256), 0, s, a, it, maxit, tol2);
-    prof_end(tok, s, K_BICG, 0.0, cols * nb * 6.0);
+    reduce(BI_NQ, ntile);
+    hipLaunchKernelGGL((k_bi_scalar<C, 2>), dim3(ntile), sb, 0, s, a, it, maxit, tol2);
+    hipLaunchKernelGGL((k_bi_sweep_c<C>), dim3(a.nrb, ntile), dim3(256), 0, s, a);
+    reduce(1, ntile);
+    hipLaunchKernelGGL((k_bi_scalar<C, 3>), dim3(ntile), sb, 0, s, a, it, maxit, tol2);
+    hipLaunchKernelGGL(k_bi_compact, dim3(1), dim3(256), 0, s, sys.ncol, (const BiCol*)sys.col, sys.tiles, d_buf);
+    prof_end(tok, s, K_BICG, 0.0, cols * nb * 8.0);
     if (hipGetLastError() != hipSuccess) return -2;
-    // rebuild the tile list from the column states
-    hipLaunchKernelGGL(k_bi_gather, dim3(gs), dim3(256), 0, s, sys.ncol, (const BiCol*)sys.col, 0, d_buf);
-    MF_HIP_CHECK(hipMemcpyAsync(h_buf, d_buf, sys.ncol * sizeof(int), hipMemcpyDeviceToHost, s));
-    MF_HIP_CHECK(hipStreamSynchronize(s));
-    ntile = 0;
-    for (int tix = 0; tix < ntile_all; ++tix) {
-      bool any = false;
-      for (int c = tix * BI_TILE; c < std::min(sys.ncol, (tix + 1) * BI_TILE); ++c)
-        any = any || h_buf[c] == ST_ACTIVE;
-      if (any) tl[ntile++] = tix;
+    if (it % CHECK == 0 || it == maxit) {
+      MF_HIP_CHECK(hipMemcpyAsync(h_buf, d_buf, sizeof(int), hipMemcpyDeviceToHost, s));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      ntile = h_buf[0];
     }
-    if (ntile > 0)
-      MF_HIP_CHECK(hipMemcpyAsync(d_tiles, tl.data(), ntile * sizeof(int), hipMemcpyHostToDevice, s));
   }
   its.assign(sys.ncol, 0);
-  hipLaunchKernelGGL(k_bi_gather, dim3(gs), dim3(256), 0, s, sys.ncol, (const BiCol*)sys.col, 1, d_buf);
-  MF_HIP_CHECK(hipMemcpyAsync(h_buf, d_buf, sys.ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_bi_its, dim3(gs), dim3(256), 0, s, sys.ncol, (const BiCol*)sys.col, d_buf + 64);
+  MF_HIP_CHECK(hipMemcpyAsync(h_buf + 64, d_buf + 64, sys.ncol * sizeof(int), hipMemcpyDeviceToHost, s));
   MF_HIP_CHECK(hipStreamSynchronize(s));
-  for (int c = 0; c < sys.ncol; ++c) its[c] = h_buf[c];
+  for (int c = 0; c < sys.ncol; ++c) its[c] = h_buf[64 + c];
   return 0;
 }
 
@@ -636,10 +757,10 @@ __global__ void k_bi_rhs(int64_t total, int m0, const double* __restrict__ rhs, 
   bh[e] = (R)(rhs[e] * cs[e % m0]);
 }
 
-// Q[i][q] (+)= [resid: rho_q X[i][q]] + us_q * sum_j 2 Re(cf[j][q] x[i][j m0 + q]) over the
-// nodes j0 .. j0 + nj - 1 held in the batch (x columns start at node j0)
+// Q[i][q] (+)= [resid: rho_q X[i][q]] + us_q * sum_j 2 Re(cf[j][q] x(i, j m0 + q)) over the
+// nodes j0 .. j0 + nj - 1 held in the batch (x tile-major, columns start at node j0)
 template <typename C>
-__global__ void k_bi_accumulate(int64_t total, int m0, int nj, int j0, const C* __restrict__ x, int ncol,
+__global__ void k_bi_accumulate(int64_t total, int64_t n, int m0, int nj, int j0, const C* __restrict__ x,
                                 const c64* __restrict__ cf, const double* __restrict__ rho,
                                 const double* __restrict__ us, const double* __restrict__ X,
                                 double* __restrict__ Q, int mode) {
@@ -649,7 +770,8 @@ __global__ void k_bi_accumulate(int64_t total, int m0, int nj, int j0, const C* 
   const int q = (int)(e % m0);
   double acc = 0.0;
   for (int j = 0; j < nj; ++j) {
-    const c64 d = convert<c64, C>(x[i * ncol + (int64_t)j * m0 + q]);
+    const int64_t c = (int64_t)j * m0 + q;
+    const c64 d = convert<c64, C>(x[((c >> 6) * n + i) * 64 + (c & 63)]);
     const c64 p = cf[(int64_t)(j0 + j) * m0 + q] * d;
     acc += 2.0 * p.re;
   }
@@ -668,11 +790,11 @@ int bi_rhs(hipStream_t s, int64_t n, int m0, const double* rhs, const double* cs
 }
 
 template <typename C>
-int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, int ncol, const c64* cf,
-                  const double* rho, const double* us, const double* X, double* Q, int mode) {
+int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, const c64* cf, const double* rho,
+                  const double* us, const double* X, double* Q, int mode) {
   const int64_t total = n * (int64_t)m0;
-  hipLaunchKernelGGL((k_bi_accumulate<C>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, m0, nj,
-                     j0, x, ncol, cf, rho, us, X, Q, mode);
+  hipLaunchKernelGGL((k_bi_accumulate<C>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, n, m0,
+                     nj, j0, x, cf, rho, us, X, Q, mode);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -684,9 +806,9 @@ template int bicgstab_batched<c32>(hipStream_t, const BiSys<c32>&, int, double, 
 template int bicgstab_batched<c64>(hipStream_t, const BiSys<c64>&, int, double, std::vector<int>&, int*, int*);
 template int bi_rhs<float>(hipStream_t, int64_t, int, const double*, const double*, float*);
 template int bi_rhs<double>(hipStream_t, int64_t, int, const double*, const double*, double*);
-template int bi_accumulate<c32>(hipStream_t, int64_t, int, int, int, const c32*, int, const c64*, const double*,
+template int bi_accumulate<c32>(hipStream_t, int64_t, int, int, int, const c32*, const c64*, const double*,
                                 const double*, const double*, double*, int);
-template int bi_accumulate<c64>(hipStream_t, int64_t, int, int, int, const c64*, int, const c64*, const double*,
+template int bi_accumulate<c64>(hipStream_t, int64_t, int, int, int, const c64*, const c64*, const double*,
                                 const double*, const double*, double*, int);
 
 }  // namespace mf
