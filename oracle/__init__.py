@@ -19,6 +19,7 @@ Readings taken where the guide is silent are listed in each module header.
 from .contour import half_contour, rational_filter, gauss_legendre_rule
 from .splitmix import splitmix64_uniform, initial_subspace
 from .ifeast import bicgstab_block, feast_csr, ifeastinit
+from . import adjoint
 from .feast import (
     feastinit,
     expand_uplo,
@@ -41,4 +42,5 @@ __all__ = [
     "bicgstab_block",
     "feast_csr",
     "ifeastinit",
+    "adjoint",
 ]

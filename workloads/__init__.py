@@ -15,6 +15,7 @@ from .generators import (
     column_major,
     laplacian_3d_csr,
     laplacian_3d_eigs,
+    differentiation_problem,
 )
 
 __all__ = [
@@ -27,4 +28,5 @@ __all__ = [
     "column_major",
     "laplacian_3d_csr",
     "laplacian_3d_eigs",
+    "differentiation_problem",
 ]

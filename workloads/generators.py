@@ -140,3 +140,14 @@ def laplacian_3d_eigs(nx, ny=None, nz=None):
     ey = 2.0 - 2.0 * np.cos(np.arange(1, ny + 1) * np.pi / (ny + 1))
     ez = 2.0 - 2.0 * np.cos(np.arange(1, nz + 1) * np.pi / (nz + 1))
     return np.sort((ex[:, None, None] + ey[None, :, None] + ez[None, None, :]).ravel())
+
+
+def differentiation_problem(n=4096, seed=3):
+    """Tridiagonal A = tridiag(-1, 2 + v, -1) and loss weights for the differentiation
+    workload.  Draw order from default_rng(seed): v ~ U[0, 1]^n, then c ~ N(0, 1)^n.
+    Returns (v, c, A dense float64)."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(0.0, 1.0, n)
+    c = rng.standard_normal(n)
+    A = 2.0 * np.eye(n) + np.diag(v) - np.eye(n, k=1) - np.eye(n, k=-1)
+    return v, c, A
