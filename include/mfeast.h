@@ -137,6 +137,30 @@ int mfeast_dcsrgv(mfeast_handle h, char uplo, int64_t n, const double* a, const 
                   double* E, double* X, int64_t ldx, int32_t* M, double* res, double* epsout,
                   int32_t* loop, const double* zne, const double* wne);
 
+/* Gradient of a loss on the eigenpairs found in the interval with respect to A, for a real
+ * symmetric standard problem (B = I): the backward pass of mfeast_dsygv.  For the M pairs
+ * (E_i, x_i) and loss gradients gE_i = dL/dE_i, gX_i = dL/dx_i, with a loss invariant
+ * under rotations inside span(X) (e.g. sum E_i + sum_i x_i^T C x_i, C symmetric),
+ * first-order perturbation of the eigenproblem (Section 1.1's eigenpairs as functions of
+ * A) gives dL/dA = X diag(gE) X^T + (X Y^T + Y X^T)/2, where y_i solves the deflated
+ * shifted system (E_i I - A + sigma X X^T) y_i = (I - X X^T) gX_i (sigma = 1 + 2 spread
+ * of E).  The M shifted matrices are factored by the batched LU of the contour solves
+ * and every solve is refined with FP64 residuals.
+ *  A          device, n x n column-major (lda >= n), full storage
+ *  M          number of pairs (1 <= M <= n)
+ *  E          device, M doubles; X device n x M column-major (ldx >= n), orthonormal
+ *  gE         device, M doubles, or NULL (zero); gX device n x M (ldgx >= n) or NULL (zero)
+ *  precision  0: complex FP64 factorization, one refinement step;
+ *             1: complex FP32 factorization, up to four FP64 refinement steps
+ *  gA         device, n x n column-major (ldga >= n), or NULL
+ *  gdiag      device, n doubles: the diagonal of dL/dA (dL/dv for A + diag(v)), or NULL
+ * At least one of gA, gdiag.  Returns 0, 202 (n), 201 (M), -(100+i) for argument i,
+ * -2 (zero pivot, non-finite value, HIP error), -900. */
+int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, int64_t lda, int32_t M,
+                       const double* E, const double* X, int64_t ldx, const double* gE,
+                       const double* gX, int64_t ldgx, int32_t precision, double* gA,
+                       int64_t ldga, double* gdiag);
+
 /* Timing of the last call in seconds, host clock around synchronized phases (the
  * guide's "FEAST-RCI timing" split, Section 2.4): out[0] factorization, [1] contour
  * solves, [2] Rayleigh-Ritz products and residuals, [3] reduced eigensolver, [4] other,

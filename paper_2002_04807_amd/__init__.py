@@ -22,8 +22,8 @@ _lib_error = None
 
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
-    "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_get_timing",
-    "mfeast_get_profile",
+    "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
+    "mfeast_get_timing", "mfeast_get_profile",
 )
 
 
@@ -60,6 +60,9 @@ def _load():
                                   c_i32p, ctypes.c_double, ctypes.c_double, c_i32p, c_dp, c_dp, i64, c_i32p, c_dp,
                                   ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
     lib.mfeast_dcsrgv.restype = c_int
+    lib.mfeast_dsy_adjoint.argtypes = [c_vp, i64, c_dp, i64, ctypes.c_int32, c_dp, c_dp, i64, c_dp, c_dp, i64,
+                                       ctypes.c_int32, c_dp, i64, c_dp]
+    lib.mfeast_dsy_adjoint.restype = c_int
     lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_get_timing.restype = c_int
     lib.mfeast_get_profile.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
@@ -218,6 +221,14 @@ def mfeast_dcsrgv(h, uplo, n, a, ia, ja, index_base, b, ib, jb, fpm, emin, emax,
             "loop": int(loop_c.value), "fpm60": int(fpm_a[59])}
 
 
+def mfeast_dsy_adjoint(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, precision, gA, ldga, gdiag):
+    """C mfeast_dsy_adjoint; returns info."""
+    hp = h.ptr if isinstance(h, Handle) else h
+    return int(_load().mfeast_dsy_adjoint(hp, int(n), _ptr(A), int(lda), int(M), _ptr(E), _ptr(X), int(ldx),
+                                          _ptr(gE), _ptr(gX), int(ldgx), int(precision), _ptr(gA), int(ldga),
+                                          _ptr(gdiag)))
+
+
 def colmajor(t):
     """(tensor, leading dimension) with element (i, j) at i + j*ld; copies only if needed."""
     if t.dim() != 2:
@@ -305,3 +316,60 @@ def feast_csr(csr, emin, emax, m0, fpm=None, B=None, X0=None, uplo="F", index_ba
     m = out["m0"]
     out.update(E=E[:m], X=X[:, :m], res=res[:m], fpm=fpm)
     return out
+
+
+def _feast_eigh_class():
+    import torch
+
+    class FeastEigh(torch.autograd.Function):
+        """Eigenpairs of a real symmetric A inside [emin, emax] (mfeast_dsygv) with a
+        backward pass by mfeast_dsy_adjoint (dL/dA for losses invariant under rotations
+        inside the span of the returned eigenvectors)."""
+
+        @staticmethod
+        def forward(ctx, A, emin, emax, m0, fpm, precision, handle):
+            out = feast(A, None, emin, emax, m0, fpm=fpm, handle=handle)
+            if out["info"] != 0:
+                raise RuntimeError("mfeast_dsygv returned info %d" % out["info"])
+            M = out["M"]
+            E = out["E"][:M].clone()
+            X = out["X"][:, :M].clone()
+            ctx.save_for_backward(A, E, X)
+            ctx.precision = precision
+            ctx.handle = handle
+            return E, X
+
+        @staticmethod
+        def backward(ctx, gE, gX):
+            A, E, X = ctx.saved_tensors
+            n, M = X.shape
+            Ac, lda = colmajor(A.to(torch.float64))
+            Xc, ldx = colmajor(X)
+            gEc = None if gE is None else gE.to(torch.float64).contiguous()
+            gXc, ldgx = (None, n) if gX is None else colmajor(gX.to(torch.float64))
+            gA = torch.empty((n, n), dtype=torch.float64, device=A.device)
+            own = ctx.handle is None
+            h = Handle(A.device.index or 0) if own else ctx.handle
+            try:
+                info = mfeast_dsy_adjoint(h, n, Ac, lda, M, E, Xc, ldx, gEc, gXc, ldgx, ctx.precision, gA, n, None)
+            finally:
+                if own:
+                    h.close()
+            if info != 0:
+                raise RuntimeError("mfeast_dsy_adjoint returned info %d" % info)
+            return gA, None, None, None, None, None, None
+
+    return FeastEigh
+
+
+_FEAST_EIGH = None
+
+
+def feast_eigh(A, emin, emax, m0, fpm=None, precision=1, handle=None):
+    """(E, X) of the eigenpairs of real symmetric A in [emin, emax], differentiable:
+    the backward pass returns dL/dA through mfeast_dsy_adjoint (precision 0: FP64
+    factorizations, 1: FP32 factorizations with FP64 refinement)."""
+    global _FEAST_EIGH
+    if _FEAST_EIGH is None:
+        _FEAST_EIGH = _feast_eigh_class()
+    return _FEAST_EIGH.apply(A, emin, emax, m0, fpm, precision, handle)

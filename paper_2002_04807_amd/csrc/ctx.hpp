@@ -1,0 +1,103 @@
+// Handle of the C interface: device, stream and the workspace that grows on demand
+// and is reused by later calls (internal header shared by the entry points).
+#pragma once
+
+#include <chrono>
+#include <cstddef>
+
+#include "kernels.hpp"
+
+namespace mf {
+
+enum Slot {
+  S_LU, S_DINV, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
+  S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
+  S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
+  S_SMALL, S_PART, S_FLAG,
+  S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF, S_LUWORK,
+  S_ADJ_AD, S_ADJ_XR, S_ADJ_R, S_ADJ_Y, S_ADJ_T, S_ADJ_SMALL,
+  S_NSLOTS
+};
+
+#define MF_TRY(...)                      \
+  do {                                   \
+    if ((__VA_ARGS__) != 0) return -2;   \
+  } while (0)
+
+template <typename T> inline int gemmT(hipStream_t s, bool am, bool cj, const GemmArgs& g) {
+  return gemm<double, is_cplx<T>::value>(s, am, cj, g, 1);
+}
+
+// row-major product C(MxN) = op(A) * B, helper for the internal blocks
+template <typename T>
+inline int rm_gemm(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, bool a_mcontig, bool conj_a,
+                   const T* B, int64_t ldb, T* C, int64_t ldc, double alpha = 1.0, double beta = 0.0) {
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.a_bs = 0;
+  g.B = B; g.ldb = ldb; g.b_bs = 0;
+  g.C = C; g.ldc = ldc; g.c_bs = 0;
+  g.alpha = alpha; g.beta = beta;
+  const int tok = prof_begin(s);
+  const int rc = gemmT<T>(s, a_mcontig, conj_a, g);
+  const double fl = (is_cplx<T>::value ? 8.0 : 2.0) * (double)M * N * K;
+  prof_end(tok, s, K_RR_GEMM, fl, (double)sizeof(T) * ((double)M * K + (double)K * N + 2.0 * M * N));
+  return rc;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0;
+  void start() { t0 = std::chrono::steady_clock::now(); }
+  double stop() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+}  // namespace mf
+
+struct mfeast_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* buf[mf::S_NSLOTS] = {};
+  size_t cap[mf::S_NSLOTS] = {};
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  int* pinned_i = nullptr;  // column states of the batched BiCGSTAB
+  size_t pinned_i_cap = 0;
+  mf::CsrWork csrA, csrB;
+  double timing[8] = {};
+  double prof[mf::K_NCLASS * 4] = {};
+
+  void* ws(mf::Slot s, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (cap[s] < bytes) {
+      if (buf[s]) (void)hipFree(buf[s]);
+      buf[s] = nullptr;
+      cap[s] = 0;
+      if (hipMalloc(&buf[s], bytes) != hipSuccess) return nullptr;
+      cap[s] = bytes;
+    }
+    return buf[s];
+  }
+  char* host(size_t bytes) {
+    if (pinned_cap < bytes) {
+      if (pinned) (void)hipHostFree(pinned);
+      pinned = nullptr;
+      pinned_cap = 0;
+      if (hipHostMalloc((void**)&pinned, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      pinned_cap = bytes;
+    }
+    return pinned;
+  }
+  int* host_ints(size_t count) {
+    const size_t bytes = count * sizeof(int) + 64;
+    if (pinned_i_cap < bytes) {
+      if (pinned_i) (void)hipHostFree(pinned_i);
+      pinned_i = nullptr;
+      pinned_i_cap = 0;
+      if (hipHostMalloc((void**)&pinned_i, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      pinned_i_cap = bytes;
+    }
+    return pinned_i;
+  }
+};

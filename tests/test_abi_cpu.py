@@ -139,3 +139,23 @@ def test_csr_argument_checks_in_table_order():
     assert _csr_call(handle=h, X=None) == -116
     assert _csr_call(handle=h, ldx=3) == -117
     assert _csr_call(handle=h, res=None) == -119
+
+
+def test_adjoint_argument_checks():
+    d = np.zeros(16)
+    f = mf.mfeast_dsy_adjoint
+    h = ctypes.c_void_p(1)
+    # (h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, precision, gA, ldga, gdiag)
+    assert f(None, 0, d, 1, 1, d, d, 1, None, None, 1, 0, d, 1, None) == 202
+    assert f(None, 4, d, 4, 0, d, d, 4, None, None, 4, 0, d, 4, None) == 201
+    assert f(None, 4, d, 4, 5, d, d, 4, None, None, 4, 0, d, 4, None) == 201
+    assert f(None, 4, d, 4, 2, d, d, 4, None, None, 4, 0, d, 4, None) == -101
+    assert f(h, 4, None, 4, 2, d, d, 4, None, None, 4, 0, d, 4, None) == -103
+    assert f(h, 4, d, 3, 2, d, d, 4, None, None, 4, 0, d, 4, None) == -104
+    assert f(h, 4, d, 4, 2, None, d, 4, None, None, 4, 0, d, 4, None) == -106
+    assert f(h, 4, d, 4, 2, d, None, 4, None, None, 4, 0, d, 4, None) == -107
+    assert f(h, 4, d, 4, 2, d, d, 3, None, None, 4, 0, d, 4, None) == -108
+    assert f(h, 4, d, 4, 2, d, d, 4, None, d, 3, 0, d, 4, None) == -111
+    assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 2, d, 4, None) == -112
+    assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 0, None, 4, None) == -113
+    assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 0, d, 3, None) == -114
