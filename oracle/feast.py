@@ -27,13 +27,18 @@ What is computed follows the guide:
 
 Readings where the guide is silent (each is listed with its reason in the
 design notes of the repository):
-  R-spur    a Ritz pair counts as found (one of the M) when its value lies in
-            [Emin, Emax] and its relative residual is below SPURIOUS_RES = 0.1.
-            Ritz values inside the interval with a larger residual are spurious:
-            their Ritz vectors mix eigenvectors from both sides of the interval
-            whose filter weights are small, so they carry no eigenvalue; they are
-            listed with the outside values.  M, the trace and the convergence test
-            use the found pairs only.
+  R-spur    a Ritz pair (theta, x), x B-normalized, counts as found (one of the M)
+            when theta lies in [Emin, Emax], its relative residual is below
+            SPURIOUS_RES = 0.1, and its absolute residual r = ||A x - theta B x||
+            satisfies r^2 < (Emax - theta)(theta - Emin).  Ritz values inside the
+            interval that fail either test are spurious: their Ritz vectors mix
+            eigenvectors from both sides of the interval whose filter weights are
+            small and nearly equal, so they carry no eigenvalue; they are listed with
+            the outside values.  The second test is the Kato-Temple bound: a unit
+            vector orthogonal to every eigenvector in the interval (the interval then
+            holds no eigenvalue of A restricted to its complement) has
+            r^2 >= (Emax - theta)(theta - Emin), so a pair below it is not such a
+            mixture.  M, the trace and the convergence test use the found pairs only.
   R-order   E(1:M) are the found Ritz values ascending, followed by all others
             ascending; X columns follow E.
   R-closed  the interval is closed.
@@ -143,13 +148,15 @@ def expand_uplo(A, uplo):
     return T + T.conj().T + D
 
 
-def _ordered(lam, res, emin, emax):
+def _ordered(lam, res, emin, emax, rabs):
     """Permutation: found pairs (R-spur) ascending, then all others ascending.
 
+    rabs: absolute residual norms ||A x - lambda B x|| of the B-normalized Ritz vectors.
     Returns (perm, M, n_inside) with n_inside the count of Ritz values in the
     interval regardless of their residual."""
     inside = (lam >= emin) & (lam <= emax)
-    found = inside & (res < SPURIOUS_RES)
+    certified = rabs ** 2 < (emax - lam) * (lam - emin)
+    found = inside & (res < SPURIOUS_RES) & certified
     idx_in = np.where(found)[0]
     idx_out = np.where(~found)[0]
     idx_in = idx_in[np.argsort(lam[idx_in], kind="stable")]
@@ -314,8 +321,9 @@ def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form=
         X = Q @ W
         BX = X if B is None else B @ X
         R = A @ X - BX * lam[None, :]
-        res = np.linalg.norm(R, axis=0) / (alpha * np.linalg.norm(BX, axis=0))
-        perm, M, n_inside = _ordered(lam, res, emin, emax)
+        rabs = np.linalg.norm(R, axis=0)
+        res = rabs / (alpha * np.linalg.norm(BX, axis=0))
+        perm, M, n_inside = _ordered(lam, res, emin, emax, rabs)
         lam_sorted, X, res = lam[perm], X[:, perm], res[perm]
         trace = float(np.sum(lam_sorted[:M]))
         epsout = 1.0 if trace_prev is None else abs(trace - trace_prev) / alpha
