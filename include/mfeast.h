@@ -103,6 +103,22 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
                  double* epsout, int32_t* loop, const double* zne, const double* wne);
 
+/* Many independent dense real symmetric problems in one call (the first of the three
+ * levels of parallelism of Section 1.1, independent search intervals or problems): the
+ * arguments of mfeast_dsygv as arrays over nprob problems.  n, lda, ldb, ldx, emin, emax,
+ * m0 (in/out), M, epsout, loop, info are host arrays of nprob entries; A, B, E, X, res are
+ * host arrays of nprob device pointers (B may be NULL for B = I everywhere, or hold NULL
+ * entries); fpm (64 entries) is shared.  Problems are spread, largest first, over
+ * concurrent streams of the handle's device (one host worker thread each, 8 by default,
+ * MFEAST_BATCH_STREAMS in the environment overrides); cooperative kernels are not used in
+ * this mode.  info[p] is problem p's code; the return value is the most negative code,
+ * else the largest positive one, else 0, or -(100+i) for an invalid argument i. */
+int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const double* const* A,
+                         const int64_t* lda, const double* const* B, const int64_t* ldb,
+                         const int32_t* fpm, const double* emin, const double* emax, int32_t* m0,
+                         double* const* E, double* const* X, const int64_t* ldx, int32_t* M,
+                         double* const* res, double* epsout, int32_t* loop, int32_t* info);
+
 /* IFEAST defaults (Section 3.5, Table tab_fpm "using IFEAST"): mfeast_init, then
  * fpm(2)=4 nodes, fpm(4)=50 loops, fpm(16)=1 trapezoidal rule, fpm(18)=100 (circle).
  * BiCGSTAB accuracy fpm(45)=1 (10^-1) and fpm(46)=40 iterations are the common defaults. */

@@ -23,7 +23,7 @@ _lib_error = None
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
     "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
-    "mfeast_get_timing", "mfeast_get_profile",
+    "mfeast_dsygv_batched", "mfeast_get_timing", "mfeast_get_profile",
 )
 
 
@@ -63,6 +63,12 @@ def _load():
     lib.mfeast_dsy_adjoint.argtypes = [c_vp, i64, c_dp, i64, ctypes.c_int32, c_dp, c_dp, i64, c_dp, c_dp, i64,
                                        ctypes.c_int32, c_dp, i64, c_dp]
     lib.mfeast_dsy_adjoint.restype = c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dpp = ctypes.POINTER(ctypes.c_double)
+    lib.mfeast_dsygv_batched.argtypes = [c_vp, ctypes.c_int32, i64p, pp, i64p, pp, i64p, c_i32p, dpp, dpp, c_i32p,
+                                         pp, pp, i64p, c_i32p, pp, dpp, c_i32p, c_i32p]
+    lib.mfeast_dsygv_batched.restype = c_int
     lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_get_timing.restype = c_int
     lib.mfeast_get_profile.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
@@ -373,3 +379,51 @@ def feast_eigh(A, emin, emax, m0, fpm=None, precision=1, handle=None):
     if _FEAST_EIGH is None:
         _FEAST_EIGH = _feast_eigh_class()
     return _FEAST_EIGH.apply(A, emin, emax, m0, fpm, precision, handle)
+
+
+def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None):
+    """Many independent real symmetric problems (B = I) in one mfeast_dsygv_batched call.
+
+    As: list of float64 GPU tensors (n_p x n_p, symmetric).  Returns a list of dicts
+    (info, M, m0, loop, epsout, E, X, res) and the batch wall time (handle timing)."""
+    import torch
+    lib = _load()
+    P = len(As)
+    fpm = mfeast_init() if fpm is None else _fpm_array(fpm).copy()
+    Ac = [colmajor(A.to(torch.float64)) for A in As]
+    n = np.array([A.shape[0] for A in As], dtype=np.int64)
+    lda = np.array([ld for _, ld in Ac], dtype=np.int64)
+    m0 = np.array(m0s, dtype=np.int32)
+    dev = As[0].device
+    E = [torch.zeros(int(m), dtype=torch.float64, device=dev) for m in m0]
+    X = [torch.zeros((int(m), int(k)), dtype=torch.float64, device=dev).mT for m, k in zip(m0, n)]
+    R = [torch.zeros(int(m), dtype=torch.float64, device=dev) for m in m0]
+    ptrs = lambda ts: (ctypes.c_void_p * P)(*[t.data_ptr() for t in ts])  # noqa: E731
+    Ap = (ctypes.c_void_p * P)(*[a.data_ptr() for a, _ in Ac])
+    emin = np.ascontiguousarray(np.asarray(emins, dtype=np.float64))
+    emax = np.ascontiguousarray(np.asarray(emaxs, dtype=np.float64))
+    M = np.zeros(P, dtype=np.int32)
+    eps = np.zeros(P, dtype=np.float64)
+    loop = np.zeros(P, dtype=np.int32)
+    info = np.zeros(P, dtype=np.int32)
+    own = handle is None
+    h = Handle(dev.index or 0) if own else handle
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    try:
+        ret = lib.mfeast_dsygv_batched(
+            h.ptr, P, n.ctypes.data_as(i64p), Ap, lda.ctypes.data_as(i64p), None, None,
+            fpm.ctypes.data_as(i32p), emin.ctypes.data_as(dp), emax.ctypes.data_as(dp), m0.ctypes.data_as(i32p),
+            ptrs(E), ptrs(X), n.ctypes.data_as(i64p), M.ctypes.data_as(i32p), ptrs(R), eps.ctypes.data_as(dp),
+            loop.ctypes.data_as(i32p), info.ctypes.data_as(i32p))
+        seconds = h.timing()[5]
+    finally:
+        if own:
+            h.close()
+    out = []
+    for p in range(P):
+        m = int(m0[p])
+        out.append({"info": int(info[p]), "M": int(M[p]), "m0": m, "loop": int(loop[p]), "epsout": float(eps[p]),
+                    "E": E[p][:m], "X": X[p][:, :m], "res": R[p][:m]})
+    return int(ret), out, seconds

@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <cstddef>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -65,6 +66,8 @@ struct mfeast_ctx {
   int* pinned_i = nullptr;  // column states of the batched BiCGSTAB
   size_t pinned_i_cap = 0;
   mf::CsrWork csrA, csrB;
+  std::vector<mfeast_ctx*> workers;  // batched calls: one handle and stream per worker thread
+  bool owns_stream = false;
   double timing[8] = {};
   double prof[mf::K_NCLASS * 4] = {};
 

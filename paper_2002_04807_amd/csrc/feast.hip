@@ -21,7 +21,10 @@
 //             (fpm(6)=1) or epsout < 10^-fpm(3) (fpm(6)=0); fpm(4) bounds the loops.
 // The host only sequences launches and reads back O(M0) scalars per iteration.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstdlib>
+#include <thread>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -36,9 +39,10 @@ using namespace mf;
 namespace {
 
 constexpr double RANK_TOL = 1.0e-13;  // kept directions of the equilibrated overlap: s > RANK_TOL * max s
-// Ritz values inside the interval with a relative residual at or above this bound are
-// spurious (mixtures of weakly filtered eigenvectors from outside the interval) and
-// are not counted among the M eigenvalues found.
+// Ritz values inside the interval with a relative residual at or above this bound, or
+// above the Kato-Temple bound of the interval (see the found-pair test), are spurious
+// (mixtures of weakly filtered eigenvectors from both sides of the interval) and are not
+// counted among the M eigenvalues found.
 constexpr double SPURIOUS_RES = 1.0e-1;
 
 }  // namespace
@@ -662,10 +666,17 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     int n_inside = 0;
     M = 0;
     double maxres = 0.0, trace = 0.0;
+    // found: inside, relative residual below SPURIOUS_RES, and r^2 < (emax - l)(l - emin)
+    // (Kato-Temple: a B-unit vector orthogonal to the eigenvectors in the interval has
+    // r^2 >= (emax - l)(l - emin), so a pair below the bound is no mixture of outside ones)
+    auto found = [&](int i) {
+      const double l = lam_cur[i];
+      return l >= emin && l <= emax && res_h[i] < SPURIOUS_RES && h_rn[i] < (emax - l) * (l - emin);
+    };
     for (int i = 0; i < m0; ++i) {
       const bool in = lam_cur[i] >= emin && lam_cur[i] <= emax;
       n_inside += in ? 1 : 0;
-      if (in && res_h[i] < SPURIOUS_RES) {
+      if (found(i)) {
         ++M;
         maxres = std::max(maxres, res_h[i]);
         trace += lam_cur[i];
@@ -673,7 +684,6 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     }
     order.resize(m0);
     for (int i = 0; i < m0; ++i) order[i] = i;
-    auto found = [&](int i) { return lam_cur[i] >= emin && lam_cur[i] <= emax && res_h[i] < SPURIOUS_RES; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       const bool fa = found(a), fb = found(b);
       if (fa != fb) return fa;
@@ -866,6 +876,12 @@ int mfeast_destroy(mfeast_handle h) {
   if (h == nullptr) return -101;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
+  for (mfeast_ctx* w : h->workers) {
+    if (w->owns_stream && w->stream) (void)hipStreamDestroy(w->stream);
+    w->stream = nullptr;
+    (void)mfeast_destroy(w);
+  }
+  h->workers.clear();
   for (int i = 0; i < S_NSLOTS; ++i)
     if (h->buf[i]) (void)hipFree(h->buf[i]);
   h->csrA.release();
@@ -943,6 +959,84 @@ int mfeast_dcsrgv(mfeast_handle h, char uplo, int64_t n, const double* a, const 
                   double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
   return csr_entry(h, uplo, n, a, ia, ja, index_base, b, ib, jb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout,
                    loop, zne, wne);
+}
+
+int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const double* const* A,
+                         const int64_t* lda, const double* const* B, const int64_t* ldb, const int32_t* fpm,
+                         const double* emin, const double* emax, int32_t* m0, double* const* E, double* const* X,
+                         const int64_t* ldx, int32_t* M, double* const* res, double* epsout, int32_t* loop,
+                         int32_t* info) {
+  if (h == nullptr) return -101;
+  if (nprob < 1) return -102;
+  if (n == nullptr) return -103;
+  if (A == nullptr) return -104;
+  if (lda == nullptr) return -105;
+  if (B != nullptr && ldb == nullptr) return -107;
+  if (fpm == nullptr) return -108;
+  if (emin == nullptr) return -109;
+  if (emax == nullptr) return -110;
+  if (m0 == nullptr) return -111;
+  if (E == nullptr) return -112;
+  if (X == nullptr) return -113;
+  if (ldx == nullptr) return -114;
+  if (M == nullptr) return -115;
+  if (res == nullptr) return -116;
+  if (epsout == nullptr) return -117;
+  if (loop == nullptr) return -118;
+  if (info == nullptr) return -119;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  Timer total;
+  total.start();
+  // inputs may still be in flight on the caller's stream
+  MF_HIP_CHECK(hipStreamSynchronize(h->stream));
+  static const int env_streams = getenv("MFEAST_BATCH_STREAMS") ? atoi(getenv("MFEAST_BATCH_STREAMS")) : 8;
+  const int nw = std::max(1, std::min<int>(nprob, env_streams));
+  while ((int)h->workers.size() < nw) {
+    mfeast_ctx* w = new mfeast_ctx();
+    w->device = h->device;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return -2;
+    }
+    w->owns_stream = true;
+    h->workers.push_back(w);
+  }
+  // largest problems first
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+  std::atomic<int> next(0);
+  auto work = [&](mfeast_ctx* w) {
+    (void)hipSetDevice(w->device);
+    set_coop_allowed(false);
+    for (;;) {
+      const int t = next.fetch_add(1);
+      if (t >= nprob) break;
+      const int p = order[t];
+      int32_t f[64];
+      for (int i = 0; i < 64; ++i) f[i] = fpm[i];
+      f[51] = 0;
+      const double* Bp = B ? B[p] : nullptr;
+      const int64_t ldbp = B ? ldb[p] : n[p];
+      info[p] = dense_entry<double>(w, 'F', n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p], X[p],
+                                    ldx[p], &M[p], res[p], &epsout[p], &loop[p], nullptr, nullptr);
+    }
+    (void)hipStreamSynchronize(w->stream);
+    set_coop_allowed(true);
+  };
+  std::vector<std::thread> threads;
+  for (int i = 1; i < nw; ++i) threads.emplace_back(work, h->workers[i]);
+  work(h->workers[0]);
+  for (std::thread& t : threads) t.join();
+  int worst = 0;
+  for (int p = 0; p < nprob; ++p)
+    if (info[p] < 0 && (worst >= 0 || info[p] < worst)) worst = info[p];
+  if (worst == 0)
+    for (int p = 0; p < nprob; ++p) worst = std::max(worst, (int)info[p]);
+  for (int i = 0; i < 8; ++i) h->timing[i] = 0.0;
+  h->timing[5] = total.stop();
+  h->timing[6] = (double)nprob;
+  return worst;
 }
 
 void mfeast_init_ifeast(int32_t* fpm) {

@@ -762,8 +762,8 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
   for (int64_t k = 0; k < n; k += LU_NB) {
     const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
     int tok = prof_begin(s);
-    const bool coop = launch_panel_coop<C, QPR>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info,
-                                               bars + (k / LU_NB) * ne, pwork);
+    const bool coop = coop_allowed() && launch_panel_coop<C, QPR>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info,
+                                                                 bars + (k / LU_NB) * ne, pwork);
     if (!coop && launch_panel<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
     // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
     prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);

@@ -11,10 +11,12 @@ struct Rec {
   double flops, bytes;
   int a, b;  // event indices
 };
-bool g_on = false;
-std::vector<hipEvent_t> g_events;
-int g_next = 0;
-std::vector<Rec> g_recs;
+// per host thread: calls on different handles may run from different threads
+thread_local bool g_on = false;
+thread_local std::vector<hipEvent_t> g_events;
+thread_local int g_next = 0;
+thread_local std::vector<Rec> g_recs;
+thread_local bool g_coop = true;
 
 int take_event() {
   if (g_next >= (int)g_events.size()) {
@@ -27,6 +29,9 @@ int take_event() {
 }  // namespace
 
 bool prof_on() { return g_on; }
+
+bool coop_allowed() { return g_coop; }
+void set_coop_allowed(bool on) { g_coop = on; }
 
 void prof_enable(bool on) {
   g_on = on;

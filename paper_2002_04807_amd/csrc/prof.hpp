@@ -23,6 +23,11 @@ enum KClass {
 };
 
 bool prof_on();
+// cooperative (grid-resident) kernels may be used by this host thread; off while several
+// streams of one process run FEAST calls concurrently, where two partly resident grids
+// could wait on each other
+bool coop_allowed();
+void set_coop_allowed(bool on);
 void prof_enable(bool on);
 // begin/end around one or more launches on stream s
 int prof_begin(hipStream_t s);

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, T* Ha, T* Hb, T* V, doubl
 template <typename T>
 int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work) {
   if (m > 2 * JAC_MAXPAIR) return -2;
-  if (m > 64) {
+  if (m > 64 || !coop_allowed()) {
     // block Jacobi (eig.hip); work holds the round's unitaries, then a counter
     T* ubuf = reinterpret_cast<T*>(work);
     int* counter = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + block_jacobi_work_bytes(m, sizeof(T)) - 64);
