@@ -130,14 +130,13 @@ int adjoint_run(mfeast_ctx* h, int64_t n, const double* A, int64_t lda, int M, c
     int* linfo = (int*)h->ws(S_INFO, (size_t)M * 4 + 64);
     c64* zdev = (c64*)h->ws(S_Z, (size_t)M * sizeof(c64));
     C* Wf = (C*)h->ws(S_WF, (size_t)M * nm * sizeof(C));
-    void* luwork = h->ws(S_LUWORK, lu_work_bytes<C>(n, M));
-    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || !luwork) return -2;
+    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf) return -2;
     std::vector<c64> z(M);
     for (int i = 0; i < M; ++i) z[i] = c64(e[i], 0.0);
     MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), M * sizeof(c64), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemsetAsync(linfo, 0, M * 4, s));
     MF_TRY(shift_form<double, C>(s, n, Ad, n, nullptr, 0, zdev, M, LU, perm));
-    MF_TRY(lu_factor<C>(s, n, M, LU, ipiv, perm, pinv, linfo, Dinv, luwork));
+    MF_TRY(lu_factor<C>(s, n, M, LU, ipiv, perm, pinv, linfo, Dinv));
     std::vector<int> hinfo(M);
     MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, M * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));

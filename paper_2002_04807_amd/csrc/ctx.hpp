@@ -15,7 +15,7 @@ enum Slot {
   S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
   S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
   S_SMALL, S_PART, S_FLAG,
-  S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF, S_LUWORK,
+  S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF,
   S_ADJ_AD, S_ADJ_XR, S_ADJ_R, S_ADJ_Y, S_ADJ_T, S_ADJ_SMALL,
   S_NSLOTS
 };

@@ -179,7 +179,6 @@ struct DenseOp : Operator<T> {
   C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr;
   int *ipiv = nullptr, *perm = nullptr, *pinv = nullptr, *linfo = nullptr;
   c64* zdev = nullptr;
-  void* luwork = nullptr;
 
   DenseOp(mfeast_ctx* h_, char uplo_, int64_t n_, const T* A_, int64_t lda_, const T* B_, int64_t ldb_,
           const std::vector<c64>& z_, int m0_)
@@ -200,8 +199,7 @@ struct DenseOp : Operator<T> {
     zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
     Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0max * szC);
     Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0max * szC) : nullptr;
-    luwork = h->ws(S_LUWORK, lu_work_bytes<C>(n, ne));
-    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !luwork) return -2;
+    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc)) return -2;
     // full storage if a triangle was given
     Af = A;
     ldaf = lda;
@@ -228,7 +226,7 @@ struct DenseOp : Operator<T> {
       MF_TRY(shift_form<T, C>(s, n, Af, ldaf, Bf, ldbf, zdev, ne, LU, perm));
       prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((B ? 2.0 : 1.0) * sizeof(T) + ne * sizeof(C)));
     }
-    MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv, luwork));
+    MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
     std::vector<int> hinfo(ne);
     MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));

@@ -12,6 +12,12 @@
 // flop count is 8 per complex multiply-add as in the algorithmic count.
 // FP32 tiles use v_mfma_f32_16x16x4f32, FP64 tiles v_mfma_f64_16x16x4f64; the
 // output lane layouts of the two differ and were checked on the device.
+// Products with few output tiles and a long K (the Gram matrices Q^H B Q, n x M0 by
+// n x M0) split K over several workgroups per tile: each writes its partial tile to a
+// scratch buffer and a second kernel adds the partials in split order (deterministic).
+#include <algorithm>
+#include <map>
+
 #include "kernels.hpp"
 
 namespace mf {
@@ -37,8 +43,8 @@ template <> struct mfma_op<double> {
 };
 
 template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
-          int TAG>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+          int TAG, bool SPLIT = false>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
   constexpr int NT = 256;
@@ -57,11 +63,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int wn0 = (wave >> 1) * WN;
   const int m0 = blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
-  const int64_t bz = blockIdx.z;
+  const int64_t bz = SPLIT ? blockIdx.z / nsplit : blockIdx.z;
+  const int sp = SPLIT ? (int)(blockIdx.z % nsplit) : 0;
   const R* A = static_cast<const R*>(g.A) + bz * g.a_bs * ES;
   const R* B = static_cast<const R*>(g.B) + bz * g.b_bs * ES;
   R* C = static_cast<R*>(g.C) + bz * g.c_bs * ES;
-  const int M = g.M, N = g.N, K = g.K;
+  const int M = g.M, N = g.N;
+  const int kfirst = SPLIT ? sp * kchunk : 0;
+  const int K = SPLIT ? min(g.K, kfirst + kchunk) : g.K;
 
   acc_t acc[ES][FM][FN];
 #pragma unroll
@@ -72,13 +81,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int j = 0; j < FN; ++j)
         for (int r = 0; r < 4; ++r) acc[e][i][j][r] = R(0);
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  // C tile for the beta term, loaded before the K loop so its latency overlaps the products
+  R cpre[ES][FM][FN][4];
+  const bool use_c = !SPLIT && g.beta != 0.0;
+  if (use_c) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm0 + i * 16 + M_::row(lane, r);
+          const int gj = n0 + wn0 + j * 16 + (lane & 15);
+          R vr = R(0), vi = R(0);
+          if (gi < M && gj < N) {
+            const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
+            vr = C[off];
+            if constexpr (CPLX) vi = C[off + 1];
+          }
+          cpre[0][i][j][r] = vr;
+          if constexpr (CPLX) cpre[ES - 1][i][j][r] = vi;
+        }
+  }
+
+  for (int k0 = kfirst; k0 < K; k0 += BK) {
     __syncthreads();
     // ---- A tile -> LDS [k][m]
     if constexpr (A_MCONTIG) {
       constexpr int KS = NT / BM;
 #pragma unroll
-      for (int kk = tid / BM; kk < BK; kk += KS) {
+      for (int it = 0; it < BK / KS; ++it) {
+        const int kk = tid / BM + it * KS;
         const int i = tid % BM;
         const int gi = m0 + i, gk = k0 + kk;
         R re = R(0), im = R(0);
@@ -93,7 +126,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     } else {
       constexpr int IS = NT / BK;
 #pragma unroll
-      for (int i = tid / BK; i < BM; i += IS) {
+      for (int it = 0; it < BM / IS; ++it) {
+        const int i = tid / BK + it * IS;
         const int kk = tid % BK;
         const int gi = m0 + i, gk = k0 + kk;
         R re = R(0), im = R(0);
@@ -110,7 +144,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     if constexpr (!B_KCONTIG) {
       constexpr int KS = NT / BN;
 #pragma unroll
-      for (int kk = tid / BN; kk < BK; kk += KS) {
+      for (int it = 0; it < BK / KS; ++it) {
+        const int kk = tid / BN + it * KS;
         const int j = tid % BN;
         const int gj = n0 + j, gk = k0 + kk;
         R re = R(0), im = R(0);
@@ -125,7 +160,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     } else {
       constexpr int JS = NT / BK;
 #pragma unroll
-      for (int j = tid / BK; j < BN; j += JS) {
+      for (int it = 0; it < BN / JS; ++it) {
+        const int j = tid / BK + it * JS;
         const int kk = tid % BK;
         const int gj = n0 + j, gk = k0 + kk;
         R re = R(0), im = R(0);
@@ -169,6 +205,25 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
   }
 
+  if constexpr (SPLIT) {
+    // partial tile of split sp: part[(bz * nsplit + sp)][M][N] (interleaved complex)
+    R* P = part + (bz * nsplit + sp) * (int64_t)M * N * ES;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm0 + i * 16 + M_::row(lane, r);
+          const int gj = n0 + wn0 + j * 16 + (lane & 15);
+          if (gi < M && gj < N) {
+            const int64_t off = ((int64_t)gi * N + gj) * ES;
+            P[off] = acc[0][i][j][r];
+            if constexpr (CPLX) P[off + 1] = acc[ES - 1][i][j][r];
+          }
+        }
+    return;
+  }
   // ---- epilogue: C = alpha * acc + beta * C
   const R alpha = (R)g.alpha, beta = (R)g.beta;
 #pragma unroll
@@ -183,9 +238,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
           R vr = alpha * acc[0][i][j][r];
           R vi = CPLX ? alpha * acc[ES - 1][i][j][r] : R(0);
-          if (g.beta != 0.0) {
-            vr += beta * C[off];
-            if constexpr (CPLX) vi += beta * C[off + 1];
+          if (use_c) {
+            vr += beta * cpre[0][i][j][r];
+            if constexpr (CPLX) vi += beta * cpre[ES - 1][i][j][r];
           }
           C[off] = vr;
           if constexpr (CPLX) C[off + 1] = vi;
@@ -193,21 +248,109 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
-static void launch(const GemmArgs& g, int batch, hipStream_t s) {
-  constexpr int BM = 64, BN = 64, BK = 16;
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
-  if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
-    if (g.tag == 1) {
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 1>), grid, dim3(256), 0, s, g);
-      return;
+// C = alpha * sum of the partial tiles (in split order) + beta * C
+template <typename R, bool CPLX>
+__global__ void k_gemm_splitk_sum(GemmArgs g, int nsplit, const R* __restrict__ part) {
+  constexpr int ES = CPLX ? 2 : 1;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  const int64_t bz = blockIdx.y;
+  if (e >= mn) return;
+  const int gi = (int)(e / g.N), gj = (int)(e % g.N);
+  R sr = R(0), si = R(0);
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const R* P = part + (bz * nsplit + sp) * mn * ES;
+    sr += P[e * ES];
+    if constexpr (CPLX) si += P[e * ES + 1];
+  }
+  R* C = static_cast<R*>(g.C) + bz * g.c_bs * ES;
+  const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
+  R vr = (R)g.alpha * sr, vi = (R)g.alpha * si;
+  if (g.beta != 0.0) {
+    vr += (R)g.beta * C[off];
+    if constexpr (CPLX) vi += (R)g.beta * C[off + 1];
+  }
+  C[off] = vr;
+  if constexpr (CPLX) C[off + 1] = vi;
+}
+
+// scratch for split-K partials: grown on demand, one buffer per host thread and device,
+// released when the thread ends
+namespace {
+struct SplitScratch {
+  std::map<int, std::pair<void*, size_t>> bufs;
+  ~SplitScratch() {
+    for (auto& kv : bufs)
+      if (kv.second.first) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(kv.second.first);
+      }
+  }
+};
+}  // namespace
+
+static void* splitk_scratch(size_t bytes) {
+  thread_local SplitScratch scratch;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto& b = scratch.bufs[dev];
+  if (b.second < bytes) {
+    if (b.first) {
+      (void)hipDeviceSynchronize();  // earlier launches may still read the old buffer
+      (void)hipFree(b.first);
     }
-    if (g.tag == 2) {
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 2>), grid, dim3(256), 0, s, g);
+    b.first = nullptr;
+    b.second = 0;
+    if (hipMalloc(&b.first, bytes) != hipSuccess) return nullptr;
+    b.second = bytes;
+  }
+  return b.first;
+}
+
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BK>
+static void launch_bk(const GemmArgs& g, int batch, hipStream_t s) {
+  constexpr int BM = 64, BN = 64;
+  const int tiles = ((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * batch;
+  // few output tiles and a long K: split K so that about 512 workgroups run
+  if (tiles < 128 && g.K >= 1024) {
+    int nsplit = std::min(std::max(2, 512 / tiles), g.K / 256);
+    nsplit = std::min(nsplit, 64);
+    const int kchunk = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
+    nsplit = (g.K + kchunk - 1) / kchunk;
+    constexpr int ES = CPLX ? 2 : 1;
+    R* part = static_cast<R*>(splitk_scratch((size_t)nsplit * batch * g.M * g.N * ES * sizeof(R)));
+    if (part != nullptr && nsplit > 1) {
+      dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch * nsplit);
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true>), grid, dim3(256), 0, s, g, nsplit,
+                         kchunk, part);
+      const int64_t mn = (int64_t)g.M * g.N;
+      hipLaunchKernelGGL((k_gemm_splitk_sum<R, CPLX>), dim3((unsigned)((mn + 255) / 256), batch), dim3(256), 0, s, g,
+                         nsplit, (const R*)part);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0>), grid, dim3(256), 0, s, g);
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
+  if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
+    if (g.tag == 1) {
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 1>), grid, dim3(256), 0, s, g, 1, 0,
+                         (R*)nullptr);
+      return;
+    }
+    if (g.tag == 2) {
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 2>), grid, dim3(256), 0, s, g, 1, 0,
+                         (R*)nullptr);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0>), grid, dim3(256), 0, s, g, 1, 0, (R*)nullptr);
+}
+
+// 16-deep K slabs for every shape (deeper slabs for the K = 64 updates measured slower:
+// fewer resident workgroups outweigh the saved load round trips)
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
+static void launch(const GemmArgs& g, int batch, hipStream_t s) {
+  launch_bk<R, CPLX, AM, CJ, BK_, CJB, 16>(g, batch, s);
 }
 
 template <typename R, bool CPLX, bool AM, bool CJ>

@@ -54,12 +54,9 @@ int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, in
 // perm_inv, a per-node info flag (>0: first zero pivot + 1), and Dinv: per node and per
 // diagonal block, the inverses of the unit-lower and of the upper LU_NB x LU_NB blocks
 // (row-major, 2 * LU_NB^2 entries per block, ceil(n / LU_NB) blocks per node).
-// work: lu_work_bytes<C>(n, ne) bytes of device scratch (panel pivot exchange, barriers).
 template <typename C>
 int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int* perm_inv, int* info,
-              C* Dinv, void* work);
-template <typename C>
-size_t lu_work_bytes(int64_t n, int ne);
+              C* Dinv);
 
 // ------------------------------------------------------------------ solves
 // Build per-node right-hand sides W_j (row-major n x m, type C) from an FP64 block RHS
