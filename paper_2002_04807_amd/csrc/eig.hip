@@ -69,8 +69,13 @@ __global__ __launch_bounds__(JT) void k_bj_sub(int m, int nbp, int round, const 
   }
   __syncthreads();
   const double abs_floor = 4.440892098500626e-16 * s_dmax + 1e-300;
+  // rotations of an element above this size keep the outer sweeps going; once a whole
+  // sweep rotates only smaller ones the remaining off-diagonal mass is second order in
+  // them (quadratic convergence), so no confirming sweep is needed
+  const double big_floor = 1.0e-10 * s_dmax;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int sweep_cnt = 0;
+    int big_cnt = 0;
     for (int r = 0; r < JS - 1; ++r) {
       // rotation of each local pair from the current 2 x 2 diagonal blocks
       if (tid < JS / 2) {
@@ -97,12 +102,16 @@ __global__ __launch_bounds__(JT) void k_bj_sub(int m, int nbp, int round, const 
         rs[tid] = sg;
         rp[tid] = p;
         rq[tid] = q;
-        rf[tid] = f;
+        rf[tid] = f ? (ab > big_floor ? 2 : 1) : 0;
       }
       __syncthreads();
-      int cnt = 0;
-      for (int i = 0; i < JS / 2; ++i) cnt += rf[i];
+      int cnt = 0, bigc = 0;
+      for (int i = 0; i < JS / 2; ++i) {
+        cnt += rf[i] ? 1 : 0;
+        bigc += rf[i] == 2 ? 1 : 0;
+      }
       sweep_cnt += cnt;  // uniform: every thread read the same flags
+      big_cnt += bigc;
       if (cnt == 0) {
         __syncthreads();  // the flags are rewritten next round
         continue;
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(JT) void k_bj_sub(int m, int nbp, int round, const 
       }
       __syncthreads();
     }
-    if (tid == 0) s_total += sweep_cnt;
+    if (tid == 0) s_total += big_cnt;
     if (sweep_cnt == 0) break;  // uniform
   }
   __syncthreads();
