@@ -417,7 +417,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   T* GZ = (T*)h->ws(S_GZ, sq);
   T* W = (T*)h->ws(S_W, sq);
   // small device arrays, packed
-  const size_t nsmall = (size_t)m0 * 12 + (size_t)ne * m0 * 4 + 64;
+  const size_t nsmall = (size_t)m0 * 13 + (size_t)ne * m0 * 4 + 64;
   double* small = (double*)h->ws(S_SMALL, nsmall * sizeof(double));
   const int nchunk = (int)((n + 255) / 256);
   double* part = (double*)h->ws(S_PART, (size_t)nchunk * m0 * 2 * sizeof(double));
@@ -441,6 +441,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   c64* d_cf = (c64*)(small + 12 * m0);               // ne*m0
   c64* d_cc = d_cf + (size_t)ne * m0;                // ne*m0
   int* d_sweeps = (int*)(small + 12 * m0 + 4 * (size_t)ne * m0);
+  int* d_pi = (int*)(small + 12 * m0 + 4 * (size_t)ne * m0 + 64);  // m0 ints
   // pinned host staging (same packing)
   double* h_absmax = (double*)hp;
   double* h_cs = h_absmax + m0;
@@ -456,6 +457,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   c64* h_cf = (c64*)(h_absmax + 12 * m0);
   c64* h_cc = h_cf + (size_t)ne * m0;
   int* h_flag = (int*)(h_absmax + 12 * m0 + 4 * (size_t)ne * m0);
+  int* h_pi = (int*)(h_absmax + 12 * m0 + 4 * (size_t)ne * m0 + 64);
 
   // ---------------- factor (dense) or convert (sparse)
   ph.start();
@@ -472,8 +474,11 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
 
   std::vector<double> lam_cur;
   std::vector<int> order;
-  int last_sweeps = 0;
+  int last_sweeps = 0, last_osweeps = 0, last_mi = 0;
   double last_dev = 0.0;
+  // found flags of the current Ritz pairs (eigensolver order), for the deflation above
+  std::vector<char> found_prev;
+  static const bool deflate = !(getenv("MFEAST_DEFLATE") && atoi(getenv("MFEAST_DEFLATE")) == 0);
   double trace_prev = 0.0;
   int info = 0;
   int M = 0;
@@ -561,6 +566,23 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       BQp = BQ;
     }
     MF_TRY(rm_gemm<T>(s, m0, m0, (int)n, Q, m0, true, true, BQp, m0, Sm, m0));
+    // Order of pass 1: the columns of the pairs found last iteration first.  Those columns
+    // are B-orthogonal to all others up to their residual, while the filtered columns of
+    // the far outside pairs carry components along them that are large after scaling;
+    // with the found columns first, Cholesky removes those components from the others
+    // and never mixes the others into the found ones.
+    int nfound = 0;
+    const bool permuted = deflate && resid && (int)found_prev.size() == m0;
+    if (permuted) {
+      for (int i = 0; i < m0; ++i)
+        if (found_prev[i]) h_pi[nfound++] = i;
+      int a = nfound;
+      for (int i = 0; i < m0; ++i)
+        if (!found_prev[i]) h_pi[a++] = i;
+      MF_HIP_CHECK(hipMemcpyAsync(d_pi, h_pi, m0 * sizeof(int), hipMemcpyHostToDevice, s));
+      MF_TRY(sym_permute<T>(s, m0, Sm, d_pi, Cm));
+      MF_TRY(copy_block<T>(s, m0, m0, Cm, m0, Sm, m0, false));
+    }
     MF_HIP_CHECK(hipMemsetAsync(dflag, 0, 16, s));
     MF_TRY(gram_equilibrate<T>(s, m0, Sm, Tm, d_dscale, dflag));
     // pass 1: Cholesky of the equilibrated overlap with column dropping (d_perm = keep mask)
@@ -576,13 +598,19 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     if (kk == 0) { info = -3; break; }
     MF_HIP_CHECK(hipMemcpyAsync(d_idx, h_idx, kk * sizeof(int), hipMemcpyHostToDevice, s));
     MF_TRY(build_h1<T>(s, m0, kk, Hw, d_dscale, d_idx, G));
+    // H1 is in the permuted row order: its row i belongs to column h_pi[i] of Q
+    T* H1 = G;
+    if (permuted) {
+      MF_TRY(scatter_rows<T>(s, m0, kk, G, d_pi, Cm));
+      H1 = Cm;
+    }
     // Q1 = Q H1, A Q1 = (A Q) H1, B Q1 = (B Q) H1  (no new product with A or B)
     T* Q1 = R;
     T* AQ1 = AX;
     T* BQ1 = hasB ? BX : Q1;
-    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, G, kk, Q1, kk));
-    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, G, kk, AQ1, kk));
-    if (hasB) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQp, m0, false, false, G, kk, BQ1, kk));
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, Q, m0, false, false, H1, kk, Q1, kk));
+    MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, AQ, m0, false, false, H1, kk, AQ1, kk));
+    if (hasB) MF_TRY(rm_gemm<T>(s, (int)n, kk, m0, BQp, m0, false, false, H1, kk, BQ1, kk));
     // pass 2: S1 = Q1^H B Q1 = I + F, T1 = Q1^H A Q1
     MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, BQ1, kk, Sm, kk));
     MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, AQ1, kk, Tm, kk));
@@ -622,16 +650,48 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       MF_HIP_CHECK(hipMemcpyAsync(d_gs, h_gs, kk2 * sizeof(double), hipMemcpyHostToDevice, s));
       MF_TRY(gather_scale_cols<T>(s, kk, kk2, Zm, kk, d_idx, d_gs, V, kk2));
     }
+    // Deflation of the pairs found last iteration: with them first in pass 1 (above) and
+    // Newton-Schulz leaving G2 close to I, the leading block of C belongs to them, is
+    // diagonal up to their residuals and is coupled to the rest only to the same order;
+    // only the trailing block of the others needs the full eigensolver.
+    int mi = 0;
+    if (permuted && dev_f < 0.5) {
+      while (mi < kk && h_idx[mi] < nfound) ++mi;
+      if (mi < 1 || kk2 - mi < 2) mi = 0;
+    }
     // C = G2^H T1 G2, eigenpairs of C
     MF_TRY(rm_gemm<T>(s, kk, kk2, kk, Tm, kk, false, false, G2, kk2, TG, kk2));
     MF_TRY(rm_gemm<T>(s, kk2, kk2, kk, G2, kk2, true, true, TG, kk2, Cm, kk2));
     MF_TRY(hermitian_part<T>(s, kk2, Cm));
-    MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
+    int osweeps = 0;
+    if (mi > 0) {
+      // C = [C_II C_IO; C_OI C_OO]: V_OO diagonalizes C_OO; C <- diag(I, V_OO)^H C diag(I, V_OO);
+      // the full eigensolver on that matrix then only removes the small coupling, and the
+      // eigenvectors of the original C are diag(I, V_OO) times its.
+      const int mo = kk2 - mi;
+      T* Coo = Sm;
+      T* Voo = Tm;
+      double* ev_oo = d_gs;
+      MF_TRY(copy_block<T>(s, mo, mo, Cm + (int64_t)mi * kk2 + mi, kk2, Coo, mo, false));
+      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw));
+      MF_TRY(rm_gemm<T>(s, mi, mo, mo, Cm + mi, kk2, false, false, Voo, mo, TG, mo));
+      MF_TRY(copy_block<T>(s, mi, mo, TG, mo, Cm + mi, kk2, false));
+      MF_TRY(copy_block<T>(s, mi, mo, TG, mo, Cm + (int64_t)mi * kk2, kk2, true));
+      MF_TRY(set_diag_block<T>(s, mo, ev_oo, Cm + (int64_t)mi * kk2 + mi, kk2));
+      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
+      MF_TRY(rm_gemm<T>(s, mo, kk2, mo, Voo, mo, false, false, Zm + (int64_t)mi * kk2, kk2, TG, kk2));
+      MF_TRY(copy_block<T>(s, mo, kk2, TG, kk2, Zm + (int64_t)mi * kk2, kk2, false));
+      MF_HIP_CHECK(hipMemcpyAsync(&osweeps, d_sweeps + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    } else {
+      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw));
+    }
     int sweeps = 0;
     MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk2 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipMemcpyAsync(&sweeps, d_sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     last_sweeps = sweeps;
+    last_osweeps = osweeps;
+    last_mi = mi;
     last_dev = dev_f;
     t_eig += ph.stop();
     ph.start();
@@ -671,10 +731,12 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       const double l = lam_cur[i];
       return l >= emin && l <= emax && res_h[i] < SPURIOUS_RES && h_rn[i] < (emax - l) * (l - emin);
     };
+    found_prev.assign(m0, 0);
     for (int i = 0; i < m0; ++i) {
       const bool in = lam_cur[i] >= emin && lam_cur[i] <= emax;
       n_inside += in ? 1 : 0;
       if (found(i)) {
+        found_prev[i] = 1;
         ++M;
         maxres = std::max(maxres, res_h[i]);
         trace += lam_cur[i];
@@ -697,8 +759,10 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     if (f(1) != 0) {
       // runtime comments (fpm(1)): iteration, #eigenvalues, trace, relative trace change,
       // largest residual of the found pairs, subspace size, spurious count
-      fprintf(stderr, "%3d %6d  %24.16E  %24.16E  %24.16E  m0=%d spurious=%d |S1-I|=%.1e sweeps=%d\n", k, M,
-              trace, eo, maxres, m0, n_inside - M, last_dev, last_sweeps);
+      fprintf(stderr, "%3d %6d  %24.16E  %24.16E  %24.16E  m0=%d spurious=%d |S1-I|=%.1e sweeps=%d",
+              k, M, trace, eo, maxres, m0, n_inside - M, last_dev, last_sweeps);
+      if (last_mi > 0) fprintf(stderr, " (deflated %d, %d sweeps on the other %d)", last_mi, last_osweeps, m0 - last_mi);
+      fprintf(stderr, "\n");
     }
     const bool conv = M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps));
     if (conv) { info = 0; break; }

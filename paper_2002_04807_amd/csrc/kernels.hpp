@@ -103,6 +103,16 @@ template <typename T>
 int scale_rows_permute_cols(hipStream_t s, int rows, int k, const T* GZ, int ldgz, const double* d,
                             const int* perm, T* W, int ldw);
 template <typename T>
+int copy_block(hipStream_t s, int rows, int cols, const T* src, int64_t lds, T* dst, int64_t ldd, bool conj_t);
+// dst[i][j] = src[p[i]][p[j]] (m x m)
+template <typename T>
+int sym_permute(hipStream_t s, int m, const T* src, const int* p, T* dst);
+// dst[p[r]][:] = src[r][:] (rows x cols, leading dimension cols)
+template <typename T>
+int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, T* dst);
+template <typename T>
+int set_diag_block(hipStream_t s, int m, const double* d, T* dst, int64_t ldd);
+template <typename T>
 int residual_norms(hipStream_t s, int64_t n, int m, const T* AX, const T* BX, const double* lam, T* R,
                    double* rnorm2, double* bnorm2, double* partial);
 template <typename T>

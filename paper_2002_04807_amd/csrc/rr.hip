@@ -416,6 +416,77 @@ int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t l
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// ---------------------------------------------------------------------------
+// Block copies for the deflated reduced eigensolve.  dst (rows x cols) = src, or with
+// conj_t, dst (cols x rows) = src^H.
+template <typename T>
+__global__ void k_copy_block(int rows, int cols, const T* __restrict__ src, int64_t lds, T* __restrict__ dst,
+                             int64_t ldd, int conj_t) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= cols) return;
+  const T v = src[(int64_t)r * lds + c];
+  if (conj_t) dst[(int64_t)c * ldd + r] = conj(v);
+  else dst[(int64_t)r * ldd + c] = v;
+}
+
+template <typename T>
+int copy_block(hipStream_t s, int rows, int cols, const T* src, int64_t lds, T* dst, int64_t ldd, bool conj_t) {
+  if (rows <= 0 || cols <= 0) return 0;
+  hipLaunchKernelGGL((k_copy_block<T>), dim3((cols + 255) / 256, rows), dim3(256), 0, s, rows, cols, src, lds, dst,
+                     ldd, conj_t ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// dst[i][j] = src[p[i]][p[j]] (m x m, both with leading dimension m)
+template <typename T>
+__global__ void k_sym_permute(int m, const T* __restrict__ src, const int* __restrict__ p, T* __restrict__ dst) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= m) return;
+  dst[(int64_t)i * m + j] = src[(int64_t)p[i] * m + p[j]];
+}
+
+template <typename T>
+int sym_permute(hipStream_t s, int m, const T* src, const int* p, T* dst) {
+  if (m <= 0) return 0;
+  hipLaunchKernelGGL((k_sym_permute<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, src, p, dst);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// dst[p[r]][:] = src[r][:] (rows x cols, leading dimension cols)
+template <typename T>
+__global__ void k_scatter_rows(int rows, int cols, const T* __restrict__ src, const int* __restrict__ p,
+                               T* __restrict__ dst) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= cols) return;
+  dst[(int64_t)p[r] * cols + c] = src[(int64_t)r * cols + c];
+}
+
+template <typename T>
+int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, T* dst) {
+  if (rows <= 0 || cols <= 0) return 0;
+  hipLaunchKernelGGL((k_scatter_rows<T>), dim3((cols + 255) / 256, rows), dim3(256), 0, s, rows, cols, src, p, dst);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// dst (m x m, ld ldd) = diag(d)
+template <typename T>
+__global__ void k_set_diag_block(int m, const double* __restrict__ d, T* __restrict__ dst, int64_t ldd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= m) return;
+  dst[(int64_t)r * ldd + c] = (r == c) ? T(d[r]) : T(0.0);
+}
+
+template <typename T>
+int set_diag_block(hipStream_t s, int m, const double* d, T* dst, int64_t ldd) {
+  if (m <= 0) return 0;
+  hipLaunchKernelGGL((k_set_diag_block<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, d, dst, ldd);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 #define MF_RR_INST(T)                                                                                          \
   template int col_absmax<T>(hipStream_t, int64_t, int, const T*, int64_t, double*);                           \
   template int gram_equilibrate<T>(hipStream_t, int, T*, T*, double*, int*);                                   \
@@ -428,7 +499,11 @@ int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t l
   template int copy_rm_to_cm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t, const int*);        \
   template int copy_cm_to_rm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t);                    \
   template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);                            \
-  template int hermitian_part<T>(hipStream_t, int, T*);
+  template int hermitian_part<T>(hipStream_t, int, T*);                                                     \
+  template int copy_block<T>(hipStream_t, int, int, const T*, int64_t, T*, int64_t, bool);                     \
+  template int set_diag_block<T>(hipStream_t, int, const double*, T*, int64_t);                                \
+  template int sym_permute<T>(hipStream_t, int, const T*, const int*, T*);                                    \
+  template int scatter_rows<T>(hipStream_t, int, int, const T*, const int*, T*);
 
 MF_RR_INST(double)
 MF_RR_INST(c64)
