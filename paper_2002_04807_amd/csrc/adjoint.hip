@@ -130,13 +130,16 @@ int adjoint_run(mfeast_ctx* h, int64_t n, const double* A, int64_t lda, int M, c
     int* linfo = (int*)h->ws(S_INFO, (size_t)M * 4 + 64);
     c64* zdev = (c64*)h->ws(S_Z, (size_t)M * sizeof(c64));
     C* Wf = (C*)h->ws(S_WF, (size_t)M * nm * sizeof(C));
-    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf) return -2;
+    C* Wy = (C*)h->ws(S_WY, (size_t)M * nm * sizeof(C));
+    C* Pinv = (C*)h->ws(S_PANINV, (size_t)M * panel_inverse_entries(n) * sizeof(C));
+    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || !Wy || !Pinv) return -2;
     std::vector<c64> z(M);
     for (int i = 0; i < M; ++i) z[i] = c64(e[i], 0.0);
     MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), M * sizeof(c64), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemsetAsync(linfo, 0, M * 4, s));
     MF_TRY(shift_form<double, C>(s, n, Ad, n, nullptr, 0, zdev, M, LU, perm));
     MF_TRY(lu_factor<C>(s, n, M, LU, ipiv, perm, pinv, linfo, Dinv));
+    MF_TRY(panel_inverses<C>(s, n, M, LU, Dinv, Pinv));
     std::vector<int> hinfo(M);
     MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, M * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -162,7 +165,7 @@ int adjoint_run(mfeast_ctx* h, int64_t n, const double* A, int64_t lda, int M, c
       MF_HIP_CHECK(hipMemcpyAsync(d_cs, h_cs, M * sizeof(double), hipMemcpyHostToDevice, s));
       MF_HIP_CHECK(hipMemcpyAsync(d_us, h_us, M * sizeof(double), hipMemcpyHostToDevice, s));
       MF_TRY(rhs_prepare<double, C>(s, n, M, rhs, M, d_cs, M, perm, Wf, (C*)nullptr));
-      MF_TRY(lu_solve<C>(s, n, M, M, LU, Dinv, Wf, (C*)nullptr));
+      MF_TRY(lu_solve<C>(s, n, M, M, LU, Pinv, Wf, (C*)nullptr, Wy));
       hipLaunchKernelGGL((k_adj_extract<C>), dim3(blocks_for(nm)), dim3(256), 0, s, n, M, (const C*)Wf,
                          (const double*)d_us, Y, step > 0 ? 1 : 0);
       if (step < refine) {

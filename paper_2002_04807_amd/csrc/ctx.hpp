@@ -11,7 +11,7 @@
 namespace mf {
 
 enum Slot {
-  S_LU, S_DINV, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
+  S_LU, S_DINV, S_PANINV, S_WY, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
   S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
   S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
   S_SMALL, S_PART, S_FLAG,

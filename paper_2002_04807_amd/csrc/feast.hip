@@ -176,7 +176,7 @@ struct DenseOp : Operator<T> {
   const T* Af = nullptr;
   const T* Bf = nullptr;
   int64_t ldaf = 0, ldbf = 0;
-  C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr;
+  C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr, *Wy = nullptr, *Pinv = nullptr;
   int *ipiv = nullptr, *perm = nullptr, *pinv = nullptr, *linfo = nullptr;
   c64* zdev = nullptr;
 
@@ -199,7 +199,9 @@ struct DenseOp : Operator<T> {
     zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
     Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0max * szC);
     Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0max * szC) : nullptr;
-    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc)) return -2;
+    Wy = (C*)h->ws(S_WY, (size_t)ne * n * m0max * szC);
+    Pinv = (C*)h->ws(S_PANINV, (size_t)ne * panel_inverse_entries(n) * szC);
+    if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Wy || !Pinv) return -2;
     // full storage if a triangle was given
     Af = A;
     ldaf = lda;
@@ -227,6 +229,11 @@ struct DenseOp : Operator<T> {
       prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((B ? 2.0 : 1.0) * sizeof(T) + ne * sizeof(C)));
     }
     MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
+    {
+      const int tok = prof_begin(s);
+      MF_TRY(panel_inverses<C>(s, n, ne, LU, Dinv, Pinv));
+      prof_end(tok, s, K_SOLVE_GEMM, 0.0, 0.0);
+    }
     std::vector<int> hinfo(ne);
     MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -249,7 +256,7 @@ struct DenseOp : Operator<T> {
     int tok = prof_begin(s);
     MF_TRY(rhs_prepare<T, C>(s, n, m, rhs, m, k.cs, ne, perm, Wf, Wc));
     prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
-    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Dinv, Wf, Wc));
+    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy));
     tok = prof_begin(s);
     MF_TRY(accumulate<T, C>(s, n, m, ne, Wf, Wc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0));
     prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));

@@ -66,11 +66,18 @@ template <typename T, typename C>
 int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const double* colscale,
                 int ne, const int* perm, C* Wf, C* Wc);
 
+// Inverses of the diagonal blocks of L and U over panels of 4 LU_NB rows, formed once
+// per factorization from LU and Dinv; panel_inverse_entries(n) entries of C per node.
+size_t panel_inverse_entries(int64_t n);
+template <typename C>
+int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv, C* Pinv);
+
 // Solve LU_j x = W_j (forward direction; Wf already permuted) and, if Wc != nullptr,
 // (LU_j)^H y = W_j for the conjugate direction (unpermuted on output; perm_inv is
-// applied by the accumulation).  In place, all nodes batched.
+// applied by the accumulation).  Results overwrite Wf / Wc; Y (n x m per node) is
+// scratch.  All nodes batched.
 template <typename C>
-int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv, C* Wf, C* Wc);
+int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y);
 
 // Q = (resid ? X*diag(rho) : 0) + diag-scaled sum over nodes (see accumulate in solve.hip).
 template <typename T, typename C>

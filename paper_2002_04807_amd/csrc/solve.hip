@@ -41,96 +41,201 @@ int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const
 }
 
 // ---------------------------------------------------------------------------
-// Blocked triangular solves.  Block kb covers rows [k, k + nbc), k = kb * LU_NB.
+// Blocked triangular solves, two levels.  The rows are cut into panels of TRSM_PH =
+// TRSM_SUB * LU_NB rows.  Once per factorization the inverse of every panel's
+// diagonal block of L and of U is formed (panel_inverses); a solve then takes two
+// MFMA products per panel: the panel's rows times the inverse, written to the other
+// buffer of a ping-pong pair, and the update of every row beyond the panel, with K =
+// the panel height.
+//
+// The four sweeps differ in direction and in how a coupling block is read:
+//   L  (forward, unit lower)      ascending,  A(i, k) = LU[r_i][c_k]
+//   U  (forward, upper)           descending, A(i, k) = LU[r_i][c_k]
+//   U^H (conjugate node, lower)   ascending,  A(i, k) = conj(LU[c_k][r_i])
+//   L^H (conjugate node, upper)   descending, A(i, k) = conj(LU[c_k][r_i])
+// with r_i the row being updated and c_k a row of the block just solved; the
+// diagonal block uses the upper inverse when DESC != HERM, conjugate-transposed
+// when HERM.
+constexpr int TRSM_SUB = 4;
+constexpr int TRSM_PH = TRSM_SUB * LU_NB;
+
+int64_t panel_count(int64_t n) { return (n + TRSM_PH - 1) / TRSM_PH; }
+size_t panel_inverse_entries(int64_t n) { return (size_t)panel_count(n) * 2 * TRSM_PH * TRSM_PH; }
+
+template <typename C> struct trsm_cols { static constexpr int value = sizeof(C) == 8 ? 32 : 16; };
+
+// In-LDS block solve of one panel, used to form the panel inverses from the
+// identity.  Workgroup (x, y, z): CW right-hand-side columns x, panel pan0 + y, node
+// z.  The panel's rows live at W + z * w_node + y * w_panel (+ p0 * ldw when
+// rows_global), one row every ldw entries; rows past n are treated as zero.
+template <typename C, bool DESC, bool HERM>
+__global__ __launch_bounds__(256) void k_trsm_panel(int64_t n, int ncols, int64_t pan0, const C* __restrict__ LUall,
+                                                    const C* __restrict__ Dinv, int64_t dstride, C* __restrict__ Wall,
+                                                    int64_t ldw, int64_t w_node, int64_t w_panel, int rows_global) {
+  constexpr int CW = trsm_cols<C>::value;
+  constexpr int RR = 4;        // rows per thread: 16 row groups x 4 = LU_NB
+  constexpr int RC = CW / 16;  // columns per thread: 16 column groups
+  __shared__ C Ws[TRSM_PH][CW];
+  __shared__ C As[LU_NB][LU_NB + 1];
+  const int tid = threadIdx.x;
+  const int node = blockIdx.z;
+  const int c0 = blockIdx.x * CW;
+  const int64_t p0 = (pan0 + blockIdx.y) * TRSM_PH;
+  const int nsb = (int)((min<int64_t>(TRSM_PH, n - p0) + LU_NB - 1) / LU_NB);
+  const C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  const C* __restrict__ D = Dinv + (int64_t)node * dstride;
+  C* __restrict__ W = Wall + (int64_t)node * w_node + (int64_t)blockIdx.y * w_panel + (rows_global ? p0 * ldw : 0);
+  const int rows = nsb * LU_NB;
+  for (int e = tid; e < rows * CW; e += 256) {
+    const int r = e / CW, c = e % CW;
+    Ws[r][c] = (p0 + r < n && c0 + c < ncols) ? W[(int64_t)r * ldw + c0 + c] : C(0);
+  }
+  const int tr = (tid >> 4) * RR, tc = (tid & 15) * RC;
+  for (int step = 0; step < nsb; ++step) {
+    const int b = DESC ? nsb - 1 - step : step;
+    const int64_t rb = p0 + (int64_t)b * LU_NB;
+    const C* __restrict__ Di = D + (rb / LU_NB) * 2 * LU_NB * LU_NB + ((DESC != HERM) ? LU_NB * LU_NB : 0);
+    __syncthreads();
+    for (int e = tid; e < LU_NB * LU_NB; e += 256) {
+      const int a = e / LU_NB, c = e % LU_NB;
+      if (HERM) As[c][a] = conj(Di[e]);  // Di[a][c] is op(D)(c, a)
+      else As[a][c] = Di[e];
+    }
+    __syncthreads();
+    C acc[RR][RC];
+    for (int i = 0; i < RR; ++i)
+      for (int j = 0; j < RC; ++j) acc[i][j] = C(0);
+    for (int k = 0; k < LU_NB; ++k) {
+      C a[RR], x[RC];
+      for (int i = 0; i < RR; ++i) a[i] = As[tr + i][k];
+      for (int j = 0; j < RC; ++j) x[j] = Ws[b * LU_NB + k][tc + j];
+      for (int i = 0; i < RR; ++i)
+        for (int j = 0; j < RC; ++j) acc[i][j] = acc[i][j] + a[i] * x[j];
+    }
+    __syncthreads();
+    for (int i = 0; i < RR; ++i)
+      for (int j = 0; j < RC; ++j) Ws[b * LU_NB + tr + i][tc + j] = acc[i][j];
+    for (int s2 = step + 1; s2 < nsb; ++s2) {
+      const int b2 = DESC ? nsb - 1 - s2 : s2;
+      const int64_t rb2 = p0 + (int64_t)b2 * LU_NB;
+      __syncthreads();
+      for (int e = tid; e < LU_NB * LU_NB; e += 256) {
+        const int a = e / LU_NB, c = e % LU_NB;  // c runs along memory
+        if (HERM) {
+          // As[i][k] = conj(LU[rb + k][rb2 + i]) with k = a, i = c
+          As[c][a] = (rb + a < n && rb2 + c < n) ? conj(LU[(rb + a) * n + rb2 + c]) : C(0);
+        } else {
+          As[a][c] = (rb2 + a < n && rb + c < n) ? LU[(rb2 + a) * n + rb + c] : C(0);
+        }
+      }
+      __syncthreads();
+      for (int i = 0; i < RR; ++i)
+        for (int j = 0; j < RC; ++j) acc[i][j] = C(0);
+      for (int k = 0; k < LU_NB; ++k) {
+        C a[RR], x[RC];
+        for (int i = 0; i < RR; ++i) a[i] = As[tr + i][k];
+        for (int j = 0; j < RC; ++j) x[j] = Ws[b * LU_NB + k][tc + j];
+        for (int i = 0; i < RR; ++i)
+          for (int j = 0; j < RC; ++j) acc[i][j] = acc[i][j] + a[i] * x[j];
+      }
+      for (int i = 0; i < RR; ++i)
+        for (int j = 0; j < RC; ++j) Ws[b2 * LU_NB + tr + i][tc + j] = Ws[b2 * LU_NB + tr + i][tc + j] - acc[i][j];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < rows * CW; e += 256) {
+    const int r = e / CW, c = e % CW;
+    if (p0 + r < n && c0 + c < ncols) W[(int64_t)r * ldw + c0 + c] = Ws[r][c];
+  }
+}
+
 template <typename C>
-int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Dinv, C* Wf, C* Wc) {
-  using R = typename real_of<C>::type;
+__global__ void k_identity_panels(int64_t count, C* P) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int64_t w = e % ((int64_t)TRSM_PH * TRSM_PH);
+  P[e] = (w / TRSM_PH == w % TRSM_PH) ? C(1) : C(0);
+}
+
+// Pinv, per node: panel_count(n) x {L_PP^-1, U_PP^-1}, each TRSM_PH x TRSM_PH
+// row-major (a narrower last panel uses the leading block).
+template <typename C>
+int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv, C* Pinv) {
+  constexpr int CW = trsm_cols<C>::value;
+  const int64_t npan = panel_count(n);
   const int64_t nblk = (n + LU_NB - 1) / LU_NB;
-  const int64_t dstride = nblk * 2 * LU_NB * LU_NB;  // Dinv entries per node
+  const int64_t dstride = nblk * 2 * LU_NB * LU_NB;
+  const int64_t per_node = (int64_t)panel_inverse_entries(n);
+  const int64_t count = per_node * ne;
+  hipLaunchKernelGGL((k_identity_panels<C>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, Pinv);
+  const dim3 grid(TRSM_PH / CW, (unsigned)npan, (unsigned)ne);
+  const int64_t sq = (int64_t)TRSM_PH * TRSM_PH;
+  hipLaunchKernelGGL((k_trsm_panel<C, false, false>), grid, dim3(256), 0, s, n, TRSM_PH, (int64_t)0, LU, Dinv,
+                     dstride, Pinv, (int64_t)TRSM_PH, per_node, 2 * sq, 0);
+  hipLaunchKernelGGL((k_trsm_panel<C, true, false>), grid, dim3(256), 0, s, n, TRSM_PH, (int64_t)0, LU, Dinv,
+                     dstride, Pinv + sq, (int64_t)TRSM_PH, per_node, 2 * sq, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename C>
+int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y) {
+  using R = typename real_of<C>::type;
   const int64_t wstride = n * (int64_t)m;
   const int64_t lstride = n * n;
-  auto diag = [&](C* W, int64_t kb, bool upper, bool herm) -> int {
-    const int64_t k = kb * LU_NB;
-    const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
-    GemmArgs g{};
-    g.M = nbc; g.N = m; g.K = nbc;
-    g.A = Dinv + kb * 2 * LU_NB * LU_NB + (upper ? LU_NB * LU_NB : 0);
-    g.lda = LU_NB; g.a_bs = dstride;
-    g.B = W + k * m; g.ldb = m; g.b_bs = wstride;
-    g.C = W + k * m; g.ldc = m; g.c_bs = wstride;
-    g.alpha = 1.0; g.beta = 0.0;
-    // herm: apply the conjugate transpose of the stored inverse (M-contiguous + conj)
-    return gemm<R, true>(s, herm, herm, g, ne);
+  const int64_t npan = panel_count(n);
+  const int64_t sq = (int64_t)TRSM_PH * TRSM_PH;
+  const int64_t pstride = (int64_t)panel_inverse_entries(n);
+  // one sweep: rows of the right-hand sides in `in`, solution to `out` (in is consumed)
+  auto sweep = [&](const C* in0, C* out, bool desc, bool herm) -> int {
+    C* in = const_cast<C*>(in0);
+    for (int64_t q = 0; q < npan; ++q) {
+      const int64_t p = desc ? npan - 1 - q : q;
+      const int64_t p0 = p * TRSM_PH;
+      const int64_t ph = std::min<int64_t>(TRSM_PH, n - p0);
+      // out_P = op(inverse of the diagonal block) in_P
+      GemmArgs d{};
+      d.M = (int)ph; d.N = m; d.K = (int)ph;
+      d.A = Pinv + p * 2 * sq + ((desc != herm) ? sq : 0); d.lda = TRSM_PH; d.a_bs = pstride;
+      d.B = in + p0 * m; d.ldb = m; d.b_bs = wstride;
+      d.C = out + p0 * m; d.ldc = m; d.c_bs = wstride;
+      d.alpha = 1.0; d.beta = 0.0;
+      if (gemm<R, true>(s, herm, herm, d, ne)) return -2;
+      // rows beyond the panel: in_rest -= A out_P
+      GemmArgs g{};
+      g.N = m; g.K = (int)ph;
+      g.B = out + p0 * m; g.ldb = m; g.b_bs = wstride;
+      g.lda = n; g.a_bs = lstride;
+      g.c_bs = wstride; g.ldc = m;
+      g.alpha = -1.0; g.beta = 1.0;
+      if (!desc) {
+        const int64_t rest = n - p0 - ph;
+        if (rest <= 0) continue;
+        g.M = (int)rest;
+        g.C = in + (p0 + ph) * m;
+        // L: rows below the panel, its columns; U^H: M-contiguous view of the panel's U rows
+        g.A = herm ? LU + p0 * n + p0 + ph : LU + (p0 + ph) * n + p0;
+      } else {
+        if (p0 <= 0) continue;
+        g.M = (int)p0;
+        g.C = in;
+        // U: rows above the panel, its columns; L^H: M-contiguous view of the panel's L rows
+        g.A = herm ? LU + p0 * n : LU + p0;
+      }
+      if (gemm<R, true>(s, herm, herm, g, ne)) return -2;
+    }
+    return 0;
   };
   // algorithmic work of one direction: 8 n^2 m flops per node (L and U sweeps)
   const double dir_flops = 8.0 * (double)n * n * m * ne;
   const double dir_bytes = (double)sizeof(C) * ne * ((double)n * n + 2.0 * n * m);
-  // forward direction:  L then U
+  // forward direction: L (W -> Y) then U (Y -> W)
   int tok = prof_begin(s);
-  for (int64_t kb = 0; kb < nblk; ++kb) {
-    const int64_t k = kb * LU_NB;
-    const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
-    if (diag(Wf, kb, false, false)) return -2;
-    const int64_t rest = n - k - nbc;
-    if (rest > 0) {
-      GemmArgs g{};
-      g.M = (int)rest; g.N = m; g.K = nbc;
-      g.A = LU + (k + nbc) * n + k; g.lda = n; g.a_bs = lstride;
-      g.B = Wf + k * m; g.ldb = m; g.b_bs = wstride;
-      g.C = Wf + (k + nbc) * m; g.ldc = m; g.c_bs = wstride;
-      g.alpha = -1.0; g.beta = 1.0;
-      if (gemm<R, true>(s, false, false, g, ne)) return -2;
-    }
-  }
-  for (int64_t kb = nblk - 1; kb >= 0; --kb) {
-    const int64_t k = kb * LU_NB;
-    const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
-    if (diag(Wf, kb, true, false)) return -2;
-    if (k > 0) {
-      GemmArgs g{};
-      g.M = (int)k; g.N = m; g.K = nbc;
-      g.A = LU + k; g.lda = n; g.a_bs = lstride;  // rows [0,k), columns [k, k+nbc)
-      g.B = Wf + k * m; g.ldb = m; g.b_bs = wstride;
-      g.C = Wf; g.ldc = m; g.c_bs = wstride;
-      g.alpha = -1.0; g.beta = 1.0;
-      if (gemm<R, true>(s, false, false, g, ne)) return -2;
-    }
-  }
+  if (sweep(Wf, Y, false, false) || sweep(Y, Wf, true, false)) return -2;
   prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   if (Wc == nullptr) return 0;
   // conjugate-transpose direction: U^H (lower) then L^H (unit upper)
   tok = prof_begin(s);
-  for (int64_t kb = 0; kb < nblk; ++kb) {
-    const int64_t k = kb * LU_NB;
-    const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
-    if (diag(Wc, kb, true, true)) return -2;
-    const int64_t rest = n - k - nbc;
-    if (rest > 0) {
-      GemmArgs g{};
-      g.M = (int)rest; g.N = m; g.K = nbc;
-      // op(A)(i, kk) = conj(U[k + kk][k + nbc + i])  -> M-contiguous view of the U block row
-      g.A = LU + k * n + k + nbc; g.lda = n; g.a_bs = lstride;
-      g.B = Wc + k * m; g.ldb = m; g.b_bs = wstride;
-      g.C = Wc + (k + nbc) * m; g.ldc = m; g.c_bs = wstride;
-      g.alpha = -1.0; g.beta = 1.0;
-      if (gemm<R, true>(s, true, true, g, ne)) return -2;
-    }
-  }
-  for (int64_t kb = nblk - 1; kb >= 0; --kb) {
-    const int64_t k = kb * LU_NB;
-    const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
-    if (diag(Wc, kb, false, true)) return -2;
-    if (k > 0) {
-      GemmArgs g{};
-      g.M = (int)k; g.N = m; g.K = nbc;
-      // op(A)(i, kk) = conj(L[k + kk][i]), i < k
-      g.A = LU + k * n; g.lda = n; g.a_bs = lstride;
-      g.B = Wc + k * m; g.ldb = m; g.b_bs = wstride;
-      g.C = Wc; g.ldc = m; g.c_bs = wstride;
-      g.alpha = -1.0; g.beta = 1.0;
-      if (gemm<R, true>(s, true, true, g, ne)) return -2;
-    }
-  }
+  if (sweep(Wc, Y, false, true) || sweep(Y, Wc, true, true)) return -2;
   prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   return 0;
 }
@@ -191,8 +296,10 @@ template int rhs_prepare<double, c32>(hipStream_t, int64_t, int, const double*, 
 template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c64*, c64*);
 template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*);
 template int rhs_prepare<c64, c64>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c64*, c64*);
-template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*);
-template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*);
+template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*, c32*);
+template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*, c64*);
+template int panel_inverses<c32>(hipStream_t, int64_t, int, const c32*, const c32*, c32*);
+template int panel_inverses<c64>(hipStream_t, int64_t, int, const c64*, const c64*, c64*);
 template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
 template int accumulate<double, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
 template int accumulate<c64, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int);
