@@ -42,16 +42,30 @@ template <> struct mfma_op<double> {
   __device__ static inline int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
+template <typename R> struct vec2;
+template <> struct vec2<float> { using t = float2; };
+template <> struct vec2<double> { using t = double2; };
+
+// One workgroup computes a BM x BN tile of C with four waves in a 2 x 2 grid (each a
+// BM/2 x BN/2 block of 16 x 16 MFMA tiles; 64 x 64 measured best: larger tiles drop
+// occupancy to one wave per SIMD).  K advances in slabs of BK: the next
+// slab's operands are loaded from global memory into registers while the current slab
+// is multiplied out of LDS, so the load latency hides behind the MFMAs.  LDS rows are
+// padded to 16 mod 64 words, which puts the four k rows an MFMA operand read touches
+// on disjoint banks.
 template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
           int TAG, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
+  using V2 = typename vec2<R>::t;
   constexpr int NT = 256;
-  constexpr int PAD = (sizeof(R) == 4) ? 4 : 2;
+  constexpr int PAD = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int ES = CPLX ? 2 : 1;  // reals per element in global memory
+  constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
+  static_assert(NA * NT == BM * BK && NB * NT == BN * BK, "tile");
 
   __shared__ R As[ES][BK][BM + PAD];
   __shared__ R Bs[ES][BK][BN + PAD];
@@ -79,103 +93,82 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j)
+#pragma unroll
         for (int r = 0; r < 4; ++r) acc[e][i][j][r] = R(0);
 
-  // C tile for the beta term, loaded before the K loop so its latency overlaps the products
-  R cpre[ES][FM][FN][4];
-  const bool use_c = !SPLIT && g.beta != 0.0;
-  if (use_c) {
+  // element q of this thread's share of a slab: (row, k) of op(A), (k, col) of B
+  auto a_pos = [&](int q, int& i, int& kk) {
+    const int e = tid + NT * q;
+    if constexpr (A_MCONTIG) { i = e % BM; kk = e / BM; }
+    else { i = e / BK; kk = e % BK; }
+  };
+  auto b_pos = [&](int q, int& kk, int& j) {
+    const int e = tid + NT * q;
+    if constexpr (B_KCONTIG) { kk = e % BK; j = e / BK; }
+    else { j = e % BN; kk = e / BN; }
+  };
+  R ra[NA][ES], rb[NB][ES];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gi = m0 + wm0 + i * 16 + M_::row(lane, r);
-          const int gj = n0 + wn0 + j * 16 + (lane & 15);
-          R vr = R(0), vi = R(0);
-          if (gi < M && gj < N) {
-            const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
-            vr = C[off];
-            if constexpr (CPLX) vi = C[off + 1];
-          }
-          cpre[0][i][j][r] = vr;
-          if constexpr (CPLX) cpre[ES - 1][i][j][r] = vi;
+    for (int q = 0; q < NA; ++q) {
+      int i, kk;
+      a_pos(q, i, kk);
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[q][0] = R(0);
+      if constexpr (CPLX) ra[q][1] = R(0);
+      if (gi < M && gk < K) {
+        const int64_t off = A_MCONTIG ? ((int64_t)gi + (int64_t)gk * g.lda) : ((int64_t)gi * g.lda + gk);
+        if constexpr (CPLX) {
+          const V2 v = *reinterpret_cast<const V2*>(A + off * 2);
+          ra[q][0] = v.x;
+          ra[q][1] = CONJ_A ? -v.y : v.y;
+        } else {
+          ra[q][0] = A[off];
         }
-  }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int kk, j;
+      b_pos(q, kk, j);
+      const int gj = n0 + j, gk = k0 + kk;
+      rb[q][0] = R(0);
+      if constexpr (CPLX) rb[q][1] = R(0);
+      if (gj < N && gk < K) {
+        const int64_t off = B_KCONTIG ? ((int64_t)gk + (int64_t)gj * g.ldb) : ((int64_t)gk * g.ldb + gj);
+        if constexpr (CPLX) {
+          const V2 v = *reinterpret_cast<const V2*>(B + off * 2);
+          rb[q][0] = v.x;
+          rb[q][1] = CONJ_B ? -v.y : v.y;
+        } else {
+          rb[q][0] = B[off];
+        }
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int i, kk;
+      a_pos(q, i, kk);
+#pragma unroll
+      for (int e = 0; e < ES; ++e) As[e][kk][i] = ra[q][e];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int kk, j;
+      b_pos(q, kk, j);
+#pragma unroll
+      for (int e = 0; e < ES; ++e) Bs[e][kk][j] = rb[q][e];
+    }
+  };
 
+  if (kfirst < K) load(kfirst);
   for (int k0 = kfirst; k0 < K; k0 += BK) {
     __syncthreads();
-    // ---- A tile -> LDS [k][m]
-    if constexpr (A_MCONTIG) {
-      constexpr int KS = NT / BM;
-#pragma unroll
-      for (int it = 0; it < BK / KS; ++it) {
-        const int kk = tid / BM + it * KS;
-        const int i = tid % BM;
-        const int gi = m0 + i, gk = k0 + kk;
-        R re = R(0), im = R(0);
-        if (gi < M && gk < K) {
-          const int64_t off = ((int64_t)gi + (int64_t)gk * g.lda) * ES;
-          re = A[off];
-          if constexpr (CPLX) im = A[off + 1];
-        }
-        As[0][kk][i] = re;
-        if constexpr (CPLX) As[1][kk][i] = CONJ_A ? -im : im;
-      }
-    } else {
-      constexpr int IS = NT / BK;
-#pragma unroll
-      for (int it = 0; it < BM / IS; ++it) {
-        const int i = tid / BK + it * IS;
-        const int kk = tid % BK;
-        const int gi = m0 + i, gk = k0 + kk;
-        R re = R(0), im = R(0);
-        if (gi < M && gk < K) {
-          const int64_t off = ((int64_t)gi * g.lda + gk) * ES;
-          re = A[off];
-          if constexpr (CPLX) im = A[off + 1];
-        }
-        As[0][kk][i] = re;
-        if constexpr (CPLX) As[1][kk][i] = CONJ_A ? -im : im;
-      }
-    }
-    // ---- B tile -> LDS [k][n]
-    if constexpr (!B_KCONTIG) {
-      constexpr int KS = NT / BN;
-#pragma unroll
-      for (int it = 0; it < BK / KS; ++it) {
-        const int kk = tid / BN + it * KS;
-        const int j = tid % BN;
-        const int gj = n0 + j, gk = k0 + kk;
-        R re = R(0), im = R(0);
-        if (gj < N && gk < K) {
-          const int64_t off = ((int64_t)gk * g.ldb + gj) * ES;
-          re = B[off];
-          if constexpr (CPLX) im = B[off + 1];
-        }
-        Bs[0][kk][j] = re;
-        if constexpr (CPLX) Bs[1][kk][j] = CONJ_B ? -im : im;
-      }
-    } else {
-      constexpr int JS = NT / BK;
-#pragma unroll
-      for (int it = 0; it < BN / JS; ++it) {
-        const int j = tid / BK + it * JS;
-        const int kk = tid % BK;
-        const int gj = n0 + j, gk = k0 + kk;
-        R re = R(0), im = R(0);
-        if (gj < N && gk < K) {
-          const int64_t off = ((int64_t)gk + (int64_t)gj * g.ldb) * ES;
-          re = B[off];
-          if constexpr (CPLX) im = B[off + 1];
-        }
-        Bs[0][kk][j] = re;
-        if constexpr (CPLX) Bs[1][kk][j] = CONJ_B ? -im : im;
-      }
-    }
+    store();
     __syncthreads();
-    // ---- MFMA over the BK slab, 4 at a time
+    if (k0 + BK < K) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -184,24 +177,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         ar[i] = As[0][kr][wm0 + i * 16 + cl];
-        if constexpr (CPLX) ai[i] = As[1][kr][wm0 + i * 16 + cl];
+        if constexpr (CPLX) ai[i] = As[ES - 1][kr][wm0 + i * 16 + cl];
       }
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         br[j] = Bs[0][kr][wn0 + j * 16 + cl];
-        if constexpr (CPLX) bi[j] = Bs[1][kr][wn0 + j * 16 + cl];
+        if constexpr (CPLX) bi[j] = Bs[ES - 1][kr][wn0 + j * 16 + cl];
       }
+      // one pass per real product, so consecutive MFMAs write different accumulators
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[0][i][j] = M_::run(ar[i], br[j], acc[0][i][j]);
-          if constexpr (CPLX) {
-            acc[0][i][j] = M_::run(-ai[i], bi[j], acc[0][i][j]);
-            acc[1][i][j] = M_::run(ar[i], bi[j], acc[1][i][j]);
-            acc[1][i][j] = M_::run(ai[i], br[j], acc[1][i][j]);
-          }
-        }
+        for (int j = 0; j < FN; ++j) acc[0][i][j] = M_::run(ar[i], br[j], acc[0][i][j]);
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[ES - 1][i][j] = M_::run(ar[i], bi[j], acc[ES - 1][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[ES - 1][i][j] = M_::run(ai[i], br[j], acc[ES - 1][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) ai[i] = -ai[i];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[0][i][j] = M_::run(ai[i], bi[j], acc[0][i][j]);
+      }
     }
   }
 
@@ -226,6 +229,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
   }
   // ---- epilogue: C = alpha * acc + beta * C
   const R alpha = (R)g.alpha, beta = (R)g.beta;
+  const bool use_c = g.beta != 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -237,13 +241,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
         if (gi < M && gj < N) {
           const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
           R vr = alpha * acc[0][i][j][r];
-          R vi = CPLX ? alpha * acc[ES - 1][i][j][r] : R(0);
-          if (use_c) {
-            vr += beta * cpre[0][i][j][r];
-            if constexpr (CPLX) vi += beta * cpre[ES - 1][i][j][r];
+          if constexpr (CPLX) {
+            R vi = alpha * acc[ES - 1][i][j][r];
+            if (use_c) {
+              const V2 c = *reinterpret_cast<const V2*>(C + off);
+              vr += beta * c.x;
+              vi += beta * c.y;
+            }
+            V2 o;
+            o.x = vr;
+            o.y = vi;
+            *reinterpret_cast<V2*>(C + off) = o;
+          } else {
+            if (use_c) vr += beta * C[off];
+            C[off] = vr;
           }
-          C[off] = vr;
-          if constexpr (CPLX) C[off + 1] = vi;
         }
       }
 }
@@ -308,28 +320,8 @@ static void* splitk_scratch(size_t bytes) {
   return b.first;
 }
 
-template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BK>
-static void launch_bk(const GemmArgs& g, int batch, hipStream_t s) {
-  constexpr int BM = 64, BN = 64;
-  const int tiles = ((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM) * batch;
-  // few output tiles and a long K: split K so that about 512 workgroups run
-  if (tiles < 128 && g.K >= 1024) {
-    int nsplit = std::min(std::max(2, 512 / tiles), g.K / 256);
-    nsplit = std::min(nsplit, 64);
-    const int kchunk = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
-    nsplit = (g.K + kchunk - 1) / kchunk;
-    constexpr int ES = CPLX ? 2 : 1;
-    R* part = static_cast<R*>(splitk_scratch((size_t)nsplit * batch * g.M * g.N * ES * sizeof(R)));
-    if (part != nullptr && nsplit > 1) {
-      dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch * nsplit);
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true>), grid, dim3(256), 0, s, g, nsplit,
-                         kchunk, part);
-      const int64_t mn = (int64_t)g.M * g.N;
-      hipLaunchKernelGGL((k_gemm_splitk_sum<R, CPLX>), dim3((unsigned)((mn + 255) / 256), batch), dim3(256), 0, s, g,
-                         nsplit, (const R*)part);
-      return;
-    }
-  }
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BM, int BN, int BK>
+static void launch_tile(const GemmArgs& g, int batch, hipStream_t s) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
   if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
     if (g.tag == 1) {
@@ -346,11 +338,30 @@ static void launch_bk(const GemmArgs& g, int batch, hipStream_t s) {
   hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0>), grid, dim3(256), 0, s, g, 1, 0, (R*)nullptr);
 }
 
-// 16-deep K slabs for every shape (deeper slabs for the K = 64 updates measured slower:
-// fewer resident workgroups outweigh the saved load round trips)
 template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
 static void launch(const GemmArgs& g, int batch, hipStream_t s) {
-  launch_bk<R, CPLX, AM, CJ, BK_, CJB, 16>(g, batch, s);
+  constexpr int BK = 16;
+  const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64) * batch;
+  // few output tiles and a long K: split K so that about 512 workgroups run
+  if (tiles < 128 && g.K >= 1024) {
+    constexpr int BM = 64, BN = 64;
+    int nsplit = std::min(std::max(2, 512 / tiles), g.K / 256);
+    nsplit = std::min(nsplit, 64);
+    const int kchunk = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
+    nsplit = (g.K + kchunk - 1) / kchunk;
+    constexpr int ES = CPLX ? 2 : 1;
+    R* part = static_cast<R*>(splitk_scratch((size_t)nsplit * batch * g.M * g.N * ES * sizeof(R)));
+    if (part != nullptr && nsplit > 1) {
+      dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch * nsplit);
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true>), grid, dim3(256), 0, s, g, nsplit,
+                         kchunk, part);
+      const int64_t mn = (int64_t)g.M * g.N;
+      hipLaunchKernelGGL((k_gemm_splitk_sum<R, CPLX>), dim3((unsigned)((mn + 255) / 256), batch), dim3(256), 0, s, g,
+                         nsplit, (const R*)part);
+      return;
+    }
+  }
+  launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, BK>(g, batch, s);
 }
 
 template <typename R, bool CPLX, bool AM, bool CJ>
