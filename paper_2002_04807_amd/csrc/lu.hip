@@ -14,12 +14,12 @@
 //             interchanges to the other panel columns and forms its rows of U; the
 //             panel columns right of the leaf are then updated by many workgroups
 //             (k_leaf_update).
-//   invert    the unit-lower and the upper LU_NB x LU_NB diagonal blocks are inverted
-//             in LDS and stored beside the factors, so that every triangular block
-//             solve (here and in the contour solves) is an MFMA product.
 //   laswp     the panel's interchanges applied to all columns outside the panel
 //             (rows are contiguous because the matrices are row-major).
-//   U12       U12 = L11^-1 A12 (MFMA product, in place).
+//   U12       U12 = L11^-1 A12 by forward substitution in LDS and registers.
+//   invert    after the last block, the unit-lower and the upper LU_NB x LU_NB
+//             diagonal blocks of every block row are inverted (one launch) and
+//             stored beside the factors for the contour solves.
 //   trailing  A22 -= L21 U12 (MFMA complex GEMM, the dense contraction of the LU).
 #include <climits>
 
@@ -462,6 +462,56 @@ __global__ __launch_bounds__(256) void k_invert_diag(int64_t n, int kfirst, int 
 }
 
 // ---------------------------------------------------------------------------
+// U12 = L11^-1 A12 for the LU_NB rows of block k (A12 already interchanged): forward
+// substitution in LDS and registers.  Workgroup x owns CW columns of A12; thread
+// (wave w, lane c) keeps rows w, w + 4, ... of its column in registers; at step i
+// the owner of row i publishes it through LDS and every row below subtracts
+// L[r][i] times it.
+template <typename C>
+struct u12_cols { static constexpr int value = sizeof(C) == 8 ? 64 : 32; };
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int k, int rest, C* __restrict__ LUall) {
+  constexpr int CW = u12_cols<C>::value;
+  constexpr int RG = 256 / CW;       // row groups
+  constexpr int RPT = LU_NB / RG;    // rows per thread
+  const int node = blockIdx.y;
+  C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  const int tid = threadIdx.x;
+  const int c = tid % CW, w = tid / CW;
+  const int64_t col = (int64_t)k + LU_NB + (int64_t)blockIdx.x * CW + c;
+  const bool live = blockIdx.x * CW + c < rest;
+  __shared__ C Ls[LU_NB][LU_NB + 1];
+  __shared__ C rowbuf[2][CW];
+  for (int e = tid; e < LU_NB * LU_NB; e += 256) {
+    const int i = e / LU_NB, j = e % LU_NB;
+    Ls[i][j] = LU[((int64_t)k + i) * n + k + j];
+  }
+  C v[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) v[q] = live ? LU[((int64_t)k + w + RG * q) * n + col] : C(0);
+  __syncthreads();
+  for (int i = 0; i < LU_NB - 1; ++i) {
+    if (w == i % RG) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (q == i / RG) rowbuf[i & 1][c] = v[q];
+    }
+    __syncthreads();
+    const C x = rowbuf[i & 1][c];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = w + RG * q;
+      if (r > i) v[q] = v[q] - Ls[r][i] * x;
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) LU[((int64_t)k + w + RG * q) * n + col] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
 template <typename C>
 __global__ void k_laswp(int64_t n, int k, int nbc, C* __restrict__ LUall, const int* __restrict__ ipiv_all) {
   __shared__ int sp[LU_NB];
@@ -499,19 +549,13 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
     if (launch_leaves<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
     // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
     prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);
-    hipLaunchKernelGGL((k_invert_diag<C>), dim3(1, ne), dim3(256), 0, s, n, (int)k, 1, LU, Dinv);
     hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, (int)k, nbc, LU, ipiv);
     const int64_t rest = n - k - nbc;
     if (rest > 0) {
-      const int64_t nblk_total = (n + LU_NB - 1) / LU_NB;
-      // U12 = L11^-1 A12 in place (one tile row: every workgroup owns whole columns)
-      GemmArgs g{};
-      g.M = nbc; g.N = (int)rest; g.K = nbc;
-      g.A = Dinv + (k / LU_NB) * 2 * LU_NB * LU_NB; g.lda = LU_NB; g.a_bs = nblk_total * 2 * LU_NB * LU_NB;
-      g.B = LU + k * n + k + nbc; g.ldb = n; g.b_bs = n * n;
-      g.C = LU + k * n + k + nbc; g.ldc = n; g.c_bs = n * n;
-      g.alpha = 1.0; g.beta = 0.0;
-      if (gemm<R, true>(s, false, false, g, ne)) return -2;
+      // U12 = L11^-1 A12 in place (nbc == LU_NB whenever columns remain to the right)
+      constexpr int CW = u12_cols<C>::value;
+      hipLaunchKernelGGL((k_trsm_u12<C>), dim3((unsigned)((rest + CW - 1) / CW), ne), dim3(256), 0, s, n, (int)k,
+                         (int)rest, LU);
       // A22 -= L21 U12
       GemmArgs t{};
       t.M = (int)rest; t.N = (int)rest; t.K = nbc;
@@ -526,6 +570,9 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
                (double)sizeof(C) * ne * (2.0 * rest * rest + 2.0 * rest * nbc));
     }
   }
+  // inverses of every diagonal block, for the solves
+  const int64_t nblk = (n + LU_NB - 1) / LU_NB;
+  hipLaunchKernelGGL((k_invert_diag<C>), dim3((unsigned)nblk, ne), dim3(256), 0, s, n, 0, (int)nblk, LU, Dinv);
   hipLaunchKernelGGL(k_perm_inverse, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ne, perm, perm_inv);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
