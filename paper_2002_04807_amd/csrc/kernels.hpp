@@ -118,8 +118,6 @@ int sym_permute(hipStream_t s, int m, const T* src, const int* p, T* dst);
 template <typename T>
 int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, T* dst);
 template <typename T>
-int set_diag_block(hipStream_t s, int m, const double* d, T* dst, int64_t ldd);
-template <typename T>
 int residual_norms(hipStream_t s, int64_t n, int m, const T* AX, const T* BX, const double* lam, T* R,
                    double* rnorm2, double* bnorm2, double* partial);
 template <typename T>

@@ -471,22 +471,6 @@ int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, 
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// dst (m x m, ld ldd) = diag(d)
-template <typename T>
-__global__ void k_set_diag_block(int m, const double* __restrict__ d, T* __restrict__ dst, int64_t ldd) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c >= m) return;
-  dst[(int64_t)r * ldd + c] = (r == c) ? T(d[r]) : T(0.0);
-}
-
-template <typename T>
-int set_diag_block(hipStream_t s, int m, const double* d, T* dst, int64_t ldd) {
-  if (m <= 0) return 0;
-  hipLaunchKernelGGL((k_set_diag_block<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, d, dst, ldd);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
-}
-
 #define MF_RR_INST(T)                                                                                          \
   template int col_absmax<T>(hipStream_t, int64_t, int, const T*, int64_t, double*);                           \
   template int gram_equilibrate<T>(hipStream_t, int, T*, T*, double*, int*);                                   \
@@ -501,7 +485,6 @@ int set_diag_block(hipStream_t s, int m, const double* d, T* dst, int64_t ldd) {
   template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);                            \
   template int hermitian_part<T>(hipStream_t, int, T*);                                                     \
   template int copy_block<T>(hipStream_t, int, int, const T*, int64_t, T*, int64_t, bool);                     \
-  template int set_diag_block<T>(hipStream_t, int, const double*, T*, int64_t);                                \
   template int sym_permute<T>(hipStream_t, int, const T*, const int*, T*);                                    \
   template int scatter_rows<T>(hipStream_t, int, int, const T*, const int*, T*);
 
