@@ -1,11 +1,12 @@
 // Block two-sided Jacobi eigensolver for the reduced Hermitian problem (gfx950).
 //
-// The m x m matrix (m up to 1024) is split into blocks of JB = 32 indices.  Every
-// round pairs the blocks with the round-robin (circle) ordering; each pair (P, Q)
-// forms a 64 x 64 Hermitian subproblem [H_PP H_PQ; H_QP H_QQ] that one workgroup
-// diagonalizes in LDS with cyclic Jacobi sweeps (its own round-robin ordering of
-// the 64 local indices), giving a unitary U_PQ.  A second launch then applies all
-// the rounds' U's at once: every 64 x 64 super-block H[I_i, I_j] becomes
+// The m x m matrix (m up to 1024) is split into blocks of JB indices (8 by default;
+// 16 and 32 selectable).  Every round pairs the blocks with the round-robin (circle)
+// ordering; each pair (P, Q) forms a 2JB x 2JB Hermitian subproblem
+// [H_PP H_PQ; H_QP H_QQ] that one workgroup diagonalizes in LDS with a cyclic Jacobi
+// sweep (its own round-robin ordering of the 2JB local indices), giving a unitary
+// U_PQ.  A second launch then applies all the round's U's at once: every super-block
+// H[I_i, I_j] becomes
 // U_i^H H[I_i, I_j] U_j (the pairs of a round are disjoint, so the super-blocks
 // update independently) and V[:, I_j] becomes V[:, I_j] U_j.  A sweep covers every
 // block pair once; sweeps stop when no subproblem needed a rotation.
@@ -307,14 +308,17 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
 }
 
 static int bj_width() {
-  static const int w = getenv("MFEAST_BJ_WIDTH") ? atoi(getenv("MFEAST_BJ_WIDTH")) : 16;
-  return w == 32 ? 32 : 16;
+  // 8-wide blocks measured fastest at M0 = 600: a 16 x 16 subproblem needs 15 inner
+  // rounds instead of 31, which outweighs the doubled number of outer rounds
+  static const int w = getenv("MFEAST_BJ_WIDTH") ? atoi(getenv("MFEAST_BJ_WIDTH")) : 8;
+  return (w == 32 || w == 8) ? w : 16;
 }
 
 template <typename T>
 int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
                  int max_sweeps) {
   if (bj_width() == 32) return block_jacobi_jb<T, 32>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
+  if (bj_width() == 8) return block_jacobi_jb<T, 8>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
   return block_jacobi_jb<T, 16>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
 }
 
