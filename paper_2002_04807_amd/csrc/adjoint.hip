@@ -122,7 +122,7 @@ int adjoint_run(mfeast_ctx* h, int64_t n, const double* A, int64_t lda, int M, c
     // factor lambda_i I - Ad for every i, batched like the contour nodes
     ph.start();
     const int64_t nblk = (n + LU_NB - 1) / LU_NB;
-    C* LU = (C*)h->ws(S_LU, (size_t)M * n * n * sizeof(C));
+    C* LU = (C*)h->ws(S_LU, (size_t)M * n * lu_ld(n) * sizeof(C));
     C* Dinv = (C*)h->ws(S_DINV, (size_t)M * nblk * 2 * LU_NB * LU_NB * sizeof(C));
     int* ipiv = (int*)h->ws(S_IPIV, (size_t)M * n * 4);
     int* perm = (int*)h->ws(S_PERM, (size_t)M * n * 4);

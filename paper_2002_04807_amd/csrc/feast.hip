@@ -199,7 +199,7 @@ struct DenseOp : Operator<T> {
     constexpr bool CPLX = is_cplx<T>::value;
     const int64_t nblk = (n + LU_NB - 1) / LU_NB;
     const size_t szT = sizeof(T), szC = sizeof(C);
-    LU = (C*)h->ws(S_LU, (size_t)ne * n * n * szC);
+    LU = (C*)h->ws(S_LU, (size_t)ne * n * lu_ld(n) * szC);
     Dinv = (C*)h->ws(S_DINV, (size_t)ne * nblk * 2 * LU_NB * LU_NB * szC);
     ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
     perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);

@@ -39,12 +39,23 @@ int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batc
 // ------------------------------------------------------------------ LU
 constexpr int LU_NB = 64;  // outer panel width of the blocked LU and of the blocked solves
 
+// Row stride of the stored shifted matrices and LU factors: n rounded up to an odd
+// multiple of 32 elements.  With a power-of-two stride every row of a column panel
+// starts at the same offset modulo the memory-channel interleave, and the panel's
+// accesses pile onto a few channels.
+__host__ __device__ inline int64_t lu_ld(int64_t n) {
+  int64_t b = (n + 31) / 32;
+  if ((b & 1) == 0) ++b;
+  return b * 32;
+}
+
 // Full Hermitian/symmetric copy (ld = n, column-major) from the triangle named by uplo.
 template <typename T>
 int expand_full(hipStream_t s, char uplo, int64_t n, const T* src, int64_t lds, T* dst);
 
-// LU_j = z_j * B - A, row-major, for j = 0..ne-1 (B == nullptr means identity);
-// also sets perm_j = identity.  A, B: full storage column-major (ld).
+// LU_j = z_j * B - A, row-major with row stride lu_ld(n) (n x lu_ld(n) entries per
+// node), for j = 0..ne-1 (B == nullptr means identity); also sets perm_j = identity.
+// A, B: full storage column-major (ld).
 template <typename T, typename C>
 int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
                const c64* z_dev, int ne, C* LU, int* perm);

@@ -55,7 +55,7 @@ int expand_full(hipStream_t s, char uplo, int64_t n, const T* src, int64_t lds, 
 
 // ---------------------------------------------------------------------------
 template <typename T, typename C>
-__global__ void k_shift_form(int64_t n, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+__global__ void k_shift_form(int64_t n, int64_t ld, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                              int64_t ldb, const c64* __restrict__ z, int ne, C* __restrict__ LU,
                              int* __restrict__ perm) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -69,7 +69,7 @@ __global__ void k_shift_form(int64_t n, const T* __restrict__ A, int64_t lda, co
   else b = c64(i == c ? 1.0 : 0.0, 0.0);
   for (int j = 0; j < ne; ++j) {
     const c64 v = z[j] * b - a;
-    LU[(int64_t)j * n * n + i * n + c] = convert<C, c64>(v);
+    LU[(int64_t)j * n * ld + i * ld + c] = convert<C, c64>(v);
   }
   if (i == 0)
     for (int j = 0; j < ne; ++j) perm[(int64_t)j * n + c] = (int)c;
@@ -79,20 +79,12 @@ template <typename T, typename C>
 int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
                const c64* z_dev, int ne, C* LU, int* perm) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-  hipLaunchKernelGGL((k_shift_form<T, C>), grid, dim3(256), 0, s, n, A, lda, B, ldb, z_dev, ne, LU, perm);
+  hipLaunchKernelGGL((k_shift_form<T, C>), grid, dim3(256), 0, s, n, lu_ld(n), A, lda, B, ldb, z_dev, ne, LU, perm);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // ---------------------------------------------------------------------------
 constexpr int MAX_N = 16384;
-
-template <typename R>
-__device__ inline void argmax_merge(R& v, int& i, R ov, int oi) {
-  if (ov > v || (ov == v && oi < i)) {
-    v = ov;
-    i = oi;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Recursive panel: the LU_NB-wide panel is factored in leaves of IB columns.  For each
@@ -103,13 +95,78 @@ __device__ inline void argmax_merge(R& v, int& i, R ov, int oi) {
 // panel columns to the right over many workgroups.  No grid-wide synchronization.
 constexpr int LEAF_THREADS = 1024;
 
+// Wavefront-wide max / min of a 32-bit unsigned value with DPP: two quad
+// permutations and two rotations inside each row of 16 lanes, then the row-15 and
+// row-31 broadcasts; lane 63 ends with the result, which every lane then reads.
+template <bool MAX>
+__device__ inline unsigned wave_reduce_u32(unsigned x) {
+  auto op = [](unsigned a, unsigned b) { return MAX ? max(a, b) : min(a, b); };
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x124, 0xF, 0xF, false));  // row_ror 4
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x128, 0xF, 0xF, false));  // row_ror 8
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x142, 0xA, 0xF, false));  // row_bcast 15
+  x = op(x, (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x143, 0xC, 0xF, false));  // row_bcast 31
+  return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Pivot keys: an eligible magnitude a >= 0 maps to its bit pattern plus one (which
+// orders like a), an ineligible row or a NaN to 0.  The key is 32 bits for float and
+// 64 bits for double magnitudes.
+template <typename R> struct pivot_key;
+template <> struct pivot_key<float> {
+  using K = unsigned;
+  __device__ static K of(float a, bool ok) { return (ok && a >= 0.0f) ? __float_as_uint(a) + 1u : 0u; }
+  __device__ static K wave_max(K x) { return wave_reduce_u32<true>(x); }
+};
+template <> struct pivot_key<double> {
+  using K = unsigned long long;
+  __device__ static K of(double a, bool ok) {
+    return (ok && a >= 0.0) ? (K)__double_as_longlong(a) + 1ull : 0ull;
+  }
+  __device__ static K wave_max(K x) {
+    const unsigned hi = wave_reduce_u32<true>((unsigned)(x >> 32));
+    const unsigned lo = wave_reduce_u32<true>((unsigned)(x >> 32) == hi ? (unsigned)x : 0u);
+    return ((K)hi << 32) | lo;
+  }
+};
+
+// a row segment of N consecutive elements as 16-byte loads and stores (16-byte aligned
+// when its size is a multiple of 16 bytes; element by element otherwise)
+template <typename C, int N>
+__device__ inline void load_row(const C* p, C (&out)[N]) {
+  if constexpr ((N * sizeof(C)) % 16 == 0) {
+    union { uint4 q[N * sizeof(C) / 16]; C e[N]; } u;
+#pragma unroll
+    for (int i = 0; i < (int)(N * sizeof(C) / 16); ++i) u.q[i] = reinterpret_cast<const uint4*>(p)[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = u.e[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = p[i];
+  }
+}
+template <typename C, int N>
+__device__ inline void store_row(C* p, const C (&in)[N]) {
+  if constexpr ((N * sizeof(C)) % 16 == 0) {
+    union { uint4 q[N * sizeof(C) / 16]; C e[N]; } u;
+#pragma unroll
+    for (int i = 0; i < N; ++i) u.e[i] = in[i];
+#pragma unroll
+    for (int i = 0; i < (int)(N * sizeof(C) / 16); ++i) reinterpret_cast<uint4*>(p)[i] = u.q[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = in[i];
+  }
+}
+
 template <typename C, int IB, int RMAX>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb, int nbc, C* __restrict__ LUall,
+__global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, int k, int jb, int nbc, C* __restrict__ LUall,
                                                          int* __restrict__ ipiv_all, int* __restrict__ perm_all,
                                                          int* __restrict__ info_all) {
   using R = typename real_of<C>::type;
   const int node = blockIdx.x;
-  C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -120,66 +177,74 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb,
   __shared__ int s_ipiv[IB];
   __shared__ C prow[IB], crow[IB];
   __shared__ C Lsub[IB][IB];
-  __shared__ R red_v[LEAF_THREADS / 64];
-  __shared__ int red_i[LEAF_THREADS / 64];
-  __shared__ int s_p;
+  using PK = pivot_key<R>;
+  __shared__ typename PK::K red_k[LEAF_THREADS / 64];
+  __shared__ unsigned red_i[LEAF_THREADS / 64];
   __shared__ int s_zero;
   // rows touched by the interchanges: the leaf's top rows and the pivot rows
   __shared__ int s_rows[2 * IB];
   __shared__ int s_nrows;
   __shared__ int s_swa[IB], s_swb[IB];  // per interchange: indices into s_rows
+  __shared__ C oval[2 * IB][LU_NB];      // touched rows of the other panel columns
+  __shared__ int opv[2 * IB];            // and of perm
 
   if (tid == 0) s_zero = 0;
+  // rows of the leaf are 16-byte aligned (ld and row0 are multiples of IB); a narrower
+  // last leaf reads its padding columns and zeroes them
   C v[RMAX][IB];
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
     const int r = tid + t * LEAF_THREADS;
+    if (r < mr) load_row<C, IB>(LU + (row0 + r) * ld + row0, v[t]);
 #pragma unroll
-    for (int c = 0; c < IB; ++c) v[t][c] = (r < mr && c < ibc) ? LU[(row0 + r) * n + row0 + c] : C(0);
+    for (int c = 0; c < IB; ++c)
+      if (!(r < mr && c < ibc)) v[t][c] = C(0);
   }
   __syncthreads();
 
-  for (int j = 0; j < ibc; ++j) {
+  // the column loop is unrolled so that every register index below is a constant
+#pragma unroll
+  for (int j = 0; j < IB; ++j) {
+    if (j >= ibc) break;
     // ---- pivot: largest |re|+|im| among local rows r >= j of column j, lowest index on ties
-    R best = R(-1);
-    int bi = INT_MAX;
+    typename PK::K best = 0;
+    unsigned bi = 0xFFFFFFFFu;
 #pragma unroll
     for (int t = 0; t < RMAX; ++t) {
       const int r = tid + t * LEAF_THREADS;
-      R a = R(-1);
-#pragma unroll
-      for (int c = 0; c < IB; ++c)
-        if (c == j) a = abs1(v[t][c]);
-      if (r >= j && r < mr && a > best) {
-        best = a;
-        bi = r;
+      const typename PK::K key = PK::of(abs1(v[t][j]), r >= j && r < mr);
+      if (key > best) {
+        best = key;
+        bi = (unsigned)r;
       }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const R ov = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      argmax_merge(best, bi, ov, oi);
-    }
+    const typename PK::K wbest = PK::wave_max(best);
+    const unsigned wbi = wave_reduce_u32<false>(best == wbest ? bi : 0xFFFFFFFFu);
     if (lane == 0) {
-      red_v[wave] = best;
-      red_i[wave] = bi;
+      red_k[wave] = wbest;
+      red_i[wave] = wbi;
     }
     __syncthreads();
-    if (tid == 0) {
-      R bv = red_v[0];
-      int bx = red_i[0];
-      for (int w = 1; w < LEAF_THREADS / 64; ++w) argmax_merge(bv, bx, red_v[w], red_i[w]);
-      if (bx == INT_MAX || !(bv > R(0))) {
-        // zero (or non-finite) column: keep the diagonal row, flag the breakdown
-        if (s_zero == 0) s_zero = (int)(row0 + j) + 1;
-        bx = j;
+    // every thread merges the per-wavefront candidates itself (no broadcast round)
+    typename PK::K bk = red_k[0];
+    unsigned bu = red_i[0];
+#pragma unroll
+    for (int w = 1; w < LEAF_THREADS / 64; ++w) {
+      const typename PK::K ok = red_k[w];
+      const unsigned oi = red_i[w];
+      if (ok > bk || (ok == bk && oi < bu)) {
+        bk = ok;
+        bu = oi;
       }
-      s_p = bx;
-      s_ipiv[j] = bx;
     }
-    __syncthreads();
-    const int p = s_p;
+    int bx = (int)bu;
+    // a zero (or non-finite) column: keep the diagonal row, flag the breakdown
+    if (bk <= 1) {
+      if (tid == 0 && s_zero == 0) s_zero = (int)(row0 + j) + 1;
+      bx = j;
+    }
+    const int p = bx;
+    if (tid == 0) s_ipiv[j] = p;
     // ---- exchange local rows j and p through LDS
     if (tid == (p & (LEAF_THREADS - 1))) {
 #pragma unroll
@@ -204,7 +269,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb,
 #pragma unroll
           for (int c = 0; c < IB; ++c) v[t][c] = crow[c];
     }
-    // ---- scale column j below the diagonal and update the leaf
+    // ---- scale column j below the diagonal and update the leaf.  No barrier follows:
+    //      red_k / red_i were last read before the barrier above, and prow / crow are
+    //      rewritten only after the next column's first barrier.
     C piv = C(0);
 #pragma unroll
     for (int c = 0; c < IB; ++c)
@@ -226,16 +293,15 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb,
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // ---- the factored leaf back to memory; its unit-lower top block to LDS
+  // (columns past ibc are padding of the last block and receive zeros)
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
     const int r = tid + t * LEAF_THREADS;
-#pragma unroll
-    for (int c = 0; c < IB; ++c)
-      if (r < mr && c < ibc) LU[(row0 + r) * n + row0 + c] = v[t][c];
+    if (r < mr) store_row<C, IB>(LU + (row0 + r) * ld + row0, v[t]);
   }
   if (tid < ibc) {
 #pragma unroll
@@ -259,78 +325,46 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb,
   __syncthreads();
   const int nr = s_nrows;
   int* perm = perm_all + (int64_t)node * n;
-  // ---- interchanges on the other panel columns (one thread per column, in registers);
+  // ---- interchanges on the other panel columns (one thread per column);
   //      thread LU_NB applies them to perm.  Then U rows of the leaf for the columns right
   //      of it: U = Lsub^-1 (swapped top rows).
   const int ocols = nbc - ibc;
   if (tid < ocols || tid == LU_NB) {
+    // each thread owns one column (or perm) and keeps the touched rows in its own LDS
+    // column, where the swap sequence and the U solve index freely
     const bool is_perm = (tid == LU_NB);
     const int cc = tid;
     const int64_t col = is_perm ? 0 : ((cc < jb) ? (k + cc) : (k + cc + ibc));
-    C val[2 * IB];
-    int pv[2 * IB];
-#pragma unroll
-    for (int e = 0; e < 2 * IB; ++e) {
-      if (e < nr) {
-        const int64_t row = row0 + s_rows[e];
-        if (is_perm) pv[e] = perm[row];
-        else val[e] = LU[row * n + col];
+    for (int e = 0; e < nr; ++e) {
+      const int64_t row = row0 + s_rows[e];
+      if (is_perm) opv[e] = perm[row];
+      else oval[e][cc] = LU[row * ld + col];
+    }
+    for (int j = 0; j < ibc; ++j) {
+      const int a = s_swa[j], b = s_swb[j];
+      if (a == b) continue;
+      if (is_perm) {
+        const int t0 = opv[a];
+        opv[a] = opv[b];
+        opv[b] = t0;
+      } else {
+        const C t0 = oval[a][cc];
+        oval[a][cc] = oval[b][cc];
+        oval[b][cc] = t0;
       }
     }
-#pragma unroll
-    for (int j = 0; j < IB; ++j) {
-      if (j < ibc) {
-        const int a = s_swa[j], b = s_swb[j];
-        if (a != b) {
-#pragma unroll
-          for (int e = 0; e < 2 * IB; ++e) {
-            // swap entries a and b with compile-time indices only
-            if (e == a) {
-#pragma unroll
-              for (int f = 0; f < 2 * IB; ++f)
-                if (f == b) {
-                  if (is_perm) {
-                    const int t0 = pv[e];
-                    pv[e] = pv[f];
-                    pv[f] = t0;
-                  } else {
-                    const C t0 = val[e];
-                    val[e] = val[f];
-                    val[f] = t0;
-                  }
-                }
-            }
-          }
-        }
-      }
-    }
-    // U rows of the leaf (columns right of the leaf): entries for local rows 0..ibc-1
+    // U rows of the leaf (columns right of the leaf): local row j sits in slot s_swa[j]
     if (!is_perm && cc >= jb) {
-      C x[IB];
-#pragma unroll
-      for (int j = 0; j < IB; ++j) {
-        if (j < ibc) {
-          C s = C(0);
-#pragma unroll
-          for (int e = 0; e < 2 * IB; ++e)
-            if (e == s_swa[j]) s = val[e];  // local row j sits in slot s_swa[j]
-#pragma unroll
-          for (int i = 0; i < IB; ++i)
-            if (i < j) s = s - Lsub[j][i] * x[i];
-          x[j] = s;
-#pragma unroll
-          for (int e = 0; e < 2 * IB; ++e)
-            if (e == s_swa[j]) val[e] = s;
-        }
+      for (int j = 0; j < ibc; ++j) {
+        C x = oval[s_swa[j]][cc];
+        for (int i = 0; i < j; ++i) x = x - Lsub[j][i] * oval[s_swa[i]][cc];
+        oval[s_swa[j]][cc] = x;
       }
     }
-#pragma unroll
-    for (int e = 0; e < 2 * IB; ++e) {
-      if (e < nr) {
-        const int64_t row = row0 + s_rows[e];
-        if (is_perm) perm[row] = pv[e];
-        else LU[row * n + col] = val[e];
-      }
+    for (int e = 0; e < nr; ++e) {
+      const int64_t row = row0 + s_rows[e];
+      if (is_perm) perm[row] = opv[e];
+      else LU[row * ld + col] = oval[e][cc];
     }
   }
   if (tid < ibc) ipiv_all[(int64_t)node * n + row0 + tid] = (int)row0 + s_ipiv[tid];
@@ -341,9 +375,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int k, int jb,
 constexpr int LU_ROWS = 64;  // rows per workgroup of the update
 
 template <typename C, int IB>
-__global__ __launch_bounds__(256) void k_leaf_update(int64_t n, int k, int jb, int nbc, C* __restrict__ LUall) {
+__global__ __launch_bounds__(256) void k_leaf_update(int64_t n, int64_t ld, int k, int jb, int nbc, C* __restrict__ LUall) {
   const int node = blockIdx.y;
-  C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   const int ibc = min(IB, nbc - jb);
   const int64_t row0 = k + jb;
   const int64_t c0 = row0 + ibc;             // first column right of the leaf
@@ -356,35 +390,35 @@ __global__ __launch_bounds__(256) void k_leaf_update(int64_t n, int k, int jb, i
   const int tid = threadIdx.x;
   for (int e = tid; e < IB * LU_NB; e += 256) {
     const int i = e / LU_NB, c = e % LU_NB;
-    Us[i][c] = (i < ibc && c < ucols) ? LU[(row0 + i) * n + c0 + c] : C(0);
+    Us[i][c] = (i < ibc && c < ucols) ? LU[(row0 + i) * ld + c0 + c] : C(0);
   }
   for (int e = tid; e < LU_ROWS * IB; e += 256) {
     const int r = e / IB, i = e % IB;
     const int64_t row = rbeg + r;
-    Ls[r][i] = (row < rend && i < ibc) ? LU[row * n + row0 + i] : C(0);
+    Ls[r][i] = (row < rend && i < ibc) ? LU[row * ld + row0 + i] : C(0);
   }
   __syncthreads();
   for (int e = tid; e < LU_ROWS * ucols; e += 256) {
     const int r = e / ucols, c = e % ucols;
     const int64_t row = rbeg + r;
     if (row >= rend) continue;
-    C s = LU[row * n + c0 + c];
+    C s = LU[row * ld + c0 + c];
 #pragma unroll
     for (int i = 0; i < IB; ++i) s = s - Ls[r][i] * Us[i][c];
-    LU[row * n + c0 + c] = s;
+    LU[row * ld + c0 + c] = s;
   }
 }
 
 template <typename C, int IB, int RMAX>
 static int run_leaves(hipStream_t s, int64_t n, int k, int nbc, int ne, C* LU, int* ipiv, int* perm, int* info) {
   for (int jb = 0; jb < nbc; jb += IB) {
-    hipLaunchKernelGGL((k_leaf<C, IB, RMAX>), dim3(ne), dim3(LEAF_THREADS), 0, s, n, k, jb, nbc, LU, ipiv, perm,
-                       info);
+    hipLaunchKernelGGL((k_leaf<C, IB, RMAX>), dim3(ne), dim3(LEAF_THREADS), 0, s, n, lu_ld(n), k, jb, nbc, LU, ipiv,
+                       perm, info);
     const int ibc = std::min(IB, nbc - jb);
     if (jb + ibc < nbc) {
       const int64_t rows = n - (k + jb + ibc);
       hipLaunchKernelGGL((k_leaf_update<C, IB>), dim3((unsigned)((rows + LU_ROWS - 1) / LU_ROWS), ne), dim3(256), 0, s,
-                         n, k, jb, nbc, LU);
+                         n, lu_ld(n), k, jb, nbc, LU);
     }
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -410,13 +444,13 @@ static int launch_leaves(hipStream_t s, int64_t n, int k, int nbc, int ne, C* LU
 // inverses of the diagonal blocks: Linv (unit lower) and Uinv (upper), row-major
 // LU_NB x LU_NB per block, zero-padded when the last block is narrower.
 template <typename C>
-__global__ __launch_bounds__(256) void k_invert_diag(int64_t n, int kfirst, int nblocks, const C* __restrict__ LUall,
+__global__ __launch_bounds__(256) void k_invert_diag(int64_t n, int64_t ld, int kfirst, int nblocks, const C* __restrict__ LUall,
                                                       C* __restrict__ Dinv) {
   const int node = blockIdx.y;
   const int blk = kfirst / LU_NB + blockIdx.x;
   const int64_t k = (int64_t)blk * LU_NB;
   const int nbc = (int)min<int64_t>(LU_NB, n - k);
-  const C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  const C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   const int nblk_total = (int)((n + LU_NB - 1) / LU_NB);
   C* __restrict__ Li = Dinv + ((int64_t)node * nblk_total + blk) * 2 * LU_NB * LU_NB;
   C* __restrict__ Ui = Li + LU_NB * LU_NB;
@@ -425,7 +459,7 @@ __global__ __launch_bounds__(256) void k_invert_diag(int64_t n, int kfirst, int 
   const int tid = threadIdx.x;
   for (int e = tid; e < LU_NB * LU_NB; e += 256) {
     const int i = e / LU_NB, j = e % LU_NB;
-    Ls[i][j] = (i < nbc && j < nbc) ? LU[(k + i) * n + k + j] : C(0);
+    Ls[i][j] = (i < nbc && j < nbc) ? LU[(k + i) * ld + k + j] : C(0);
   }
   __syncthreads();
   // unit lower inverse: column c solved by thread c
@@ -471,12 +505,12 @@ template <typename C>
 struct u12_cols { static constexpr int value = sizeof(C) == 8 ? 64 : 32; };
 
 template <typename C>
-__global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int k, int rest, C* __restrict__ LUall) {
+__global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int64_t ld, int k, int rest, C* __restrict__ LUall) {
   constexpr int CW = u12_cols<C>::value;
   constexpr int RG = 256 / CW;       // row groups
   constexpr int RPT = LU_NB / RG;    // rows per thread
   const int node = blockIdx.y;
-  C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   const int tid = threadIdx.x;
   const int c = tid % CW, w = tid / CW;
   const int64_t col = (int64_t)k + LU_NB + (int64_t)blockIdx.x * CW + c;
@@ -485,11 +519,11 @@ __global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int k, int rest, C*
   __shared__ C rowbuf[2][CW];
   for (int e = tid; e < LU_NB * LU_NB; e += 256) {
     const int i = e / LU_NB, j = e % LU_NB;
-    Ls[i][j] = LU[((int64_t)k + i) * n + k + j];
+    Ls[i][j] = LU[((int64_t)k + i) * ld + k + j];
   }
   C v[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) v[q] = live ? LU[((int64_t)k + w + RG * q) * n + col] : C(0);
+  for (int q = 0; q < RPT; ++q) v[q] = live ? LU[((int64_t)k + w + RG * q) * ld + col] : C(0);
   __syncthreads();
   for (int i = 0; i < LU_NB - 1; ++i) {
     if (w == i % RG) {
@@ -507,26 +541,26 @@ __global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int k, int rest, C*
   }
   if (live) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) LU[((int64_t)k + w + RG * q) * n + col] = v[q];
+    for (int q = 0; q < RPT; ++q) LU[((int64_t)k + w + RG * q) * ld + col] = v[q];
   }
 }
 
 // ---------------------------------------------------------------------------
 template <typename C>
-__global__ void k_laswp(int64_t n, int k, int nbc, C* __restrict__ LUall, const int* __restrict__ ipiv_all) {
+__global__ void k_laswp(int64_t n, int64_t ld, int k, int nbc, C* __restrict__ LUall, const int* __restrict__ ipiv_all) {
   __shared__ int sp[LU_NB];
   const int node = blockIdx.y;
   if (threadIdx.x < nbc) sp[threadIdx.x] = ipiv_all[(int64_t)node * n + k + threadIdx.x];
   __syncthreads();
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= n || (c >= k && c < k + nbc)) return;
-  C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   for (int j = 0; j < nbc; ++j) {
     const int64_t a = k + j, b = sp[j];
     if (a != b) {
-      const C t0 = LU[a * n + c];
-      LU[a * n + c] = LU[b * n + c];
-      LU[b * n + c] = t0;
+      const C t0 = LU[a * ld + c];
+      LU[a * ld + c] = LU[b * ld + c];
+      LU[b * ld + c] = t0;
     }
   }
 }
@@ -543,25 +577,26 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
               C* Dinv) {
   if (n > MAX_N) return -2;
   using R = typename real_of<C>::type;
+  const int64_t ld = lu_ld(n);
   for (int64_t k = 0; k < n; k += LU_NB) {
     const int nbc = (int)std::min<int64_t>(LU_NB, n - k);
     int tok = prof_begin(s);
     if (launch_leaves<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
     // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
     prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);
-    hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, (int)k, nbc, LU, ipiv);
+    hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ld, (int)k, nbc, LU, ipiv);
     const int64_t rest = n - k - nbc;
     if (rest > 0) {
       // U12 = L11^-1 A12 in place (nbc == LU_NB whenever columns remain to the right)
       constexpr int CW = u12_cols<C>::value;
-      hipLaunchKernelGGL((k_trsm_u12<C>), dim3((unsigned)((rest + CW - 1) / CW), ne), dim3(256), 0, s, n, (int)k,
+      hipLaunchKernelGGL((k_trsm_u12<C>), dim3((unsigned)((rest + CW - 1) / CW), ne), dim3(256), 0, s, n, ld, (int)k,
                          (int)rest, LU);
       // A22 -= L21 U12
       GemmArgs t{};
       t.M = (int)rest; t.N = (int)rest; t.K = nbc;
-      t.A = LU + (k + nbc) * n + k; t.lda = n; t.a_bs = n * n;
-      t.B = LU + k * n + k + nbc; t.ldb = n; t.b_bs = n * n;
-      t.C = LU + (k + nbc) * n + k + nbc; t.ldc = n; t.c_bs = n * n;
+      t.A = LU + (k + nbc) * ld + k; t.lda = ld; t.a_bs = n * ld;
+      t.B = LU + k * ld + k + nbc; t.ldb = ld; t.b_bs = n * ld;
+      t.C = LU + (k + nbc) * ld + k + nbc; t.ldc = ld; t.c_bs = n * ld;
       t.alpha = -1.0; t.beta = 1.0;
       t.tag = 1;
       tok = prof_begin(s);
@@ -572,7 +607,7 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
   }
   // inverses of every diagonal block, for the solves
   const int64_t nblk = (n + LU_NB - 1) / LU_NB;
-  hipLaunchKernelGGL((k_invert_diag<C>), dim3((unsigned)nblk, ne), dim3(256), 0, s, n, 0, (int)nblk, LU, Dinv);
+  hipLaunchKernelGGL((k_invert_diag<C>), dim3((unsigned)nblk, ne), dim3(256), 0, s, n, ld, 0, (int)nblk, LU, Dinv);
   hipLaunchKernelGGL(k_perm_inverse, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ne, perm, perm_inv);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256) void k_trsm_panel(int64_t n, int ncols, int64_
   const int c0 = blockIdx.x * CW;
   const int64_t p0 = (pan0 + blockIdx.y) * TRSM_PH;
   const int nsb = (int)((min<int64_t>(TRSM_PH, n - p0) + LU_NB - 1) / LU_NB);
-  const C* __restrict__ LU = LUall + (int64_t)node * n * n;
+  const int64_t ld = lu_ld(n);
+  const C* __restrict__ LU = LUall + (int64_t)node * n * ld;
   const C* __restrict__ D = Dinv + (int64_t)node * dstride;
   C* __restrict__ W = Wall + (int64_t)node * w_node + (int64_t)blockIdx.y * w_panel + (rows_global ? p0 * ldw : 0);
   const int rows = nsb * LU_NB;
@@ -123,9 +124,9 @@ __global__ __launch_bounds__(256) void k_trsm_panel(int64_t n, int ncols, int64_
         const int a = e / LU_NB, c = e % LU_NB;  // c runs along memory
         if (HERM) {
           // As[i][k] = conj(LU[rb + k][rb2 + i]) with k = a, i = c
-          As[c][a] = (rb + a < n && rb2 + c < n) ? conj(LU[(rb + a) * n + rb2 + c]) : C(0);
+          As[c][a] = (rb + a < n && rb2 + c < n) ? conj(LU[(rb + a) * ld + rb2 + c]) : C(0);
         } else {
-          As[a][c] = (rb2 + a < n && rb + c < n) ? LU[(rb2 + a) * n + rb + c] : C(0);
+          As[a][c] = (rb2 + a < n && rb + c < n) ? LU[(rb2 + a) * ld + rb + c] : C(0);
         }
       }
       __syncthreads();
@@ -181,7 +182,8 @@ template <typename C>
 int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y) {
   using R = typename real_of<C>::type;
   const int64_t wstride = n * (int64_t)m;
-  const int64_t lstride = n * n;
+  const int64_t ld = lu_ld(n);
+  const int64_t lstride = n * ld;
   const int64_t npan = panel_count(n);
   const int64_t sq = (int64_t)TRSM_PH * TRSM_PH;
   const int64_t pstride = (int64_t)panel_inverse_entries(n);
@@ -204,7 +206,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
       GemmArgs g{};
       g.N = m; g.K = (int)ph;
       g.B = out + p0 * m; g.ldb = m; g.b_bs = wstride;
-      g.lda = n; g.a_bs = lstride;
+      g.lda = ld; g.a_bs = lstride;
       g.c_bs = wstride; g.ldc = m;
       g.alpha = -1.0; g.beta = 1.0;
       if (!desc) {
@@ -213,13 +215,13 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
         g.M = (int)rest;
         g.C = in + (p0 + ph) * m;
         // L: rows below the panel, its columns; U^H: M-contiguous view of the panel's U rows
-        g.A = herm ? LU + p0 * n + p0 + ph : LU + (p0 + ph) * n + p0;
+        g.A = herm ? LU + p0 * ld + p0 + ph : LU + (p0 + ph) * ld + p0;
       } else {
         if (p0 <= 0) continue;
         g.M = (int)p0;
         g.C = in;
         // U: rows above the panel, its columns; L^H: M-contiguous view of the panel's L rows
-        g.A = herm ? LU + p0 * n : LU + p0;
+        g.A = herm ? LU + p0 * ld : LU + p0;
       }
       if (gemm<R, true>(s, herm, herm, g, ne)) return -2;
     }
