@@ -17,6 +17,7 @@ enum Slot {
   S_SMALL, S_PART, S_FLAG,
   S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF,
   S_ADJ_AD, S_ADJ_XR, S_ADJ_R, S_ADJ_Y, S_ADJ_T, S_ADJ_SMALL,
+  S_IR_XF, S_IR_YC, S_IR_T, S_IR_AX, S_IR_BX,
   S_NSLOTS
 };
 

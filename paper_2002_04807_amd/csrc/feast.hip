@@ -127,6 +127,7 @@ static int check_fpm(const int32_t* fpm, bool expert) {
   if (f(6) != 0 && f(6) != 1) return 106;
   if (f(14) != 0 && f(14) != 1) return 114;
   if (f(42) != 0 && f(42) != 1) return 142;
+  if (f(50) < 0 || f(50) > 8) return 150;
   return 0;
 }
 
@@ -188,6 +189,9 @@ struct DenseOp : Operator<T> {
   C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr, *Wy = nullptr, *Pinv = nullptr;
   int *ipiv = nullptr, *perm = nullptr, *pinv = nullptr, *linfo = nullptr;
   c64* zdev = nullptr;
+  // fpm(50): extra refinement steps of the FP32 solves (FP64 solutions and residuals)
+  int ir_steps = 0;
+  c64 *irXf = nullptr, *irYc = nullptr, *irT = nullptr, *irAX = nullptr, *irBX = nullptr;
 
   DenseOp(mfeast_ctx* h_, char uplo_, int64_t n_, const T* A_, int64_t lda_, const T* B_, int64_t ldb_,
           const std::vector<c64>& z_, int m0_)
@@ -211,6 +215,15 @@ struct DenseOp : Operator<T> {
     Wy = (C*)h->ws(S_WY, (size_t)ne * n * m0max * szC);
     Pinv = (C*)h->ws(S_PANINV, (size_t)ne * panel_inverse_entries(n) * szC);
     if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Wy || !Pinv) return -2;
+    if (ir_steps > 0 && sizeof(C) == sizeof(c32)) {
+      const size_t blk64 = (size_t)ne * n * m0max * sizeof(c64);
+      irXf = (c64*)h->ws(S_IR_XF, blk64);
+      irYc = CPLX ? (c64*)h->ws(S_IR_YC, blk64) : nullptr;
+      irT = CPLX ? (c64*)h->ws(S_IR_T, blk64) : nullptr;
+      irAX = (c64*)h->ws(S_IR_AX, blk64);
+      irBX = B ? (c64*)h->ws(S_IR_BX, blk64) : nullptr;
+      if (!irXf || (CPLX && (!irYc || !irT)) || !irAX || (B && !irBX)) return -2;
+    }
     // full storage if a triangle was given
     Af = A;
     ldaf = lda;
@@ -266,9 +279,69 @@ struct DenseOp : Operator<T> {
     MF_TRY(rhs_prepare<T, C>(s, n, m, rhs, m, k.cs, ne, perm, Wf, Wc));
     prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
     MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy));
+    if (sizeof(C) == sizeof(c32) && irXf != nullptr) {
+      if constexpr (sizeof(C) == sizeof(c32)) MF_TRY(refine(s, m, rhs, k));
+      tok = prof_begin(s);
+      MF_TRY(accumulate<T, c64>(s, n, m, ne, irXf, irYc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0));
+      prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(c64) + (resid ? 2.0 : 1.0) * sizeof(T)));
+      return 0;
+    }
     tok = prof_begin(s);
     MF_TRY(accumulate<T, C>(s, n, m, ne, Wf, Wc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0));
     prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));
+    return 0;
+  }
+
+  // Y_j = Mat X_j for every node (Mat: this operator's full FP64 A or B, column-major,
+  // shared by the nodes); complex X with a real Mat is read as 2m real columns
+  int apply_nodes(hipStream_t s, const T* Mat, int64_t ldm, int m, const c64* X, c64* Y) {
+    constexpr bool CPLX = is_cplx<T>::value;
+    GemmArgs g{};
+    g.M = (int)n; g.K = (int)n;
+    g.A = Mat; g.lda = ldm; g.a_bs = 0;
+    g.alpha = 1.0; g.beta = 0.0;
+    const int cols = CPLX ? m : 2 * m;
+    g.N = cols;
+    g.B = X; g.ldb = cols; g.b_bs = n * (int64_t)cols;
+    g.C = Y; g.ldc = cols; g.c_bs = n * (int64_t)cols;
+    const int tok = prof_begin(s);
+    const int rc = gemm<double, CPLX>(s, true, false, g, ne);
+    prof_end(tok, s, K_RR_GEMM, 8.0 * (double)n * n * m * ne, 0.0);
+    return rc;
+  }
+
+  // fpm(50) refinement steps: the FP32 solutions in Wf / Wc are widened to FP64; each
+  // step forms the FP64 residual of every node's system, solves it with the FP32
+  // factors and adds the correction.  The conjugate-node solutions stay in the row
+  // order of the factors (the accumulation applies perm_inv), so their residual is
+  // formed on a gathered copy.
+  int refine(hipStream_t s, int m, const T* rhs, const Coef& k) {
+    constexpr bool CPLX = is_cplx<T>::value;
+    const int64_t cnt = (int64_t)ne * n * m;
+    MF_TRY(widen<C>(s, cnt, Wf, irXf, false));
+    if (CPLX) MF_TRY(widen<C>(s, cnt, Wc, irYc, false));
+    for (int step = 0; step < ir_steps; ++step) {
+      MF_TRY(apply_nodes(s, Af, ldaf, m, irXf, irAX));
+      const c64* BXf = irXf;
+      if (Bf) {
+        MF_TRY(apply_nodes(s, Bf, ldbf, m, irXf, irBX));
+        BXf = irBX;
+      }
+      MF_TRY(ir_residual<T, C>(s, n, m, ne, rhs, m, k.cs, zdev, false, perm, irAX, BXf, Wf));
+      if (CPLX) {
+        MF_TRY(gather_rows_c64(s, n, m, ne, irYc, pinv, irT));
+        MF_TRY(apply_nodes(s, Af, ldaf, m, irT, irAX));
+        const c64* BXc = irT;
+        if (Bf) {
+          MF_TRY(apply_nodes(s, Bf, ldbf, m, irT, irBX));
+          BXc = irBX;
+        }
+        MF_TRY(ir_residual<T, C>(s, n, m, ne, rhs, m, k.cs, zdev, true, nullptr, irAX, BXc, Wc));
+      }
+      MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy));
+      MF_TRY(widen<C>(s, cnt, Wf, irXf, true));
+      if (CPLX) MF_TRY(widen<C>(s, cnt, Wc, irYc, true));
+    }
     return 0;
   }
 };
@@ -888,6 +961,7 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   nodes_for(fpm, emin, emax, zne, wne, z, w);
   if (fpm[41] == 1) {
     DenseOp<T, c32> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
+    op.ir_steps = fpm[49];
     return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w);
   }
   DenseOp<T, c64> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
@@ -1004,6 +1078,7 @@ void mfeast_init(int32_t* fpm) {
   fpm[41] = 1;   // fpm(42) single-precision solves
   fpm[44] = 1;   // fpm(45) BiCGStab accuracy 1e-1
   fpm[45] = 40;  // fpm(46) BiCGStab iterations
+  fpm[49] = 0;   // fpm(50) extra refinement steps of the FP32 solves (dense)
   fpm[50] = 0;   // fpm(51) seed of the random starting block
   fpm[51] = 0;   // fpm(52) per-class kernel timing (mfeast_get_profile) off
 }

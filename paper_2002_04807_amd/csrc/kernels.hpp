@@ -90,6 +90,17 @@ int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv,
 template <typename C>
 int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y);
 
+// Refinement of the FP32 contour solves (fpm(50)): dst = (add ? dst : 0) + widen(src);
+// row gather dst_j[r] = src_j[perm_inv_j[r]]; residual of node j's system (z_j B - A) x
+// = rhs diag(cs) (conj(z_j) for the conjugate node) from FP64 products AX, BX, written
+// (row-permuted by perm when given) in FP32.
+template <typename C>
+int widen(hipStream_t s, int64_t count, const C* src, c64* dst, bool add);
+int gather_rows_c64(hipStream_t s, int64_t n, int m, int ne, const c64* src, const int* perm_inv, c64* dst);
+template <typename T, typename C>
+int ir_residual(hipStream_t s, int64_t n, int m, int ne, const T* rhs, int64_t ld, const double* cs, const c64* z,
+                bool conj_z, const int* perm, const c64* AX, const c64* BX, C* out);
+
 // Q = (resid ? X*diag(rho) : 0) + diag-scaled sum over nodes (see accumulate in solve.hip).
 template <typename T, typename C>
 int accumulate(hipStream_t s, int64_t n, int m, int ne, const C* Wf, const C* Wc, const int* perm_inv,

@@ -294,6 +294,78 @@ int accumulate(hipStream_t s, int64_t n, int m, int ne, const C* Wf, const C* Wc
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// ---------------------------------------------------------------------------
+// Extra iterative refinement of the FP32 contour solves (fpm(50) steps): the
+// solutions are kept in FP64, their residuals against the FP64 operator are formed
+// with FP64 products, solved again with the FP32 factors and added.
+
+// dst = (add ? dst : 0) + widen(src), count elements
+template <typename C>
+__global__ void k_widen(int64_t count, const C* __restrict__ src, c64* __restrict__ dst, int add) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const c64 v = convert<c64, C>(src[e]);
+  dst[e] = add ? dst[e] + v : v;
+}
+
+template <typename C>
+int widen(hipStream_t s, int64_t count, const C* src, c64* dst, bool add) {
+  hipLaunchKernelGGL((k_widen<C>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, src, dst,
+                     add ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// dst_j[r][:] = src_j[perm_inv_j[r]][:]  (n x m per node)
+__global__ void k_gather_rows_c64(int64_t n, int m, const c64* __restrict__ src, const int* __restrict__ perm_inv,
+                                  c64* __restrict__ dst) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  const int64_t j = blockIdx.z;
+  if (c >= m) return;
+  const int64_t blk = n * (int64_t)m;
+  dst[j * blk + r * m + c] = src[j * blk + (int64_t)perm_inv[j * n + r] * m + c];
+}
+
+int gather_rows_c64(hipStream_t s, int64_t n, int m, int ne, const c64* src, const int* perm_inv, c64* dst) {
+  hipLaunchKernelGGL(k_gather_rows_c64, dim3((unsigned)((m + 255) / 256), (unsigned)n, (unsigned)ne), dim3(256), 0, s,
+                     n, m, src, perm_inv, dst);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Residual of node j's system (z_j B - A) x = b with b = rhs * diag(cs) (or the
+// conjugate node conj(z_j) for the conjugate-transpose solve of a Hermitian pencil):
+// r = b - z BX + AX, rounded to C.  out_j[i] = r[perm_j[i]] (forward solves take
+// permuted right-hand sides) or r[i] when perm is null.
+template <typename T, typename C>
+__global__ void k_ir_residual(int64_t n, int m, const T* __restrict__ rhs, int64_t ld, const double* __restrict__ cs,
+                              const c64* __restrict__ z, int conj_z, const int* __restrict__ perm,
+                              const c64* __restrict__ AX, const c64* __restrict__ BX, C* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  const int64_t j = blockIdx.z;
+  if (c >= m) return;
+  const int64_t blk = n * (int64_t)m;
+  const int64_t src = perm ? (int64_t)perm[j * n + i] : i;
+  const c64 zj = conj_z ? c64(z[j].re, -z[j].im) : z[j];
+  const c64 b = convert<c64, T>(rhs[src * ld + c]) * c64(cs[c], 0.0);
+  const c64 r = b - zj * BX[j * blk + src * m + c] + AX[j * blk + src * m + c];
+  out[j * blk + i * m + c] = convert<C, c64>(r);
+}
+
+template <typename T, typename C>
+int ir_residual(hipStream_t s, int64_t n, int m, int ne, const T* rhs, int64_t ld, const double* cs, const c64* z,
+                bool conj_z, const int* perm, const c64* AX, const c64* BX, C* out) {
+  hipLaunchKernelGGL((k_ir_residual<T, C>), dim3((unsigned)((m + 255) / 256), (unsigned)n, (unsigned)ne), dim3(256), 0,
+                     s, n, m, rhs, ld, cs, z, conj_z ? 1 : 0, perm, AX, BX, out);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template int widen<c32>(hipStream_t, int64_t, const c32*, c64*, bool);
+template int ir_residual<double, c32>(hipStream_t, int64_t, int, int, const double*, int64_t, const double*,
+                                      const c64*, bool, const int*, const c64*, const c64*, c32*);
+template int ir_residual<c64, c32>(hipStream_t, int64_t, int, int, const c64*, int64_t, const double*, const c64*,
+                                   bool, const int*, const c64*, const c64*, c32*);
+
 template int rhs_prepare<double, c32>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c32*, c32*);
 template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c64*, c64*);
 template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*);

@@ -187,3 +187,36 @@ def test_expert_contour_and_warnings():
     assert _run_gpu(A, None, 0.0, 0.5, 3, None, True)["info"] == 3
     assert _run_gpu(A, None, 0.0, 0.5, 20, None, True, extra={2: 16, 3: 0})["info"] == 2
     assert _run_gpu(A, -np.eye(n), 0.0, 0.5, 20, None, False)["info"] == -3
+
+
+@pytest.mark.parametrize("steps,bound", [(1, 1e-8), (2, 1e-11)])
+def test_first_contour_with_refined_fp32_solves(steps, bound):
+    """fpm(50) extra refinement steps: the FP32 solves of the first contour approach the
+    oracle's FP64 contour sum (a single FP32 solve stays near 1e-5, see above)."""
+    _say("first contour refined steps=%d" % steps)
+    n, m0 = 200, 70
+    A = gen.laplacian_1d_dense(n)
+    Y = oracle.initial_subspace(n, m0, 3, False)
+    out = _run_gpu(A, None, 0.0, 0.5, m0, Y, True, extra={13: 1, 49: steps})
+    ref = _run_oracle(A, None, 0.0, 0.5, m0, Y, extra={13: 1})
+    assert out["info"] == ref["info"] == 4
+    Q = out["X"].cpu().numpy()
+    rel = np.abs(Q - ref["X"]).max() / np.abs(ref["X"]).max()
+    assert rel < bound, rel
+
+
+def test_complex_generalized_with_refined_fp32_solves():
+    """fpm(50)=1 on a complex generalized pencil (both solve directions refined): the
+    result matches the oracle and converges no later than the plain FP64 form."""
+    n = 333
+    _say("complex generalized refined n=%d" % n)
+    A, B, lam, _ = gen.prescribed_complex_pencil(n, seed=n, lam_lo=-5, lam_hi=5)
+    emin, emax = -1.0, 1.0
+    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    m0 = int(np.ceil(1.5 * cnt)) + 3
+    Y = oracle.initial_subspace(n, m0, 1, True)
+    out = _run_gpu(A, B, emin, emax, m0, Y, True, extra={49: 1})
+    ref = _run_oracle(A, B, emin, emax, m0, Y)
+    _check(out, ref, emin, emax, B=B)
+    out64 = _run_gpu(A, B, emin, emax, m0, Y, False)
+    assert out["loop"] <= out64["loop"], (out["loop"], out64["loop"])
