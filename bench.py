@@ -26,10 +26,11 @@ sys.path.insert(0, ROOT)
 METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res≤1e-10"
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a plain
-# copy's reading, see profiles/), valid only while the kernel's source is unchanged
+# copy's reading, see profiles/), valid only while the kernels' sources are unchanged
 TRAFFIC = {
-    "lu_panel": {"bytes": 37.8e6 + 46.5e6, "source": "paper_2002_04807_amd/csrc/lu.hip",
-                 "sha256_16": "5d47ca3c081c32fe"},
+    "contour_solve": {"bytes": 7.035e9,
+                      "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
+                      "sha256_16": "66d0b2c896a7812f"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
@@ -108,11 +109,13 @@ KERNELS = {
 
 def _source_unchanged(entry):
     import hashlib
-    path = os.path.join(ROOT, entry["source"])
+    h = hashlib.sha256()
     try:
-        return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] == entry["sha256_16"]
+        for src in entry["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except OSError:
         return False
+    return h.hexdigest()[:16] == entry["sha256_16"]
 
 
 def roofline_of(prof):
