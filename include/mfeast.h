@@ -57,7 +57,8 @@ int mfeast_set_stream(mfeast_handle h, void* hip_stream);
  * FP32 contour solves of the dense drivers (default 0; each step forms the FP64
  * residual of every node's system and solves it again with the FP32 factors),
  * fpm(51) seed of the random starting block, fpm(52) = 1 records per-class kernel
- * timings for mfeast_get_profile. */
+ * timings for mfeast_get_profile, fpm(53) = 1 forms complex FP32 products with four
+ * real products instead of Gauss's three (default 0: three). */
 void mfeast_init(int32_t* fpm);
 
 /* Half-contour nodes and weights (zfeast_contour; Section 4.2 "Search contour",
@@ -92,7 +93,8 @@ int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t r
  *          weights (expert mode); NULL = generated from fpm(2), fpm(16), fpm(18)
  * fpm(42)=1 (default) factors and solves the shifted systems in complex FP32 with the
  * FP64 residual form of the iteration (plus fpm(50) refinement steps of each solve);
- * fpm(42)=0 uses complex FP64 throughout.  Return 150: fpm(50) outside 0..8. */
+ * fpm(42)=0 uses complex FP64 throughout.  Return 150: fpm(50) outside 0..8; 153:
+ * fpm(53) not 0 or 1. */
 int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda,
                  const double* B, int64_t ldb, int32_t* fpm, double emin, double emax,
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,

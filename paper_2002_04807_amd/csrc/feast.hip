@@ -128,6 +128,7 @@ static int check_fpm(const int32_t* fpm, bool expert) {
   if (f(14) != 0 && f(14) != 1) return 114;
   if (f(42) != 0 && f(42) != 1) return 142;
   if (f(50) < 0 || f(50) > 8) return 150;
+  if (f(53) != 0 && f(53) != 1) return 153;
   return 0;
 }
 
@@ -959,6 +960,7 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   T* Xt = reinterpret_cast<T*>(X);
   std::vector<c64> z, w;
   nodes_for(fpm, emin, emax, zne, wne, z, w);
+  set_gemm_3m(fpm[52] == 0);
   if (fpm[41] == 1) {
     DenseOp<T, c32> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
     op.ir_steps = fpm[49];
@@ -1001,6 +1003,7 @@ static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, con
   if (hipSetDevice(h->device) != hipSuccess) return -900;
   std::vector<c64> z, w;
   nodes_for(fpm, emin, emax, zne, wne, z, w);
+  set_gemm_3m(fpm[52] == 0);
   const double tol = std::pow(10.0, -fpm[44]);
   fpm[59] = 0;
   int info;
@@ -1081,6 +1084,7 @@ void mfeast_init(int32_t* fpm) {
   fpm[49] = 0;   // fpm(50) extra refinement steps of the FP32 solves (dense)
   fpm[50] = 0;   // fpm(51) seed of the random starting block
   fpm[51] = 0;   // fpm(52) per-class kernel timing (mfeast_get_profile) off
+  fpm[52] = 0;   // fpm(53) complex FP32 products: 0 three-product scheme, 1 four-product
 }
 
 int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct, double* zne, double* wne) {

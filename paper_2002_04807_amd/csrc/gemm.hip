@@ -58,7 +58,7 @@ template <> struct vec2<double> { using t = double2; };
 // padded to 16 mod 64 words, which puts the four k rows an MFMA operand read touches
 // on disjoint banks.
 template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
-          int TAG, bool SPLIT = false>
+          int TAG, bool SPLIT = false, bool G3M = false>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
@@ -110,9 +110,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
   const int kfirst = SPLIT ? sp * kchunk : 0;
   const int K = SPLIT ? min(g.K, kfirst + kchunk) : g.K;
 
-  acc_t acc[ES][FM][FN];
+  // complex products: four real passes (P_re += Ar Br - Ai Bi, P_im += Ar Bi + Ai Br), or
+  // with G3M the three of Gauss's scheme: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),
+  // re = P1 - P2, im = P3 - P1 - P2
+  constexpr int NACC = !CPLX ? 1 : (G3M ? 3 : 2);
+  acc_t acc[NACC][FM][FN];
 #pragma unroll
-  for (int e = 0; e < ES; ++e)
+  for (int e = 0; e < NACC; ++e)
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -213,15 +217,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[0][i][j] = M_::run(ar[i], br[j], acc[0][i][j]);
-      if constexpr (CPLX) {
+      if constexpr (CPLX && G3M) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acc[ES - 1][i][j] = M_::run(ar[i], bi[j], acc[ES - 1][i][j]);
+          for (int j = 0; j < FN; ++j) acc[1][i][j] = M_::run(ai[i], bi[j], acc[1][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) ai[i] = ar[i] + ai[i];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bi[j] = br[j] + bi[j];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acc[ES - 1][i][j] = M_::run(ai[i], br[j], acc[ES - 1][i][j]);
+          for (int j = 0; j < FN; ++j) acc[2][i][j] = M_::run(ai[i], bi[j], acc[2][i][j]);
+      } else if constexpr (CPLX) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[1][i][j] = M_::run(ar[i], bi[j], acc[1][i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[1][i][j] = M_::run(ai[i], br[j], acc[1][i][j]);
 #pragma unroll
         for (int i = 0; i < FM; ++i) ai[i] = -ai[i];
 #pragma unroll
@@ -231,6 +248,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
       }
     }
   }
+
+  // real and imaginary parts of the product tile
+  auto re_of = [&](int i, int j, int r) -> R {
+    if constexpr (CPLX && G3M) return acc[0][i][j][r] - acc[1][i][j][r];
+    else return acc[0][i][j][r];
+  };
+  auto im_of = [&](int i, int j, int r) -> R {
+    if constexpr (CPLX && G3M) return acc[2][i][j][r] - acc[0][i][j][r] - acc[1][i][j][r];
+    else return acc[NACC - 1][i][j][r];
+  };
 
   if constexpr (SPLIT) {
     // partial tile of split sp: part[(bz * nsplit + sp)][M][N] (interleaved complex)
@@ -245,8 +272,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
           const int gj = n0 + wn0 + j * 16 + (lane & 15);
           if (gi < M && gj < N) {
             const int64_t off = ((int64_t)gi * N + gj) * ES;
-            P[off] = acc[0][i][j][r];
-            if constexpr (CPLX) P[off + 1] = acc[ES - 1][i][j][r];
+            P[off] = re_of(i, j, r);
+            if constexpr (CPLX) P[off + 1] = im_of(i, j, r);
           }
         }
     return;
@@ -264,9 +291,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk
         const int gj = n0 + wn0 + j * 16 + (lane & 15);
         if (gi < M && gj < N) {
           const int64_t off = ((int64_t)gi * g.ldc + gj) * ES;
-          R vr = alpha * acc[0][i][j][r];
+          R vr = alpha * re_of(i, j, r);
           if constexpr (CPLX) {
-            R vi = alpha * acc[ES - 1][i][j][r];
+            R vi = alpha * im_of(i, j, r);
             if (use_c) {
               const V2 c = *reinterpret_cast<const V2*>(C + off);
               vr += beta * c.x;
@@ -344,23 +371,30 @@ static void* splitk_scratch(size_t bytes) {
   return b.first;
 }
 
-template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BM, int BN, int BK>
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BM, int BN, int BK, bool G3M>
 static void launch_tile(const GemmArgs& g, int batch, hipStream_t s) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch);
   if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
     if (g.tag == 1) {
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 1>), grid, dim3(256), 0, s, g, 1, 0,
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 1, false, G3M>), grid, dim3(256), 0, s, g, 1, 0,
                          (R*)nullptr);
       return;
     }
     if (g.tag == 2) {
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 2>), grid, dim3(256), 0, s, g, 1, 0,
+      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 2, false, G3M>), grid, dim3(256), 0, s, g, 1, 0,
                          (R*)nullptr);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0>), grid, dim3(256), 0, s, g, 1, 0, (R*)nullptr);
+  hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, false, G3M>), grid, dim3(256), 0, s, g, 1, 0,
+                     (R*)nullptr);
 }
+
+// Gauss's three-product complex scheme for FP32 products (measured 10-25% faster there;
+// with FP64 the third accumulator set lowers occupancy and it is slower)
+static thread_local bool g_3m = true;
+void set_gemm_3m(bool on) { g_3m = on; }
+bool gemm_3m() { return g_3m; }
 
 template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
 static void launch(const GemmArgs& g, int batch, hipStream_t s) {
@@ -387,7 +421,13 @@ static void launch(const GemmArgs& g, int batch, hipStream_t s) {
   }
   // 8-deep K slabs for FP32 (measured 3-7% faster there), 16-deep for FP64
   constexpr int TBK = sizeof(R) == 4 ? 8 : 16;
-  launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK>(g, batch, s);
+  if constexpr (CPLX && sizeof(R) == 4) {
+    if (g_3m) {
+      launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, true>(g, batch, s);
+      return;
+    }
+  }
+  launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, false>(g, batch, s);
 }
 
 template <typename R, bool CPLX, bool AM, bool CJ>

@@ -35,6 +35,10 @@ template <typename R, bool CPLX>
 int gemm_op(hipStream_t s, GemmOp opa, GemmOp opb, const GemmArgs& g, int batch);
 template <typename R, bool CPLX>
 int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batch);
+// complex FP32 products of the calling host thread use Gauss's three-product scheme
+// (default on; fpm(53) = 1 selects the four-product scheme for a call)
+void set_gemm_3m(bool on);
+bool gemm_3m();
 
 // ------------------------------------------------------------------ LU
 constexpr int LU_NB = 64;  // outer panel width of the blocked LU and of the blocked solves

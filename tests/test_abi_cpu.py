@@ -76,7 +76,7 @@ def test_argument_checks_in_table_order(name):
     assert _call(name, emin=1.0, emax=1.0) == 200
     for idx, val, code in [(1, 21, 102), (2, 17, 103), (3, -1, 104), (4, 2, 105), (5, 2, 106),
                            (13, 3, 114), (15, 2, 116), (17, 0, 118), (41, 2, 142), (49, 9, 150),
-                           (49, -1, 150)]:
+                           (49, -1, 150), (52, 2, 153)]:
         f = oracle.feastinit().astype(np.int32)
         f[idx] = val
         assert _call(name, fpm=f) == code, (idx, val)
