@@ -1,10 +1,10 @@
 // Block two-sided Jacobi eigensolver for the reduced Hermitian problem (gfx950).
 //
-// The m x m matrix (m up to 1024) is split into blocks of JB indices (8 by default;
-// 16 and 32 selectable).  Every round pairs the blocks with the round-robin (circle)
+// The m x m matrix (m up to 1024) is split into blocks of JB indices (8 by default,
+// 16 selectable).  Every round pairs the blocks with the round-robin (circle)
 // ordering; each pair (P, Q) forms a 2JB x 2JB Hermitian subproblem
-// [H_PP H_PQ; H_QP H_QQ] that one workgroup diagonalizes in LDS with a cyclic Jacobi
-// sweep (its own round-robin ordering of the 2JB local indices), giving a unitary
+// [H_PP H_PQ; H_QP H_QQ] on which one workgroup runs one cyclic Jacobi sweep in LDS
+// (its own round-robin ordering of the 2JB local indices), giving a unitary
 // U_PQ.  A second launch then applies all the round's U's at once: every super-block
 // H[I_i, I_j] becomes
 // U_i^H H[I_i, I_j] U_j (the pairs of a round are disjoint, so the super-blocks
@@ -27,6 +27,22 @@ __device__ inline T sgn_phase(T b, double ab);
 template <> __device__ inline double sgn_phase<double>(double b, double ab) { return b >= 0 ? 1.0 : -1.0; }
 template <> __device__ inline c64 sgn_phase<c64>(c64 b, double ab) { return c64(b.re / ab, b.im / ab); }
 
+// 1/sqrt(x) and 1/x for x > 0 from the hardware approximations plus three Newton steps
+// (each step squares the relative error, so full FP64 accuracy from any start within
+// about 1e-3)
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y = y * fma(-x, y, 2.0);
+  return y;
+}
+
 // block pair of round r, circle method over nbp (even) block indices
 __device__ inline void block_pair(int i, int r, int nbp, int& P, int& Q) {
   const int a = (i == 0) ? 0 : 1 + (i - 1 + r) % (nbp - 1);
@@ -40,118 +56,135 @@ template <int JB>
 __device__ inline int gidx(int l, int P, int Q) { return l < JB ? P * JB + l : Q * JB + (l - JB); }
 
 // ---------------------------------------------------------------------------
+// rotation of local pair (p, q) from the 2 x 2 diagonal block of S: c real, s complex
+template <typename T>
+__device__ inline int jrot(double app, double aqq, T apq, double tol, double abs_floor, double big_floor, double& c,
+                           T& sg) {
+  double ab2;
+  if constexpr (is_cplx<T>::value) ab2 = apq.re * apq.re + apq.im * apq.im;
+  else ab2 = apq * apq;
+  c = 1.0;
+  sg = T(0.0);
+  if (!(ab2 > tol * tol * fabs(app * aqq) && ab2 > abs_floor * abs_floor)) return 0;
+  const double inv_ab = rsqrt_nr(ab2);
+  const T ph = inv_ab * apq;
+  const double tau = (aqq - app) * 0.5 * inv_ab;
+  double t;
+  if (fabs(tau) > 1e150) {
+    t = 0.5 * rcp_nr(tau);
+  } else {
+    const double u = fma(tau, tau, 1.0);
+    const double h = u * rsqrt_nr(u);
+    t = (tau >= 0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + h);
+  }
+  c = rsqrt_nr(fma(t, t, 1.0));
+  sg = (t * c) * ph;
+  return (ab2 > big_floor * big_floor) ? 2 : 1;
+}
+
+// local pair i of round r (circle method over JS indices)
+template <int JS>
+__device__ inline void local_pair(int i, int r, int& p, int& q) {
+  const int a = (i == 0) ? 0 : 1 + (i - 1 + r) % (JS - 1);
+  const int b = 1 + (JS - 2 - i + r) % (JS - 1);
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// One cyclic sweep of the 2JB x 2JB subproblem.  S is double-buffered so that a round
+// needs one barrier: every thread computes the one or two rotations its own items need
+// from the current buffer (redundantly with other threads) and writes the rotated
+// values to the other buffer.  Items: the (JS/2)^2 2 x 2 blocks of S and the JS x JS/2
+// column pairs of U.
 template <typename T, int JB>
-__global__ __launch_bounds__(JT) void k_bj_sub(int m, int nbp, int round, const T* __restrict__ H,
-                                               T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol,
-                                               int inner_sweeps) {
+__global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, const T* __restrict__ H,
+                                                T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol) {
   constexpr int JS = 2 * JB;
-  __shared__ T S[JS][JS + 1];
+  constexpr int NSI = (JS / 2) * (JS / 2), NUI = JS * (JS / 2);
+  __shared__ T S[2][JS][JS + 1];
   __shared__ T U[JS][JS + 1];
-  __shared__ double rc[JS / 2];
-  __shared__ T rs[JS / 2];
-  __shared__ int rp[JS / 2], rq[JS / 2], rf[JS / 2];
   __shared__ int s_total;
   __shared__ double s_dmax;
   const int tid = threadIdx.x;
+  const int nt = blockDim.x;
   int P, Q;
   block_pair(blockIdx.x, round, nbp, P, Q);
-  for (int e = tid; e < JS * JS; e += JT) {
+  for (int e = tid; e < JS * JS; e += nt) {
     const int a = e / JS, c = e % JS;
     const int ga = gidx<JB>(a, P, Q), gc = gidx<JB>(c, P, Q);
-    S[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
+    S[0][a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
     U[a][c] = (a == c) ? T(1.0) : T(0.0);
   }
   if (tid == 0) s_total = 0;
   __syncthreads();
-  if (tid == 0) {
-    double d = 0.0;
-    for (int a = 0; a < JS; ++a) d = fmax(d, fabs(real_part(S[a][a])));
-    s_dmax = d;
+  if (tid < 64) {
+    double d = tid < JS ? fabs(real_part(S[0][tid][tid])) : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
+    if (tid == 0) s_dmax = d;
   }
   __syncthreads();
   const double abs_floor = 4.440892098500626e-16 * s_dmax + 1e-300;
-  // rotations of an element above this size keep the outer sweeps going; once a whole
-  // sweep rotates only smaller ones the remaining off-diagonal mass is second order in
-  // them (quadratic convergence), so no confirming sweep is needed
   const double big_floor = 1.0e-10 * s_dmax;
-  for (int sw = 0; sw < inner_sweeps; ++sw) {
-    int sweep_cnt = 0;
-    int big_cnt = 0;
-    for (int r = 0; r < JS - 1; ++r) {
-      // rotation of each local pair from the current 2 x 2 diagonal blocks
-      if (tid < JS / 2) {
-        const int a = (tid == 0) ? 0 : 1 + (tid - 1 + r) % (JS - 1);
-        const int b = 1 + (JS - 2 - tid + r) % (JS - 1);
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0;
-        T sg = T(0.0);
-        int f = 0;
-        const double app = real_part(S[p][p]), aqq = real_part(S[q][q]);
-        const T apq = S[p][q];
-        const double ab = absv<T>(apq);
-        if (ab > tol * sqrt(fabs(app * aqq)) && ab > abs_floor) {
-          const T ph = sgn_phase<T>(apq, ab);
-          const double tau = (aqq - app) / (2.0 * ab);
-          double t;
-          if (fabs(tau) > 1e150) t = 0.5 / tau;
-          else t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sg = (t * c) * ph;
-          f = 1;
-        }
-        rc[tid] = c;
-        rs[tid] = sg;
-        rp[tid] = p;
-        rq[tid] = q;
-        rf[tid] = f ? (ab > big_floor ? 2 : 1) : 0;
-      }
-      __syncthreads();
-      int cnt = 0, bigc = 0;
-      for (int i = 0; i < JS / 2; ++i) {
-        cnt += rf[i] ? 1 : 0;
-        bigc += rf[i] == 2 ? 1 : 0;
-      }
-      sweep_cnt += cnt;  // uniform: every thread read the same flags
-      big_cnt += bigc;
-      if (cnt == 0) {
-        __syncthreads();  // the flags are rewritten next round
-        continue;
-      }
-      // S <- J^H S J on the 32 x 32 grid of 2 x 2 blocks, U <- U J
-      for (int e = tid; e < (JS / 2) * (JS / 2); e += JT) {
+  int my_big = 0;
+  int cur = 0;
+  for (int r = 0; r < JS - 1; ++r) {
+    for (int e = tid; e < NSI + NUI; e += nt) {
+      if (e < NSI) {
         const int Pi = e / (JS / 2), Qi = e % (JS / 2);
-        if (!rf[Pi] && !rf[Qi]) continue;
-        const int p1 = rp[Pi], q1 = rq[Pi], p2 = rp[Qi], q2 = rq[Qi];
-        const double cP = rc[Pi], cQ = rc[Qi];
-        const T sP = rs[Pi], sQ = rs[Qi];
-        const T h11 = S[p1][p2], h12 = S[p1][q2], h21 = S[q1][p2], h22 = S[q1][q2];
-        const T t11 = cQ * h11 - h12 * conj(sQ);
-        const T t12 = h11 * sQ + cQ * h12;
-        const T t21 = cQ * h21 - h22 * conj(sQ);
-        const T t22 = h21 * sQ + cQ * h22;
-        S[p1][p2] = cP * t11 - sP * t21;
-        S[p1][q2] = cP * t12 - sP * t22;
-        S[q1][p2] = conj(sP) * t11 + cP * t21;
-        S[q1][q2] = conj(sP) * t12 + cP * t22;
+        int p1, q1, p2, q2;
+        local_pair<JS>(Pi, r, p1, q1);
+        local_pair<JS>(Qi, r, p2, q2);
+        double cP, cQ;
+        T sP, sQ;
+        const int fP = jrot<T>(real_part(S[cur][p1][p1]), real_part(S[cur][q1][q1]), S[cur][p1][q1], tol, abs_floor,
+                               big_floor, cP, sP);
+        const int fQ = (Qi == Pi) ? fP
+                                  : jrot<T>(real_part(S[cur][p2][p2]), real_part(S[cur][q2][q2]), S[cur][p2][q2],
+                                            tol, abs_floor, big_floor, cQ, sQ);
+        if (Qi == Pi) {
+          cQ = cP;
+          sQ = sP;
+          my_big += (fP == 2) ? 1 : 0;
+        }
+        const T h11 = S[cur][p1][p2], h12 = S[cur][p1][q2], h21 = S[cur][q1][p2], h22 = S[cur][q1][q2];
+        T o11 = h11, o12 = h12, o21 = h21, o22 = h22;
+        if (fP || fQ) {
+          const T t11 = cQ * h11 - h12 * conj(sQ);
+          const T t12 = h11 * sQ + cQ * h12;
+          const T t21 = cQ * h21 - h22 * conj(sQ);
+          const T t22 = h21 * sQ + cQ * h22;
+          o11 = cP * t11 - sP * t21;
+          o12 = cP * t12 - sP * t22;
+          o21 = conj(sP) * t11 + cP * t21;
+          o22 = conj(sP) * t12 + cP * t22;
+        }
+        S[cur ^ 1][p1][p2] = o11;
+        S[cur ^ 1][p1][q2] = o12;
+        S[cur ^ 1][q1][p2] = o21;
+        S[cur ^ 1][q1][q2] = o22;
+      } else {
+        const int u = e - NSI;
+        const int x = u / (JS / 2), Qi = u % (JS / 2);
+        int p2, q2;
+        local_pair<JS>(Qi, r, p2, q2);
+        double cQ;
+        T sQ;
+        if (jrot<T>(real_part(S[cur][p2][p2]), real_part(S[cur][q2][q2]), S[cur][p2][q2], tol, abs_floor, big_floor,
+                    cQ, sQ)) {
+          const T a = U[x][p2], b = U[x][q2];
+          U[x][p2] = cQ * a - b * conj(sQ);
+          U[x][q2] = a * sQ + cQ * b;
+        }
       }
-      for (int e = tid; e < JS * (JS / 2); e += JT) {
-        const int x = e / (JS / 2), Qi = e % (JS / 2);
-        if (!rf[Qi]) continue;
-        const int p2 = rp[Qi], q2 = rq[Qi];
-        const double cQ = rc[Qi];
-        const T sQ = rs[Qi];
-        const T a = U[x][p2], b = U[x][q2];
-        U[x][p2] = cQ * a - b * conj(sQ);
-        U[x][q2] = a * sQ + cQ * b;
-      }
-      __syncthreads();
     }
-    if (tid == 0) s_total += big_cnt;
-    if (sweep_cnt == 0) break;  // uniform
+    cur ^= 1;
+    __syncthreads();
   }
+  if (my_big) atomicAdd(&s_total, my_big);
   __syncthreads();
   T* Uo = Ubuf + (int64_t)blockIdx.x * JS * JS;
-  for (int e = tid; e < JS * JS; e += JT) Uo[e] = U[e / JS][e % JS];
+  for (int e = tid; e < JS * JS; e += nt) Uo[e] = U[e / JS][e % JS];
   if (tid == 0 && s_total > 0) atomicAdd(rotcount, s_total);
 }
 
@@ -280,7 +313,6 @@ template <typename T, int JB>
 static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
                            int max_sweeps) {
   constexpr int JS = 2 * JB;
-  static const int inner_sweeps = getenv("MFEAST_BJ_INNER") ? atoi(getenv("MFEAST_BJ_INNER")) : 1;
   const int nb = (m + JB - 1) / JB;
   const int nbp = nb + (nb & 1);
   const int npr = nbp / 2;
@@ -292,8 +324,7 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
   for (; sweep < max_sweeps; ++sweep) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
     for (int r = 0; r < nbp - 1; ++r) {
-      hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr), dim3(JT), 0, s, m, nbp, r, H, ubuf, counter, 1.0e-15,
-                         inner_sweeps);
+      hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr), dim3(JT), 0, s, m, nbp, r, H, ubuf, counter, 1.0e-15);
       hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(nh + nvrow * npr), dim3(JT), 0, s, m, nbp, r, H, V, ubuf);
     }
     if (hipMemcpyAsync(&hcount, counter, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
@@ -311,13 +342,12 @@ static int bj_width() {
   // 8-wide blocks measured fastest at M0 = 600: a 16 x 16 subproblem needs 15 inner
   // rounds instead of 31, which outweighs the doubled number of outer rounds
   static const int w = getenv("MFEAST_BJ_WIDTH") ? atoi(getenv("MFEAST_BJ_WIDTH")) : 8;
-  return (w == 32 || w == 8) ? w : 16;
+  return w == 16 ? 16 : 8;
 }
 
 template <typename T>
 int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
                  int max_sweeps) {
-  if (bj_width() == 32) return block_jacobi_jb<T, 32>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
   if (bj_width() == 8) return block_jacobi_jb<T, 8>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
   return block_jacobi_jb<T, 16>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
 }
