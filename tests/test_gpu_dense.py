@@ -220,3 +220,18 @@ def test_complex_generalized_with_refined_fp32_solves():
     _check(out, ref, emin, emax, B=B)
     out64 = _run_gpu(A, B, emin, emax, m0, Y, False)
     assert out["loop"] <= out64["loop"], (out["loop"], out64["loop"])
+
+
+def test_four_product_scheme_matches_oracle():
+    """fpm(53)=1: the complex FP32 products use four real products instead of Gauss's
+    three; same parity bar on a complex generalized pencil with a ragged tail."""
+    n = 333
+    _say("complex generalized four-product n=%d" % n)
+    A, B, lam, _ = gen.prescribed_complex_pencil(n, seed=n + 1, lam_lo=-5, lam_hi=5)
+    emin, emax = -1.0, 1.0
+    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    m0 = int(np.ceil(1.5 * cnt)) + 3
+    Y = oracle.initial_subspace(n, m0, 2, True)
+    out = _run_gpu(A, B, emin, emax, m0, Y, True, extra={52: 1})
+    ref = _run_oracle(A, B, emin, emax, m0, Y)
+    _check(out, ref, emin, emax, B=B)
