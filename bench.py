@@ -100,7 +100,8 @@ KERNELS = {
     "lu_panel": ("k_leaf + k_leaf_update (recursive panel)", "alu", "fp32_vector", "one 64-column panel of all 8 nodes"),
     "lu_trailing_gemm": ("k_gemm (LU trailing update)", "mfma", "fp32_mfma", "one trailing update, all nodes"),
     "contour_solve": ("k_gemm (panel-inverse products and updates of the block solves)", "mfma", "fp32_mfma",
-                      "one direction (L and U sweeps) of the block solves, all 8 nodes"),
+                      "one contour's block solves, all 8 nodes: the forward (L, U) and the "
+                      "conjugate-transpose (U^H, L^H) sweeps, which run concurrently on two streams"),
     "rr_gemm": ("k_gemm (FP64 Rayleigh-Ritz)", "mfma", "fp64_mfma", "one FP64 product"),
     "reduced_eig": ("k_bj_sub + k_bj_upd (block Jacobi)", "alu", "fp64_vector",
                     "one reduced eigensolve (48 m^3 flops per Jacobi sweep)"),

@@ -11,7 +11,7 @@
 namespace mf {
 
 enum Slot {
-  S_LU, S_DINV, S_PANINV, S_WY, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
+  S_LU, S_DINV, S_PANINV, S_WY, S_WY2, S_IPIV, S_PERM, S_PINV, S_INFO, S_Z, S_WF, S_WC,
   S_X, S_Q, S_R, S_AQ, S_BQ, S_AX, S_BX, S_AF, S_BF,
   S_S, S_T, S_HW, S_V, S_G, S_TG, S_C, S_Z2, S_GZ, S_W,
   S_SMALL, S_PART, S_FLAG,
@@ -69,6 +69,10 @@ struct mfeast_ctx {
   mf::CsrWork csrA, csrB;
   std::vector<mfeast_ctx*> workers;  // batched calls: one handle and stream per worker thread
   bool owns_stream = false;
+  // second stream and two events: the conjugate-transpose solves of the complex
+  // Hermitian drivers run there next to the forward ones
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double timing[8] = {};
   double prof[mf::K_NCLASS * 4] = {};
 
@@ -82,6 +86,26 @@ struct mfeast_ctx {
       cap[s] = bytes;
     }
     return buf[s];
+  }
+  bool ensure_aux() {
+    if (aux != nullptr) return true;
+    if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+      aux = nullptr;
+      return false;
+    }
+    if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess) {
+      release_aux();
+      return false;
+    }
+    return true;
+  }
+  void release_aux() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
+    ev_fork = ev_join = nullptr;
+    aux = nullptr;
   }
   char* host(size_t bytes) {
     if (pinned_cap < bytes) {

@@ -187,7 +187,9 @@ struct DenseOp : Operator<T> {
   const T* Af = nullptr;
   const T* Bf = nullptr;
   int64_t ldaf = 0, ldbf = 0;
-  C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr, *Wy = nullptr, *Pinv = nullptr;
+  C *LU = nullptr, *Dinv = nullptr, *Wf = nullptr, *Wc = nullptr, *Wy = nullptr, *Wy2 = nullptr, *Pinv = nullptr;
+  SolveSide<C> side{};
+  bool two_streams = false;  // the conjugate-transpose solves on the handle's second stream
   int *ipiv = nullptr, *perm = nullptr, *pinv = nullptr, *linfo = nullptr;
   c64* zdev = nullptr;
   // fpm(50): extra refinement steps of the FP32 solves (FP64 solutions and residuals)
@@ -214,6 +216,12 @@ struct DenseOp : Operator<T> {
     Wf = (C*)h->ws(S_WF, (size_t)ne * n * m0max * szC);
     Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * n * m0max * szC) : nullptr;
     Wy = (C*)h->ws(S_WY, (size_t)ne * n * m0max * szC);
+    if (CPLX && h->ensure_aux()) {
+      Wy2 = (C*)h->ws(S_WY2, (size_t)ne * n * m0max * szC);
+      if (!Wy2) return -2;
+      side = SolveSide<C>{h->aux, h->ev_fork, h->ev_join, Wy2};
+      two_streams = true;
+    }
     Pinv = (C*)h->ws(S_PANINV, (size_t)ne * panel_inverse_entries(n) * szC);
     if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Wy || !Pinv) return -2;
     if (ir_steps > 0 && sizeof(C) == sizeof(c32)) {
@@ -279,7 +287,7 @@ struct DenseOp : Operator<T> {
     int tok = prof_begin(s);
     MF_TRY(rhs_prepare<T, C>(s, n, m, rhs, m, k.cs, ne, perm, Wf, Wc));
     prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
-    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy));
+    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy, two_streams ? &side : nullptr));
     if (sizeof(C) == sizeof(c32) && irXf != nullptr) {
       if constexpr (sizeof(C) == sizeof(c32)) MF_TRY(refine(s, m, rhs, k));
       tok = prof_begin(s);
@@ -339,7 +347,7 @@ struct DenseOp : Operator<T> {
         }
         MF_TRY(ir_residual<T, C>(s, n, m, ne, rhs, m, k.cs, zdev, true, nullptr, irAX, BXc, Wc));
       }
-      MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy));
+      MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy, two_streams ? &side : nullptr));
       MF_TRY(widen<C>(s, cnt, Wf, irXf, true));
       if (CPLX) MF_TRY(widen<C>(s, cnt, Wc, irYc, true));
     }
@@ -1050,6 +1058,7 @@ int mfeast_destroy(mfeast_handle h) {
     if (h->buf[i]) (void)hipFree(h->buf[i]);
   h->csrA.release();
   h->csrB.release();
+  h->release_aux();
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->pinned_i) (void)hipHostFree(h->pinned_i);
   delete h;

@@ -91,8 +91,17 @@ int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv,
 // (LU_j)^H y = W_j for the conjugate direction (unpermuted on output; perm_inv is
 // applied by the accumulation).  Results overwrite Wf / Wc; Y (n x m per node) is
 // scratch.  All nodes batched.
+// The conjugate-transpose direction on a second stream (s2, with its own ping-pong
+// buffer Y2 of n x m per node) next to the forward one on s; s waits for it.
 template <typename C>
-int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y);
+struct SolveSide {
+  hipStream_t s2;
+  hipEvent_t fork, join;
+  C* Y2;
+};
+template <typename C>
+int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y,
+             const SolveSide<C>* side = nullptr);
 
 // Refinement of the FP32 contour solves (fpm(50)): dst = (add ? dst : 0) + widen(src);
 // row gather dst_j[r] = src_j[perm_inv_j[r]]; residual of node j's system (z_j B - A) x

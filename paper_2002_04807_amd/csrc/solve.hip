@@ -179,7 +179,8 @@ int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv,
 }
 
 template <typename C>
-int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y) {
+int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y,
+             const SolveSide<C>* side) {
   using R = typename real_of<C>::type;
   const int64_t wstride = n * (int64_t)m;
   const int64_t ld = lu_ld(n);
@@ -188,7 +189,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
   const int64_t sq = (int64_t)TRSM_PH * TRSM_PH;
   const int64_t pstride = (int64_t)panel_inverse_entries(n);
   // one sweep: rows of the right-hand sides in `in`, solution to `out` (in is consumed)
-  auto sweep = [&](const C* in0, C* out, bool desc, bool herm) -> int {
+  auto sweep = [&](hipStream_t st, const C* in0, C* out, bool desc, bool herm) -> int {
     C* in = const_cast<C*>(in0);
     for (int64_t q = 0; q < npan; ++q) {
       const int64_t p = desc ? npan - 1 - q : q;
@@ -201,7 +202,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
       d.B = in + p0 * m; d.ldb = m; d.b_bs = wstride;
       d.C = out + p0 * m; d.ldc = m; d.c_bs = wstride;
       d.alpha = 1.0; d.beta = 0.0;
-      if (gemm<R, true>(s, herm, herm, d, ne)) return -2;
+      if (gemm<R, true>(st, herm, herm, d, ne)) return -2;
       // rows beyond the panel: in_rest -= A out_P
       GemmArgs g{};
       g.N = m; g.K = (int)ph;
@@ -223,21 +224,34 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
         // U: rows above the panel, its columns; L^H: M-contiguous view of the panel's L rows
         g.A = herm ? LU + p0 * ld : LU + p0;
       }
-      if (gemm<R, true>(s, herm, herm, g, ne)) return -2;
+      if (gemm<R, true>(st, herm, herm, g, ne)) return -2;
     }
     return 0;
   };
   // algorithmic work of one direction: 8 n^2 m flops per node (L and U sweeps)
   const double dir_flops = 8.0 * (double)n * n * m * ne;
   const double dir_bytes = (double)sizeof(C) * ne * ((double)n * n + 2.0 * n * m);
+  if (Wc != nullptr && side != nullptr) {
+    // both directions at once: they share only the factors, which they read; the
+    // conjugate-transpose one runs on side->s2 with its own ping-pong buffer
+    const int tok = prof_begin(s);
+    if (hipEventRecord(side->fork, s) != hipSuccess) return -2;
+    if (hipStreamWaitEvent(side->s2, side->fork, 0) != hipSuccess) return -2;
+    if (sweep(side->s2, Wc, side->Y2, false, true) || sweep(side->s2, side->Y2, Wc, true, true)) return -2;
+    if (hipEventRecord(side->join, side->s2) != hipSuccess) return -2;
+    if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
+    if (hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return -2;
+    prof_end(tok, s, K_SOLVE_GEMM, 2.0 * dir_flops, 2.0 * dir_bytes);
+    return 0;
+  }
   // forward direction: L (W -> Y) then U (Y -> W)
   int tok = prof_begin(s);
-  if (sweep(Wf, Y, false, false) || sweep(Y, Wf, true, false)) return -2;
+  if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
   prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   if (Wc == nullptr) return 0;
   // conjugate-transpose direction: U^H (lower) then L^H (unit upper)
   tok = prof_begin(s);
-  if (sweep(Wc, Y, false, true) || sweep(Y, Wc, true, true)) return -2;
+  if (sweep(s, Wc, Y, false, true) || sweep(s, Y, Wc, true, true)) return -2;
   prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
   return 0;
 }
@@ -370,8 +384,10 @@ template int rhs_prepare<double, c32>(hipStream_t, int64_t, int, const double*, 
 template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c64*, c64*);
 template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*);
 template int rhs_prepare<c64, c64>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c64*, c64*);
-template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*, c32*);
-template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*, c64*);
+template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*, c32*,
+                          const SolveSide<c32>*);
+template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*, c64*,
+                          const SolveSide<c64>*);
 template int panel_inverses<c32>(hipStream_t, int64_t, int, const c32*, const c32*, c32*);
 template int panel_inverses<c64>(hipStream_t, int64_t, int, const c64*, const c64*, c64*);
 template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
