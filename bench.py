@@ -25,12 +25,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res≤1e-10"
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a plain
-# copy's reading, see profiles/), valid only while the kernels' sources are unchanged
+# HBM bytes per launch unit from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
+# plain copy's readings), valid while the listed sources hash to the profiled ones
 TRAFFIC = {
-    "contour_solve": {"bytes": 7.166e9,
+    "contour_solve": {"bytes": 14.35e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "155e699a69dc56f8"},
+                      "sha256_16": "65c51ab4b88fb20e"},
+    "reduced_eig": {"bytes": 4.05e9,
+                    "sources": ["paper_2002_04807_amd/csrc/eig.hip"],
+                    "sha256_16": "8efddfe75f4eece4"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
