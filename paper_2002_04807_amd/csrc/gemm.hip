@@ -57,9 +57,15 @@ template <> struct vec2<double> { using t = double2; };
 // is multiplied out of LDS, so the load latency hides behind the MFMAs.  LDS rows are
 // padded to 16 mod 64 words, which puts the four k rows an MFMA operand read touches
 // on disjoint banks.
+// Workgroups of 4 waves per compute unit the register allocation has to leave room for:
+// 3 for complex FP64 (the accumulators move from AGPRs into VGPRs; 12-15% faster on the
+// LU and solve shapes than at 2), 5 for FP32 (1-8% faster than at 4).
+template <typename R, bool CPLX>
+constexpr int gemm_min_blocks() { return (sizeof(R) == 8 && CPLX) ? 3 : (sizeof(R) == 4 ? 5 : 1); }
+
 template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
           int TAG, bool SPLIT = false, bool G3M = false>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
+__global__ __launch_bounds__(256, (gemm_min_blocks<R, CPLX>())) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
   using V2 = typename vec2<R>::t;
