@@ -208,3 +208,23 @@ def test_invalid_csr_is_rejected_on_device():
     assert out["info"] == -105
     out = mf.feast_csr((v, p + 1, c), 0.0, 1.0, 8, index_base=0)
     assert out["info"] == -105
+
+
+def test_laplacian_64cube_full_size():
+    """The benchmark configuration: 64^3 Laplacian (n = 262144), [0, 0.08] (69 eigenvalues
+    with degenerate triples), M0 = 160, 16 trapezoidal nodes on a circle, BiCGSTAB to 1e-4
+    (at most 2000 iterations) in complex FP32, residual bar 1e-10; held to the closed form
+    (the oracle cannot run at this size within a test)."""
+    nx = 64
+    _say("ifeast 64^3 full size")
+    v, p, c = _laplacian(nx)
+    dev = torch.device("cuda:0")
+    csr = (torch.tensor(v, device=dev), torch.tensor(p, device=dev), torch.tensor(c, device=dev))
+    f = mf.mfeast_init_ifeast()
+    f[1], f[2], f[44], f[45] = 16, 10, 4, 2000
+    out = mf.feast_csr(csr, 0.0, 0.08, 160, fpm=f)
+    torch.cuda.synchronize()
+    _say("ifeast 64^3: info %d M %d loop %d fpm60 %d" % (out["info"], out["M"], out["loop"], out["fpm60"]))
+    assert out["info"] == 0
+    _closed_form_check(out, nx, nx, nx, 0.0, 0.08, 69)
+    assert np.all(out["res"].cpu().numpy()[:69] <= 1e-10)
