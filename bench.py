@@ -28,9 +28,9 @@ METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res
 # HBM bytes per launch unit from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
 # plain copy's readings), valid while the listed sources hash to the profiled ones
 TRAFFIC = {
-    "contour_solve": {"bytes": 14.35e9,
+    "contour_solve": {"bytes": 14.05e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "65c51ab4b88fb20e"},
+                      "sha256_16": "c3fcf19cca226602"},
     "reduced_eig": {"bytes": 4.05e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip"],
                     "sha256_16": "8efddfe75f4eece4"},
