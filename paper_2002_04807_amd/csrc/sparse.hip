@@ -339,6 +339,26 @@ __device__ inline void bi_store_partials(const double (&acc)[NQ], double* part, 
   }
 }
 
+// the same, reusing a caller's LDS block (at least NQ * 2 KB) that other code of the
+// kernel used before: the leading barrier ends those uses
+template <int NQ>
+__device__ inline void bi_store_partials_in(const double (&acc)[NQ], double* part, int nrb, int ncol, int c,
+                                            double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[(q * BI_WAVES + w) * BI_TILE + lane] = acc[q];
+  __syncthreads();
+  if (w == 0 && c >= 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double v = red[(q * BI_WAVES + 0) * BI_TILE + lane] + red[(q * BI_WAVES + 1) * BI_TILE + lane] +
+                       red[(q * BI_WAVES + 2) * BI_TILE + lane] + red[(q * BI_WAVES + 3) * BI_TILE + lane];
+      part[((int64_t)q * nrb + blockIdx.x) * ncol + c] = v;
+    }
+  }
+}
+
 // rows of this wave
 struct RowRange {
   int64_t r0, r1;
@@ -347,6 +367,38 @@ __device__ inline RowRange bi_rows(int64_t n) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t r0 = (int64_t)blockIdx.x * BI_RB + (int64_t)w * BI_RW;
   return {r0, (r0 + BI_RW < n) ? r0 + BI_RW : n};
+}
+
+// A's rows of one wave staged in LDS (row pointers relative to the first entry, column
+// indices, values), so that a row's gathers wait only for LDS and not for the chain of
+// global loads rp -> ci -> operand.  Waves whose rows hold more than BI_CAP entries read
+// A from global memory as before.
+constexpr int BI_CAP = 512;
+template <typename R>
+struct BiStage {
+  int rp[BI_RW + 1];
+  int ci[BI_CAP];
+  R va[BI_CAP];
+};
+template <typename R, int NQ>
+constexpr size_t bi_lds_bytes() {
+  return (BI_WAVES * sizeof(BiStage<R>) > (size_t)NQ * BI_WAVES * BI_TILE * sizeof(double))
+             ? BI_WAVES * sizeof(BiStage<R>)
+             : (size_t)NQ * BI_WAVES * BI_TILE * sizeof(double);
+}
+template <typename R>
+__device__ inline bool bi_stage_rows(BiStage<R>& S, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                     const R* __restrict__ va, int64_t r0, int64_t r1, int lane) {
+  if (r1 <= r0) return false;
+  const int kb0 = rp[r0], ke1 = rp[r1];
+  if (ke1 - kb0 > BI_CAP) return false;
+  const int nr = (int)(r1 - r0);
+  for (int l = lane; l <= nr; l += 64) S.rp[l] = rp[r0 + l] - kb0;
+  for (int k = lane; k < ke1 - kb0; k += 64) {
+    S.ci[k] = ci[kb0 + k];
+    S.va[k] = va[kb0 + k];
+  }
+  return true;
 }
 
 // sum_k M(i, k) in(k) over one sparse row, eight entries in flight at a time; `get`
@@ -422,18 +474,32 @@ __global__ __launch_bounds__(256) void k_bi_sweep_a(BiK<C> a) {
   const C* __restrict__ p = a.p + tb;
   C* __restrict__ v = a.v + tb;
   auto get = [&](int64_t k) { return p[k * BI_TILE]; };
-  for (int64_t i = rr.r0; i < rr.r1; ++i) {
-    const int kb = a.rp[i], ke = a.rp[i + 1];
-    if (!act) continue;
-    const C sa = bi_row_dot<C, R>(a.ci, a.va, kb, ke, get);
+  __shared__ __align__(16) char lds[bi_lds_bytes<R, 2>()];
+  BiStage<R>& S = reinterpret_cast<BiStage<R>*>(lds)[threadIdx.x >> 6];
+  const bool staged = bi_stage_rows<R>(S, a.rp, a.ci, a.va, rr.r0, rr.r1, lane);
+  __syncthreads();
+  auto row = [&](int64_t i, const C& sa) {
     const C sb = (a.rpb == nullptr) ? get(i) : bi_row_dot<C, R>(a.cib, a.vb, a.rpb[i], a.rpb[i + 1], get);
     const C o = z * sb - sa;
     v[i * BI_TILE] = o;
     const double h = (double)a.bh[i * a.m0 + q];
     acc[0] += h * (double)o.re;
     acc[1] += h * (double)o.im;
+  };
+  if (staged) {
+    for (int64_t i = rr.r0; i < rr.r1; ++i) {
+      const int kb = S.rp[i - rr.r0], ke = S.rp[i - rr.r0 + 1];
+      if (!act) continue;
+      row(i, bi_row_dot<C, R>(S.ci, S.va, kb, ke, get));
+    }
+  } else {
+    for (int64_t i = rr.r0; i < rr.r1; ++i) {
+      const int kb = a.rp[i], ke = a.rp[i + 1];
+      if (!act) continue;
+      row(i, bi_row_dot<C, R>(a.ci, a.va, kb, ke, get));
+    }
   }
-  bi_store_partials<2>(acc, a.part, a.nrb, a.ldp, act ? c : -1);
+  bi_store_partials_in<2>(acc, a.part, a.nrb, a.ldp, act ? c : -1, reinterpret_cast<double*>(lds));
 }
 
 // sweep B: s = r - alpha v (not stored), t = z_j (B s) - A s;
@@ -462,10 +528,11 @@ __global__ __launch_bounds__(256) void k_bi_sweep_b(BiK<C> a) {
   const C* __restrict__ v = a.v + tb;
   C* __restrict__ t = a.t + tb;
   auto get = [&](int64_t k) { return r[k * BI_TILE] - al * v[k * BI_TILE]; };
-  for (int64_t i = rr.r0; i < rr.r1; ++i) {
-    const int kb = a.rp[i], ke = a.rp[i + 1];
-    if (!act) continue;
-    const C sa = bi_row_dot<C, R>(a.ci, a.va, kb, ke, get);
+  __shared__ __align__(16) char lds[bi_lds_bytes<R, BI_NQ>()];
+  BiStage<R>& S = reinterpret_cast<BiStage<R>*>(lds)[threadIdx.x >> 6];
+  const bool staged = bi_stage_rows<R>(S, a.rp, a.ci, a.va, rr.r0, rr.r1, lane);
+  __syncthreads();
+  auto row = [&](int64_t i, const C& sa) {
     const C si = get(i);
     const C sb = (a.rpb == nullptr) ? si : bi_row_dot<C, R>(a.cib, a.vb, a.rpb[i], a.rpb[i + 1], get);
     const C o = z * sb - sa;
@@ -480,8 +547,21 @@ __global__ __launch_bounds__(256) void k_bi_sweep_b(BiK<C> a) {
     acc[5] += tre * sim - tim * sre;
     acc[6] += tre * tre + tim * tim;
     acc[7] += sre * sre + sim * sim;
+  };
+  if (staged) {
+    for (int64_t i = rr.r0; i < rr.r1; ++i) {
+      const int kb = S.rp[i - rr.r0], ke = S.rp[i - rr.r0 + 1];
+      if (!act) continue;
+      row(i, bi_row_dot<C, R>(S.ci, S.va, kb, ke, get));
+    }
+  } else {
+    for (int64_t i = rr.r0; i < rr.r1; ++i) {
+      const int kb = a.rp[i], ke = a.rp[i + 1];
+      if (!act) continue;
+      row(i, bi_row_dot<C, R>(a.ci, a.va, kb, ke, get));
+    }
   }
-  bi_store_partials<BI_NQ>(acc, a.part, a.nrb, a.ldp, act ? c : -1);
+  bi_store_partials_in<BI_NQ>(acc, a.part, a.nrb, a.ldp, act ? c : -1, reinterpret_cast<double*>(lds));
 }
 
 // sweep C: x += alpha p + omega s, r' = s - omega t, p' = r' + beta (p - omega v);
