@@ -307,20 +307,30 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
 #pragma unroll
     for (int c = 0; c < IB; ++c) Lsub[tid][c] = v[0][c];
   }
-  // ---- list of the rows the interchanges touch (local indices), and the swap sequence
-  if (tid == 0) {
-    int nr = 0;
-    auto slot = [&](int r) {
-      for (int e = 0; e < nr; ++e)
-        if (s_rows[e] == r) return e;
-      s_rows[nr] = r;
-      return nr++;
-    };
-    for (int j = 0; j < ibc; ++j) {
-      s_swa[j] = slot(j);
-      s_swb[j] = slot(s_ipiv[j]);
+  // ---- list of the rows the interchanges touch (local indices) in order of first
+  //      appearance in the sequence j, ipiv[j], j+1, ipiv[j+1], ...; and the swap
+  //      sequence as slots of that list.  One wavefront: lane e holds the e-th row of the
+  //      sequence, finds its first occurrence, and counts the distinct rows before it.
+  if (tid < 64) {
+    const int e = tid;
+    const bool live = e < 2 * ibc;
+    const int r = !live ? -1 : ((e & 1) ? s_ipiv[e >> 1] : (e >> 1));
+    int first = e;  // lowest lane holding the same row
+#pragma unroll
+    for (int f = 0; f < 2 * IB; ++f) {
+      const int rf = __shfl(r, f);
+      if (f < first && rf == r) first = f;
     }
-    s_nrows = nr;
+    const bool is_first = live && first == e;
+    const unsigned long long firsts = __ballot(is_first);
+    const int my_slot = __popcll(firsts & ((1ull << e) - 1ull));  // valid on first lanes
+    const int slot = __shfl(my_slot, first);
+    if (is_first) s_rows[my_slot] = r;
+    if (live) {
+      if (e & 1) s_swb[e >> 1] = slot;
+      else s_swa[e >> 1] = slot;
+    }
+    if (e == 0) s_nrows = __popcll(firsts);
   }
   __syncthreads();
   const int nr = s_nrows;
@@ -335,10 +345,23 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
     const bool is_perm = (tid == LU_NB);
     const int cc = tid;
     const int64_t col = is_perm ? 0 : ((cc < jb) ? (k + cc) : (k + cc + ibc));
-    for (int e = 0; e < nr; ++e) {
-      const int64_t row = row0 + s_rows[e];
-      if (is_perm) opv[e] = perm[row];
-      else oval[e][cc] = LU[row * ld + col];
+    // all the gathers are issued before the first one is used
+    C gv[2 * IB];
+    int gp[2 * IB];
+#pragma unroll
+    for (int e = 0; e < 2 * IB; ++e) {
+      if (e < nr) {
+        const int64_t row = row0 + s_rows[e];
+        if (is_perm) gp[e] = perm[row];
+        else gv[e] = LU[row * ld + col];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * IB; ++e) {
+      if (e < nr) {
+        if (is_perm) opv[e] = gp[e];
+        else oval[e][cc] = gv[e];
+      }
     }
     for (int j = 0; j < ibc; ++j) {
       const int a = s_swa[j], b = s_swb[j];
