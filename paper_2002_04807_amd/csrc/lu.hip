@@ -160,8 +160,8 @@ __device__ inline void store_row(C* p, const C (&in)[N]) {
   }
 }
 
-template <typename C, int IB, int RMAX>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, int k, int jb, int nbc, C* __restrict__ LUall,
+template <typename C, int IB, int RMAX, int NT = LEAF_THREADS>
+__global__ __launch_bounds__(NT) void k_leaf(int64_t n, int64_t ld, int k, int jb, int nbc, C* __restrict__ LUall,
                                                          int* __restrict__ ipiv_all, int* __restrict__ perm_all,
                                                          int* __restrict__ info_all) {
   using R = typename real_of<C>::type;
@@ -178,8 +178,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
   __shared__ C prow[IB], crow[IB];
   __shared__ C Lsub[IB][IB];
   using PK = pivot_key<R>;
-  __shared__ typename PK::K red_k[LEAF_THREADS / 64];
-  __shared__ unsigned red_i[LEAF_THREADS / 64];
+  __shared__ typename PK::K red_k[NT / 64];
+  __shared__ unsigned red_i[NT / 64];
   __shared__ int s_zero;
   // rows touched by the interchanges: the leaf's top rows and the pivot rows
   __shared__ int s_rows[2 * IB];
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
   C v[RMAX][IB];
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
-    const int r = tid + t * LEAF_THREADS;
+    const int r = tid + t * NT;
     if (r < mr) load_row<C, IB>(LU + (row0 + r) * ld + row0, v[t]);
 #pragma unroll
     for (int c = 0; c < IB; ++c)
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
     unsigned bi = 0xFFFFFFFFu;
 #pragma unroll
     for (int t = 0; t < RMAX; ++t) {
-      const int r = tid + t * LEAF_THREADS;
+      const int r = tid + t * NT;
       const typename PK::K key = PK::of(abs1(v[t][j]), r >= j && r < mr);
       if (key > best) {
         best = key;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
     typename PK::K bk = red_k[0];
     unsigned bu = red_i[0];
 #pragma unroll
-    for (int w = 1; w < LEAF_THREADS / 64; ++w) {
+    for (int w = 1; w < NT / 64; ++w) {
       const typename PK::K ok = red_k[w];
       const unsigned oi = red_i[w];
       if (ok > bk || (ok == bk && oi < bu)) {
@@ -246,10 +246,10 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
     const int p = bx;
     if (tid == 0) s_ipiv[j] = p;
     // ---- exchange local rows j and p through LDS
-    if (tid == (p & (LEAF_THREADS - 1))) {
+    if (tid == (p & (NT - 1))) {
 #pragma unroll
       for (int t = 0; t < RMAX; ++t)
-        if (t == (p / LEAF_THREADS))
+        if (t == (p / NT))
 #pragma unroll
           for (int c = 0; c < IB; ++c) prow[c] = v[t][c];
     }
@@ -262,10 +262,10 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
 #pragma unroll
       for (int c = 0; c < IB; ++c) v[0][c] = prow[c];
     }
-    if (p != j && tid == (p & (LEAF_THREADS - 1))) {
+    if (p != j && tid == (p & (NT - 1))) {
 #pragma unroll
       for (int t = 0; t < RMAX; ++t)
-        if (t == (p / LEAF_THREADS))
+        if (t == (p / NT))
 #pragma unroll
           for (int c = 0; c < IB; ++c) v[t][c] = crow[c];
     }
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
     const C inv = ok ? cdiv(C(1), piv) : C(0);
 #pragma unroll
     for (int t = 0; t < RMAX; ++t) {
-      const int r = tid + t * LEAF_THREADS;
+      const int r = tid + t * NT;
       if (r > j && r < mr && ok) {
         C l = C(0);
 #pragma unroll
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(int64_t n, int64_t ld, in
   // (columns past ibc are padding of the last block and receive zeros)
 #pragma unroll
   for (int t = 0; t < RMAX; ++t) {
-    const int r = tid + t * LEAF_THREADS;
+    const int r = tid + t * NT;
     if (r < mr) store_row<C, IB>(LU + (row0 + r) * ld + row0, v[t]);
   }
   if (tid < ibc) {
@@ -432,10 +432,10 @@ __global__ __launch_bounds__(256) void k_leaf_update(int64_t n, int64_t ld, int 
   }
 }
 
-template <typename C, int IB, int RMAX>
+template <typename C, int IB, int RMAX, int NT = LEAF_THREADS>
 static int run_leaves(hipStream_t s, int64_t n, int k, int nbc, int ne, C* LU, int* ipiv, int* perm, int* info) {
   for (int jb = 0; jb < nbc; jb += IB) {
-    hipLaunchKernelGGL((k_leaf<C, IB, RMAX>), dim3(ne), dim3(LEAF_THREADS), 0, s, n, lu_ld(n), k, jb, nbc, LU, ipiv,
+    hipLaunchKernelGGL((k_leaf<C, IB, RMAX, NT>), dim3(ne), dim3(NT), 0, s, n, lu_ld(n), k, jb, nbc, LU, ipiv,
                        perm, info);
     const int ibc = std::min(IB, nbc - jb);
     if (jb + ibc < nbc) {
@@ -451,10 +451,11 @@ template <typename C>
 static int launch_leaves(hipStream_t s, int64_t n, int k, int nbc, int ne, C* LU, int* ipiv, int* perm, int* info) {
   constexpr bool dbl = sizeof(C) == 16;
   const int64_t rows = n - k;
-  if (rows <= 1024) return dbl ? run_leaves<C, 4, 1>(s, n, k, nbc, ne, LU, ipiv, perm, info)
-                               : run_leaves<C, 8, 1>(s, n, k, nbc, ne, LU, ipiv, perm, info);
-  if (rows <= 2048) return dbl ? run_leaves<C, 4, 2>(s, n, k, nbc, ne, LU, ipiv, perm, info)
-                               : run_leaves<C, 8, 2>(s, n, k, nbc, ne, LU, ipiv, perm, info);
+  // short panels: fewer waves, several rows each (cheaper barriers and candidate merges)
+  if (rows <= 1024) return dbl ? run_leaves<C, 4, 4, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info)
+                               : run_leaves<C, 8, 4, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info);
+  if (rows <= 2048) return dbl ? run_leaves<C, 4, 4, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info)
+                               : run_leaves<C, 8, 4, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info);
   if (rows <= 4096) return dbl ? run_leaves<C, 4, 4>(s, n, k, nbc, ne, LU, ipiv, perm, info)
                                : run_leaves<C, 8, 4>(s, n, k, nbc, ne, LU, ipiv, perm, info);
   if (rows <= 8192) return dbl ? run_leaves<C, 2, 8>(s, n, k, nbc, ne, LU, ipiv, perm, info)
