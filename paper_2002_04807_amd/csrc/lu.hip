@@ -454,10 +454,10 @@ static int launch_leaves(hipStream_t s, int64_t n, int k, int nbc, int ne, C* LU
   // short panels: fewer waves, several rows each (cheaper barriers and candidate merges)
   if (rows <= 1024) return dbl ? run_leaves<C, 4, 4, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info)
                                : run_leaves<C, 8, 4, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info);
-  if (rows <= 2048) return dbl ? run_leaves<C, 4, 4, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info)
-                               : run_leaves<C, 8, 4, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info);
-  if (rows <= 4096) return dbl ? run_leaves<C, 4, 4>(s, n, k, nbc, ne, LU, ipiv, perm, info)
-                               : run_leaves<C, 8, 4>(s, n, k, nbc, ne, LU, ipiv, perm, info);
+  if (rows <= 2048) return dbl ? run_leaves<C, 4, 8, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info)
+                               : run_leaves<C, 8, 8, 256>(s, n, k, nbc, ne, LU, ipiv, perm, info);
+  if (rows <= 4096) return dbl ? run_leaves<C, 4, 8, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info)
+                               : run_leaves<C, 8, 8, 512>(s, n, k, nbc, ne, LU, ipiv, perm, info);
   if (rows <= 8192) return dbl ? run_leaves<C, 2, 8>(s, n, k, nbc, ne, LU, ipiv, perm, info)
                                : run_leaves<C, 4, 8>(s, n, k, nbc, ne, LU, ipiv, perm, info);
   return dbl ? run_leaves<C, 1, 16>(s, n, k, nbc, ne, LU, ipiv, perm, info)
