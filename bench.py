@@ -122,12 +122,14 @@ def _source_unchanged(entry):
     return h.hexdigest()[:16] == entry["sha256_16"]
 
 
-def roofline_of(prof):
-    """Roofline of the kernel class with the largest device time in this call: algorithmic
-    flops (8 per complex multiply-add) per launch over the mean launch time, both from the
-    library's HIP-event profile of the timed call."""
-    cands = [c for c in KERNELS if prof.get(c, {}).get("ms", 0.0) > 0.0]
-    cls = max(cands, key=lambda c: prof[c]["ms"])
+def roofline_of(prof, rank=0):
+    """Roofline of the kernel class with the largest device time in this call (rank 0; rank 1
+    the next one): algorithmic flops (8 per complex multiply-add) or bytes per launch over
+    the mean launch time, both from the library's HIP-event profile of the timed call."""
+    cands = sorted([c for c in KERNELS if prof.get(c, {}).get("ms", 0.0) > 0.0], key=lambda c: -prof[c]["ms"])
+    if rank >= len(cands):
+        return None
+    cls = cands[rank]
     p = prof[cls]
     kernel, bound, peak_key, unit_desc = KERNELS[cls]
     peak = PEAK[peak_key]
@@ -442,6 +444,9 @@ def main():
     contour_tflops = f_alg / t_contour / 1e12 if t_contour > 0 else None
 
     roofline = roofline_of(prof)
+    # the two largest classes are close on this workload (reduced eigensolver, block solves):
+    # the second one's roofline is reported beside the first
+    roofline_next = roofline_of(prof, 1)
 
     result = {
         "metric": METRIC, "value": value, "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps,
@@ -453,6 +458,7 @@ def main():
         "contour_tflops": contour_tflops,
         "accuracy": acc[-1],
         "roofline": roofline,
+        "roofline_next": roofline_next,
     }
 
     if not args.no_fp64:
