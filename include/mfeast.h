@@ -43,10 +43,14 @@ extern "C" {
 typedef struct mfeast_ctx* mfeast_handle;
 
 /* Create a handle bound to HIP device `device`; work is issued on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  Returns 0, -101 (h NULL) or -900. */
+ * (a hipStream_t; NULL = the default stream).  For complex Hermitian problems the
+ * handle also creates, on first use, a non-blocking stream of its own and two events:
+ * the conjugate-transpose block solves run there next to the forward ones and are
+ * joined back to `hip_stream` before the contour sum.  Returns 0, -101 (h NULL) or
+ * -900. */
 int mfeast_create(mfeast_handle* h, int device, void* hip_stream);
 
-/* Release the handle and its workspace.  Returns 0 or -101. */
+/* Release the handle, its workspace and its internal stream.  Returns 0 or -101. */
 int mfeast_destroy(mfeast_handle h);
 
 /* Change the stream later calls of this handle issue work on. */
