@@ -20,6 +20,7 @@ from .contour import half_contour, rational_filter, gauss_legendre_rule
 from .splitmix import splitmix64_uniform, initial_subspace
 from .ifeast import bicgstab_block, feast_csr, ifeastinit
 from . import adjoint
+from . import stochastic
 from .feast import (
     feastinit,
     expand_uplo,
@@ -43,4 +44,5 @@ __all__ = [
     "feast_csr",
     "ifeastinit",
     "adjoint",
+    "stochastic",
 ]

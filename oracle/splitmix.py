@@ -11,6 +11,9 @@ mixed by the published finaliser, and mapped to [-1, 1) as 2 * (z >> 11) * 2^-53
 For a real n x m0 block, t = i + j * n (column-major).  For a complex block the
 real part of entry (i, j) uses t = 2 (i + j n) and the imaginary part t = 2 (i + j n) + 1.
 The HIP library implements the same published generator independently.
+
+Probe block of the stochastic eigenvalue count (fpm(14)=2): real Rademacher entries,
++1 or -1 by the top bit of the same raw outputs (set -> -1), with t = i + j * n.
 """
 
 import numpy as np
@@ -47,4 +50,11 @@ def initial_subspace(n, m0, seed, is_complex):
         im = v[1::2].reshape(m0, n).T
         return (re + 1j * im).astype(np.complex128)
     v = splitmix64_uniform(seed, n * m0)
+    return v.reshape(m0, n).T.astype(np.float64).copy()
+
+
+def rademacher_block(n, m0, seed):
+    """n x m0 block of +-1: -1 where the top bit of SplitMix64 output t = i + j n is set."""
+    z = splitmix64_raw(seed, n * m0)
+    v = np.where((z >> np.uint64(63)) != np.uint64(0), -1.0, 1.0)
     return v.reshape(m0, n).T.astype(np.float64).copy()
