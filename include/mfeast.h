@@ -23,7 +23,8 @@
  *    100+i (fpm(i), Fortran numbering), then -(100+i) for an invalid i-th argument of
  *    the call (1-based position in the C prototype).  Warnings: 1 no eigenvalue in the
  *    interval, 2 no convergence within fpm(4) loops, 3 M0 too small (M >= M0),
- *    4 subspace returned after one contour (fpm(14)=1).  Errors: -2 device or
+ *    4 subspace returned after one contour (fpm(14)=1), 5 only the stochastic estimate
+ *    of the eigenvalue count returned (fpm(14)=2).  Errors: -2 device or
  *    factorization failure (zero pivot, non-finite value, HIP error), -3 the reduced
  *    problem is not positive definite (B may not be positive definite).
  *    -900 no usable HIP device for the handle (a code outside the guide's ranges).
@@ -88,7 +89,8 @@ int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t r
  *          (in: initial guess when fpm(5)=1)
  *  X       device, n x m0 column-major (ldx >= n): eigenvectors following E, or the
  *          subspace Q after one contour when fpm(14)=1 (in: initial subspace when fpm(5)=1)
- *  M       host: number of eigenvalues found in [emin, emax]
+ *  M       host: number of eigenvalues found in [emin, emax] (the estimate rounded to the
+ *          nearest integer when fpm(14)=2)
  *  res     device, m0 doubles: ||A x_i - lambda_i B x_i|| / ||alpha B x_i||,
  *          alpha = max(|emin|, |emax|)
  *  epsout  host: relative trace change |trace_k - trace_{k-1}| / alpha
@@ -128,6 +130,20 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
                          const int32_t* fpm, const double* emin, const double* emax, int32_t* m0,
                          double* const* E, double* const* X, const int64_t* ldx, int32_t* M,
                          double* const* res, double* epsout, int32_t* loop, int32_t* info);
+
+/* Stochastic estimate of the eigenvalue count (fpm(14)=2; Table tab_fpm, Table tab_info
+ * code 5; the method cited in the guide's references, Di Napoli, Polizzi, Saad 2016):
+ * the first contour is applied to m0 probe vectors Y with entries +1 or -1 (SplitMix64,
+ * seed fpm(51): -1 where the top bit of output i + j*n is set), giving Q; the estimate
+ * is Re(trace(Y^H Q)) / m0, which approximates the sum of the quadrature filter over the
+ * spectrum, i.e. the number of eigenvalues inside up to the filter's smearing at the
+ * interval ends.  On return (info 5): M = the estimate rounded to the nearest integer
+ * (at least 0), E[0] (device) = the unrounded estimate, loop = 0, epsout = 1; X, res and
+ * E[1..] are not written.  fpm(5) is ignored in this mode.  Every dense, batched and
+ * sparse entry point accepts it (the sparse ones with their inexact BiCGSTAB solves).
+ * mfeast_init_stochastic sets the guide's defaults for the mode: mfeast_init, then
+ * fpm(2)=3 half-contour nodes, fpm(8)=6, fpm(14)=2, fpm(15)=1. */
+void mfeast_init_stochastic(int32_t* fpm);
 
 /* IFEAST defaults (Section 3.5, Table tab_fpm "using IFEAST"): mfeast_init, then
  * fpm(2)=4 nodes, fpm(4)=50 loops, fpm(16)=1 trapezoidal rule, fpm(18)=100 (circle).

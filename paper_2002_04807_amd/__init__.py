@@ -22,7 +22,7 @@ _lib_error = None
 
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
-    "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
+    "mfeast_init_stochastic", "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
     "mfeast_dsygv_batched", "mfeast_get_timing", "mfeast_get_profile",
 )
 
@@ -47,6 +47,8 @@ def _load():
     lib.mfeast_init.restype = None
     lib.mfeast_init_ifeast.argtypes = [c_i32p]
     lib.mfeast_init_ifeast.restype = None
+    lib.mfeast_init_stochastic.argtypes = [c_i32p]
+    lib.mfeast_init_stochastic.restype = None
     lib.mfeast_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, c_dp, c_dp]
     lib.mfeast_contour.restype = c_int
@@ -111,6 +113,13 @@ def mfeast_init_ifeast():
     """IFEAST defaults of fpm[64] as an int32 numpy array."""
     fpm = np.zeros(64, dtype=np.int32)
     _load().mfeast_init_ifeast(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return fpm
+
+
+def mfeast_init_stochastic():
+    """fpm[64] defaults of the stochastic eigenvalue-count mode (fpm(14)=2)."""
+    fpm = np.zeros(64, dtype=np.int32)
+    _load().mfeast_init_stochastic(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return fpm
 
 

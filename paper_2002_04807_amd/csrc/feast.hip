@@ -125,7 +125,7 @@ static int check_fpm(const int32_t* fpm, bool expert) {
   if (f(4) < 0) return 104;
   if (f(5) != 0 && f(5) != 1) return 105;
   if (f(6) != 0 && f(6) != 1) return 106;
-  if (f(14) != 0 && f(14) != 1) return 114;
+  if (f(14) < 0 || f(14) > 2) return 114;
   if (f(42) != 0 && f(42) != 1) return 142;
   if (f(50) < 0 || f(50) > 8) return 150;
   if (f(53) != 0 && f(53) != 1) return 153;
@@ -567,7 +567,9 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   t_fact += ph.stop();
 
   // ---------------- starting block
-  if (f(5) == 1) MF_TRY(copy_cm_to_rm<T>(s, n, m0, Xu, ldx, Xw, m0));
+  // (the stochastic count probes with its own +-1 block whatever fpm(5) says)
+  if (f(14) == 2) MF_TRY(rademacher_block<T>(s, n, m0, (uint64_t)(uint32_t)f(51), Xw, m0));
+  else if (f(5) == 1) MF_TRY(copy_cm_to_rm<T>(s, n, m0, Xu, ldx, Xw, m0));
   else MF_TRY(random_block<T>(s, n, m0, (uint64_t)(uint32_t)f(51), Xw, m0));
 
   std::vector<double> lam_cur;
@@ -645,6 +647,27 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_solve += ph.stop();
 
+    if (f(14) == 2) {
+      // stochastic count: Q is the filter applied to the +-1 probes Y, and
+      // Re(trace(Y^H Q)) / m0 estimates the sum of the filter over the spectrum, i.e.
+      // the number of eigenvalues inside (Hutchinson's estimator on the quadrature filter)
+      double* d_dots = d_absmax;
+      MF_TRY(col_dots<T>(s, n, m0, Xw, Q, d_dots, part));
+      MF_HIP_CHECK(hipMemcpyAsync(h_absmax, d_dots, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      double est = 0.0;
+      for (int c = 0; c < m0; ++c) est += h_absmax[c];
+      est /= m0;
+      if (!std::isfinite(est)) return -2;
+      MF_HIP_CHECK(hipMemcpyAsync(E, &est, sizeof(double), hipMemcpyHostToDevice, s));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      *m0p = m0;
+      *Mout = est > 0.0 ? (int32_t)std::floor(est + 0.5) : 0;
+      *loop = 0;
+      *epsout = 1.0;
+      info = 5;
+      break;
+    }
     if (f(14) == 1) {
       MF_TRY(copy_rm_to_cm<T>(s, n, m0, Q, m0, Xu, ldx));
       MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -877,7 +900,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     ++k;
   }
 
-  if (info != 4 && info != -3 && info != -2) {
+  if (info != 4 && info != 5 && info != -3 && info != -2) {
     // copy eigenpairs to the caller's layout in the reported order
     std::vector<double> e_out(m0), r_out(m0);
     for (int i = 0; i < m0; ++i) {
@@ -1221,6 +1244,15 @@ void mfeast_init_ifeast(int32_t* fpm) {
   fpm[3] = 50;    // fpm(4)  refinement loops
   fpm[15] = 1;    // fpm(16) trapezoidal rule
   fpm[17] = 100;  // fpm(18) circle
+}
+
+void mfeast_init_stochastic(int32_t* fpm) {
+  if (fpm == nullptr) return;
+  mfeast_init(fpm);
+  fpm[1] = 3;    // fpm(2)  half-contour nodes
+  fpm[7] = 6;    // fpm(8)  full-contour nodes (non-Hermitian, unused)
+  fpm[13] = 2;   // fpm(14) stochastic estimate of the count
+  fpm[14] = 1;   // fpm(15) one-sided contour
 }
 
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count) {

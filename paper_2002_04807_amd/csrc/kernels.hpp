@@ -162,6 +162,13 @@ template <typename T>
 int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T* dst, int64_t ldd);
 template <typename T>
 int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld);
+// n x m row-major block of +-1 (stochastic count probes; SplitMix64 top bit, counter i + j n)
+template <typename T>
+int rademacher_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld);
+// out[c] = Re(sum_r conj(Y[r][c]) Q[r][c]), row-major n x m blocks with leading dimension m;
+// partial: ceil(n / 256) * m doubles
+template <typename T>
+int col_dots(hipStream_t s, int64_t n, int m, const T* Y, const T* Q, double* out, double* partial);
 
 // ------------------------------------------------------------------ B-orthonormalization (orth.hip)
 // Cholesky with column dropping of a Hermitian m x m row-major A (lower part): L in place,

@@ -388,12 +388,15 @@ int copy_cm_to_rm(hipStream_t s, int64_t n, int m, const T* src, int64_t lds, T*
 // Starting block from SplitMix64 (Steele, Lea, Flood 2014): entry counter t maps to
 // state seed + (t+1) * 0x9E3779B97F4A7C15, the published finaliser, then 2*(z>>11)*2^-53 - 1.
 // Counter of entry (i, j) of the n x m block: t = i + j*n (real), 2(i + j*n) + {0,1} (complex).
-__device__ inline double splitmix_uniform(uint64_t seed, uint64_t t) {
+__device__ inline uint64_t splitmix_raw(uint64_t seed, uint64_t t) {
   uint64_t z = seed + (t + 1ull) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z = z ^ (z >> 31);
-  return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+  return z ^ (z >> 31);
+}
+
+__device__ inline double splitmix_uniform(uint64_t seed, uint64_t t) {
+  return 2.0 * ((double)(splitmix_raw(seed, t) >> 11) * 0x1.0p-53) - 1.0;
 }
 
 template <typename T>
@@ -413,6 +416,59 @@ __global__ void k_random_block(int64_t n, int m, uint64_t seed, T* __restrict__ 
 template <typename T>
 int random_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld) {
   hipLaunchKernelGGL((k_random_block<T>), dim3((unsigned)n, (m + 255) / 256), dim3(256), 0, s, n, m, seed, Y, ld);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Probe block of the stochastic eigenvalue count: real Rademacher entries, -1 where the
+// top bit of SplitMix64 output t = i + j*n is set, else +1 (imaginary parts zero).
+template <typename T>
+__global__ void k_rademacher_block(int64_t n, int m, uint64_t seed, T* __restrict__ Y, int64_t ld) {
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.x;
+  if (j >= m) return;
+  const uint64_t t = (uint64_t)i + (uint64_t)j * (uint64_t)n;
+  Y[i * ld + j] = T((splitmix_raw(seed, t) >> 63) ? -1.0 : 1.0);
+}
+
+template <typename T>
+int rademacher_block(hipStream_t s, int64_t n, int m, uint64_t seed, T* Y, int64_t ld) {
+  hipLaunchKernelGGL((k_rademacher_block<T>), dim3((unsigned)n, (m + 255) / 256), dim3(256), 0, s, n, m, seed, Y,
+                     ld);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// out[c] = Re(sum_r conj(Y[r][c]) Q[r][c]) for row-major n x m blocks (leading dimension
+// m): per-chunk partial sums of RES_ROWS rows, then one sum over the chunks per column
+// (deterministic order)
+template <typename T>
+__global__ void k_coldot_partial(int64_t n, int m, const T* __restrict__ Y, const T* __restrict__ Q,
+                                 double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (c >= m) return;
+  double acc = 0.0;
+  const int64_t r1 = ((chunk + 1) * RES_ROWS < n) ? (chunk + 1) * RES_ROWS : n;
+  for (int64_t r = chunk * RES_ROWS; r < r1; ++r) {
+    const T y = Y[r * m + c], q = Q[r * m + c];
+    if constexpr (is_cplx<T>::value) acc += y.re * q.re + y.im * q.im;
+    else acc += y * q;
+  }
+  part[chunk * m + c] = acc;
+}
+
+__global__ void k_coldot_final(int m, int nchunk, const double* __restrict__ part, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  double acc = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) acc += part[(int64_t)ch * m + c];
+  out[c] = acc;
+}
+
+template <typename T>
+int col_dots(hipStream_t s, int64_t n, int m, const T* Y, const T* Q, double* out, double* partial) {
+  const int nchunk = (int)((n + RES_ROWS - 1) / RES_ROWS);
+  hipLaunchKernelGGL((k_coldot_partial<T>), dim3((m + 255) / 256, nchunk), dim3(256), 0, s, n, m, Y, Q, partial);
+  hipLaunchKernelGGL(k_coldot_final, dim3((m + 255) / 256), dim3(256), 0, s, m, nchunk, partial, out);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -483,6 +539,8 @@ int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, 
   template int copy_rm_to_cm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t, const int*);        \
   template int copy_cm_to_rm<T>(hipStream_t, int64_t, int, const T*, int64_t, T*, int64_t);                    \
   template int random_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);                            \
+  template int rademacher_block<T>(hipStream_t, int64_t, int, uint64_t, T*, int64_t);                        \
+  template int col_dots<T>(hipStream_t, int64_t, int, const T*, const T*, double*, double*);                  \
   template int hermitian_part<T>(hipStream_t, int, T*);                                                     \
   template int copy_block<T>(hipStream_t, int, int, const T*, int64_t, T*, int64_t, bool);                     \
   template int sym_permute<T>(hipStream_t, int, const T*, const int*, T*);                                    \

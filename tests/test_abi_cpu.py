@@ -105,6 +105,12 @@ def test_ifeast_defaults_match_oracle():
     np.testing.assert_array_equal(got.astype(np.int64), oracle.ifeastinit())
 
 
+def test_stochastic_defaults_match_oracle():
+    from oracle.stochastic import stochasticinit
+    got = mf.mfeast_init_stochastic()
+    np.testing.assert_array_equal(got.astype(np.int64), stochasticinit())
+
+
 def _csr_call(n=10, m0=4, emin=0.0, emax=1.0, fpm=None, handle=None, **kw):
     """mfeast_dcsrgv with host dummies: only the host-side argument checks run."""
     fpm = oracle.ifeastinit().astype(np.int32) if fpm is None else fpm
