@@ -49,10 +49,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="only run this many FP32 steps (for rocprofv3 runs); no JSON extras")
-    p.add_argument("--workload", default="pencil", choices=("pencil", "sparse", "batched", "adjoint"),
+    p.add_argument("--workload", default="pencil", choices=("pencil", "sparse", "batched", "adjoint", "count"),
                    help="pencil: the metric's n=4096 generalized complex Hermitian problem (default); "
                         "sparse: 64^3 Laplacian CSR with batched BiCGSTAB; batched: 128 independent "
-                        "real problems; adjoint: forward and backward of the n=4096 tridiagonal workload")
+                        "real problems; adjoint: forward and backward of the n=4096 tridiagonal workload; "
+                        "count: stochastic eigenvalue-count estimate on the n=4096 pencil")
     return p.parse_args()
 
 
@@ -387,6 +388,74 @@ def bench_adjoint(args, mf, torch, np, gen):
     }
 
 
+def bench_count(args, mf, torch, np, gen):
+    """Stochastic eigenvalue count (fpm(14)=2) on the n = 4096 complex Hermitian pencil of the
+    headline workload, [-1, 1], M0 = 600 probe vectors, 3 Gauss half-contour nodes, FP32 solves:
+    one step = one estimate (3 node LUs, forward and conjugate-transpose solves, the trace)."""
+    from oracle.stochastic import stochastic_count
+    dev = torch.device("cuda:0")
+    A, B, lam, _ = gen.prescribed_complex_pencil(N, seed=SEED)
+    exact = int(((lam >= EMIN) & (lam <= EMAX)).sum())
+    At = torch.from_numpy(np.asfortranarray(A)).to(dev)
+    Bt = torch.from_numpy(np.asfortranarray(B)).to(dev)
+    E = torch.zeros(M0, dtype=torch.float64, device=dev)
+    res = torch.zeros(M0, dtype=torch.float64, device=dev)
+    X = torch.zeros((M0, N), dtype=torch.complex128, device=dev).mT
+    h = mf.Handle(0)
+
+    def step(profile):
+        fpm = mf.mfeast_init_stochastic()
+        fpm[51] = 1 if profile else 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = mf.mfeast_zhegv(h, "F", N, At, N, Bt, N, fpm, EMIN, EMAX, M0, E, X, N, res)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        step(False)
+    times = []
+    for _ in range(max(1, args.steps)):
+        out, t = step(False)
+        times.append(t)
+    est = float(E[0].item())
+    out_p, _ = step(True)
+    prof = h.profile()
+    h.close()
+    roofline = roofline_of(prof)
+    roofline_next = roofline_of(prof, 1)
+    for r in (roofline, roofline_next):
+        if r is not None:
+            r["unit_of_work"] = r["unit_of_work"].replace("8 nodes", "3 nodes")
+    print("bench: count steps %s s, estimate %.3f (exact count %d)" % (["%.4f" % t for t in times], est, exact),
+          file=sys.stderr, flush=True)
+    t = float(np.median(times))
+    result = {
+        "metric": "stochastic eigenvalue-count estimates/s (fpm(14)=2)", "value": 1.0 / t, "unit": "estimates/s",
+        "n_gpus": 1, "steps": len(times), "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 solves + f64 accumulation", "data": "synthetic",
+        "config": {"workload": "generalized complex Hermitian n=4096 (seed 0), [-1,1], 600 +-1 probes, "
+                               "3-node Gauss half contour, FP32 solves", "n": N, "m0": M0, "nodes": 3},
+        "accuracy": {"estimate": est, "M": out["M"], "info": out["info"], "exact_count": exact},
+        "roofline": roofline,
+        "roofline_next": roofline_next,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        est_ref, _ = stochastic_count(A, B, EMIN, EMAX, 64, ne=3, seed=0)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "estimates/s", "cores": _cores(), "kind": "oracle",
+                                  "sample": "the whole oracle estimate with 64 probes (3 complex128 LUs of n=4096 "
+                                            "and their solves), %.1f s; 600 probes cost more" % t_cpu}
+        fpm = mf.mfeast_init_stochastic()
+        h2 = mf.Handle(0)
+        mf.mfeast_zhegv(h2, "F", N, At, N, Bt, N, fpm, EMIN, EMAX, 64, E, X, N, res)
+        torch.cuda.synchronize()
+        h2.close()
+        result["accuracy"]["parity_64_probes"] = {"gpu": float(E[0].item()), "oracle": est_ref}
+    return result
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -403,7 +472,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.workload != "pencil":
-        fn = {"sparse": bench_sparse, "batched": bench_batched, "adjoint": bench_adjoint}[args.workload]
+        fn = {"sparse": bench_sparse, "batched": bench_batched, "adjoint": bench_adjoint,
+              "count": bench_count}[args.workload]
         print(json.dumps(fn(args, mf, torch, np, gen)))
         return
     dev = torch.device("cuda:0")
