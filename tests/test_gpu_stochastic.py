@@ -92,3 +92,22 @@ def test_count_sparse_laplacian_8cube():
     torch.cuda.synchronize()
     est = _check(out, est_ref, M_ref, True)
     _say("  estimate %.6f (oracle %.6f)" % (est, est_ref))
+
+
+def test_count_batched_problems():
+    _say("stochastic count: three batched real problems")
+    rng = np.random.default_rng(21)
+    probs = []
+    for n in (96, 160, 257):
+        A, lam, _ = gen.prescribed_real_problem(n, rng, -2.0, 2.0)
+        probs.append((A, -0.7, 0.4, 24))
+    fpm = mf.mfeast_init_stochastic()
+    fpm[41] = 0
+    As = [torch.from_numpy(np.ascontiguousarray(A)).to(DEV) for A, _, _, _ in probs]
+    ret, outs, _ = mf.feast_batched(As, [p[1] for p in probs], [p[2] for p in probs], [p[3] for p in probs],
+                                    fpm=fpm)
+    torch.cuda.synchronize()
+    assert ret == 5, ret
+    for (A, emin, emax, m0), out in zip(probs, outs):
+        est_ref, M_ref = stochastic_count(A, None, emin, emax, m0, ne=3, seed=0)
+        _check(out, est_ref, M_ref, False)
