@@ -5,11 +5,12 @@
 // ordering; each pair (P, Q) forms a 2JB x 2JB Hermitian subproblem
 // [H_PP H_PQ; H_QP H_QQ] on which one workgroup runs one cyclic Jacobi sweep in LDS
 // (its own round-robin ordering of the 2JB local indices), giving a unitary
-// U_PQ.  A second launch then applies all the round's U's at once: every super-block
-// H[I_i, I_j] becomes
-// U_i^H H[I_i, I_j] U_j (the pairs of a round are disjoint, so the super-blocks
-// update independently) and V[:, I_j] becomes V[:, I_j] U_j.  A sweep covers every
-// block pair once; sweeps stop when no subproblem needed a rotation.
+// U_PQ.  A second launch then applies all the round's U's to H at once: every
+// super-block H[I_i, I_j] becomes U_i^H H[I_i, I_j] U_j (the pairs of a round are
+// disjoint, so the super-blocks update independently).  V[:, I_j] becomes V[:, I_j] U_j
+// in the next round's subproblem launch, whose spare compute units take it (the
+// subproblems never read V).  A sweep covers every block pair once; sweeps stop when no
+// subproblem needed a rotation.
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -91,20 +92,69 @@ __device__ inline void local_pair(int i, int r, int& p, int& q) {
   q = max(a, b);
 }
 
+// V[:, I_j] <- V[:, I_j] U_j for the pairs j of round `round`: item bid covers row block
+// bid / npr (JS rows) and pair bid % npr; X and Um are LDS tiles of the caller.
+template <typename T, int JB>
+__device__ inline void bj_v_update(int m, int nbp, int round, int bid, T* __restrict__ V, const T* __restrict__ Ubuf,
+                                   T (*X)[2 * JB + 1], T (*Um)[2 * JB + 1]) {
+  constexpr int JS = 2 * JB;
+  constexpr int RW = JS / 16;
+  const int tid = threadIdx.x;
+  const int npr = nbp / 2;
+  const int r0 = (tid >> 4) * RW, c0 = (tid & 15) * RW;
+  T acc[RW][RW];
+  {
+    const int j = bid % npr;
+    const int xb = bid / npr;  // row block of JS rows of V
+    int Pj, Qj;
+    block_pair(j, round, nbp, Pj, Qj);
+    const T* Uj = Ubuf + (int64_t)j * JS * JS;
+    for (int e = tid; e < JS * JS; e += JT) {
+      const int a = e / JS, c = e % JS;
+      const int ga = xb * JS + a, gc = gidx<JB>(c, Pj, Qj);
+      X[a][c] = (ga < m && gc < m) ? V[(int64_t)ga * m + gc] : T(0.0);
+      Um[a][c] = Uj[e];
+    }
+    __syncthreads();
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T xa[RW], ub[RW];
+      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
+      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
+    }
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) {
+        const int ga = xb * JS + r0 + a, gc = gidx<JB>(c0 + c, Pj, Qj);
+        if (ga < m && gc < m) V[(int64_t)ga * m + gc] = acc[a][c];
+      }
+  }
+}
+
 // One cyclic sweep of the 2JB x 2JB subproblem.  S is double-buffered so that a round
 // needs one barrier: every thread computes the one or two rotations its own items need
 // from the current buffer (redundantly with other threads) and writes the rotated
 // values to the other buffer.  Items: the (JS/2)^2 2 x 2 blocks of S and the JS x JS/2
 // column pairs of U.
+// Workgroups [0, nsub) run the subproblems of round `round`; the ones after them apply
+// the unitaries Uv of the previous round `vround` to V (V is not read by the
+// subproblems, so its update runs beside them instead of on the path between rounds).
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, const T* __restrict__ H,
-                                                T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol) {
+__global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int nsub, const T* __restrict__ H,
+                                                T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol,
+                                                int vround, T* __restrict__ V, const T* __restrict__ Uv) {
   constexpr int JS = 2 * JB;
   constexpr int NSI = (JS / 2) * (JS / 2), NUI = JS * (JS / 2);
   __shared__ T S[2][JS][JS + 1];
   __shared__ T U[JS][JS + 1];
   __shared__ int s_total;
   __shared__ double s_dmax;
+  if ((int)blockIdx.x >= nsub) {
+    bj_v_update<T, JB>(m, nbp, vround, (int)blockIdx.x - nsub, V, Uv, S[0], S[1]);
+    return;
+  }
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   int P, Q;
@@ -189,11 +239,10 @@ __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, const
 }
 
 // ---------------------------------------------------------------------------
-// Apply the round's U's.  Blocks [0, npr*(npr+1)/2): H super-block pairs i <= j
-// (the (j, i) block is written as the conjugate transpose).  Blocks after that:
-// V row-block x pair j.
+// Apply the round's U's to H: one workgroup per super-block pair i <= j (the (j, i)
+// block is written as the conjugate transpose).
 template <typename T, int JB>
-__global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __restrict__ H, T* __restrict__ V,
+__global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __restrict__ H,
                                                const T* __restrict__ Ubuf) {
   constexpr int JS = 2 * JB;
   constexpr int RW = JS / 16;  // rows (and columns) of the result per thread: 16 x 16 threads
@@ -206,7 +255,7 @@ __global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __r
   // each thread owns an RW x RW tile of the JS x JS result
   const int r0 = (tid >> 4) * RW, c0 = (tid & 15) * RW;
   T acc[RW][RW];
-  if (bid < nh) {
+  {
     // (i, j) with i <= j from the linear index
     int i = 0;
     while (bid >= npr - i) {
@@ -259,34 +308,6 @@ __global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __r
           if (i != j) H[(int64_t)gc * m + ga] = conj(acc[a][c]);
         }
       }
-  } else {
-    bid -= nh;
-    const int j = bid % npr;
-    const int xb = bid / npr;  // row block of 64 rows of V
-    int Pj, Qj;
-    block_pair(j, round, nbp, Pj, Qj);
-    const T* Uj = Ubuf + (int64_t)j * JS * JS;
-    for (int e = tid; e < JS * JS; e += JT) {
-      const int a = e / JS, c = e % JS;
-      const int ga = xb * JS + a, gc = gidx<JB>(c, Pj, Qj);
-      X[a][c] = (ga < m && gc < m) ? V[(int64_t)ga * m + gc] : T(0.0);
-      Um[a][c] = Uj[e];
-    }
-    __syncthreads();
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
-    for (int k = 0; k < JS; ++k) {
-      T xa[RW], ub[RW];
-      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
-      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
-      for (int a = 0; a < RW; ++a)
-        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
-    }
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) {
-        const int ga = xb * JS + r0 + a, gc = gidx<JB>(c0 + c, Pj, Qj);
-        if (ga < m && gc < m) V[(int64_t)ga * m + gc] = acc[a][c];
-      }
   }
 }
 
@@ -307,7 +328,7 @@ __global__ void k_diag_out(int m, const T* __restrict__ H, double* evals, int* c
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 // H (m x m) destroyed; V receives the eigenvectors (columns), evals the eigenvalues
-// (unsorted).  ubuf: (2 JB)^2 (nbp/2) entries of T for the round's unitaries; counter:
+// (unsorted).  ubuf: 2 (2 JB)^2 (nbp/2) entries of T for two rounds' unitaries; counter:
 // 2 ints.
 template <typename T, int JB>
 static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
@@ -318,19 +339,36 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
   const int npr = nbp / 2;
   const int nh = npr * (npr + 1) / 2;
   const int nvrow = (m + JS - 1) / JS;
+  const int nvi = nvrow * npr;  // V items of one round
+  // the unitaries alternate between two buffers: round g's subproblems write Ub[g % 2]
+  // while the V items of round g - 1 in the same launch read Ub[(g - 1) % 2]
+  T* Ub[2] = {ubuf, ubuf + (size_t)JS * JS * npr};
   hipLaunchKernelGGL((k_identity<T>), dim3((m + 255) / 256, m), dim3(256), 0, s, m, V);
   int sweep = 0;
   int hcount = 1;
+  int g = 0;
+  int vpend = -1;  // round whose V items are still to run (the last round of the last sweep)
   for (; sweep < max_sweeps; ++sweep) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
-    for (int r = 0; r < nbp - 1; ++r) {
-      hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr), dim3(JT), 0, s, m, nbp, r, H, ubuf, counter, 1.0e-15);
-      hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(nh + nvrow * npr), dim3(JT), 0, s, m, nbp, r, H, V, ubuf);
+    const int nr = nbp - 1;
+    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + (vpend >= 0 ? nvi : 0)), dim3(JT), 0, s, m, nbp, 0, npr, H,
+                       Ub[g & 1], counter, 1.0e-15, vpend, V, Ub[(g + 1) & 1]);
+    for (int r = 0; r < nr; ++r, ++g) {
+      hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(nh), dim3(JT), 0, s, m, nbp, r, H, Ub[g & 1]);
+      if (r + 1 < nr) {
+        hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + nvi), dim3(JT), 0, s, m, nbp, r + 1, npr, H,
+                           Ub[(g + 1) & 1], counter, 1.0e-15, r, V, Ub[g & 1]);
+      } else {
+        vpend = r;
+      }
     }
     if (hipMemcpyAsync(&hcount, counter, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
     if (hipStreamSynchronize(s) != hipSuccess) return -2;
     if (hcount == 0) break;
   }
+  if (vpend >= 0)
+    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(nvi), dim3(JT), 0, s, m, nbp, 0, 0, H, Ub[g & 1], counter, 1.0e-15,
+                       vpend, V, Ub[(g + 1) & 1]);
   hipLaunchKernelGGL((k_diag_out<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, H, evals, counter + 1);
   int sw = sweep + 1;
   if (hipMemcpyAsync(sweeps_out, &sw, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
@@ -353,13 +391,10 @@ int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_ou
 }
 
 size_t block_jacobi_work_bytes(int m, size_t elem) {
-  // sized for the widest block choice
-  const int JB = 32, JS = 64;
-  const int nb = (m + JB - 1) / JB;
-  const int nbp16 = ((m + 15) / 16) + (((m + 15) / 16) & 1);
-  const size_t a = (size_t)JS * JS * ((nb + (nb & 1)) / 2) * elem;
-  const size_t b = (size_t)32 * 32 * (nbp16 / 2) * elem;
-  return (a > b ? a : b) + 64;
+  // two sets of round unitaries for either block width, then the counters
+  const int nb8 = (m + 7) / 8, nb16 = (m + 15) / 16;
+  const size_t u8 = (size_t)256 * ((nb8 + (nb8 & 1)) / 2), u16 = (size_t)1024 * ((nb16 + (nb16 & 1)) / 2);
+  return 2 * (u8 > u16 ? u8 : u16) * elem + 64;
 }
 
 template int block_jacobi<double>(hipStream_t, int, double*, double*, double*, int*, double*, int*, int);
