@@ -5,12 +5,13 @@
 // ordering; each pair (P, Q) forms a 2JB x 2JB Hermitian subproblem
 // [H_PP H_PQ; H_QP H_QQ] on which one workgroup runs one cyclic Jacobi sweep in LDS
 // (its own round-robin ordering of the 2JB local indices), giving a unitary
-// U_PQ.  A second launch then applies all the round's U's to H at once: every
-// super-block H[I_i, I_j] becomes U_i^H H[I_i, I_j] U_j (the pairs of a round are
-// disjoint, so the super-blocks update independently).  V[:, I_j] becomes V[:, I_j] U_j
-// in the next round's subproblem launch, whose spare compute units take it (the
-// subproblems never read V).  A sweep covers every block pair once; sweeps stop when no
-// subproblem needed a rotation.
+// U_PQ.  The round's U's are then applied: every super-block H[I_i, I_j] becomes
+// U_i^H H[I_i, I_j] U_j (the pairs of a round are disjoint, so the super-blocks update
+// independently) and V[:, I_j] becomes V[:, I_j] U_j.  Only the 2 npr super-blocks that
+// the next round's subproblems read get a launch of their own between the rounds; the
+// other super-blocks and V are updated by spare workgroups of the next round's
+// subproblem launch (which never touches them).  A sweep covers every block pair once;
+// sweeps stop when no subproblem needed a rotation.
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -133,16 +134,110 @@ __device__ inline void bj_v_update(int m, int nbp, int round, int bid, T* __rest
   }
 }
 
+// H[I_i, I_j] <- U_i^H H[I_i, I_j] U_j for the pairs i <= j of round `round` (the (j, i)
+// block is written as the conjugate transpose); X and Um are LDS tiles of the caller.
+template <typename T, int JB>
+__device__ inline void bj_h_update(int m, int nbp, int round, int i, int j, T* __restrict__ H,
+                                   const T* __restrict__ Ubuf, T (*X)[2 * JB + 1], T (*Um)[2 * JB + 1]) {
+  constexpr int JS = 2 * JB;
+  constexpr int RW = JS / 16;  // rows (and columns) of the result per thread: 16 x 16 threads
+  const int tid = threadIdx.x;
+  // each thread owns an RW x RW tile of the JS x JS result
+  const int r0 = (tid >> 4) * RW, c0 = (tid & 15) * RW;
+  T acc[RW][RW];
+  {
+    int Pi, Qi, Pj, Qj;
+    block_pair(i, round, nbp, Pi, Qi);
+    block_pair(j, round, nbp, Pj, Qj);
+    const T* Ui = Ubuf + (int64_t)i * JS * JS;
+    const T* Uj = Ubuf + (int64_t)j * JS * JS;
+    for (int e = tid; e < JS * JS; e += JT) {
+      const int a = e / JS, c = e % JS;
+      const int ga = gidx<JB>(a, Pi, Qi), gc = gidx<JB>(c, Pj, Qj);
+      X[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
+      Um[a][c] = Uj[e];
+    }
+    __syncthreads();
+    // T = X Uj
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T xa[RW], ub[RW];
+      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
+      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
+    }
+    __syncthreads();
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) X[r0 + a][c0 + c] = acc[a][c];
+    for (int e = tid; e < JS * JS; e += JT) Um[e / JS][e % JS] = Ui[e];
+    __syncthreads();
+    // out = Ui^H T
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
+    for (int k = 0; k < JS; ++k) {
+      T ua[RW], xb[RW];
+      for (int a = 0; a < RW; ++a) ua[a] = conj(Um[k][r0 + a]);
+      for (int c = 0; c < RW; ++c) xb[c] = X[k][c0 + c];
+      for (int a = 0; a < RW; ++a)
+        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + ua[a] * xb[c];
+    }
+    for (int a = 0; a < RW; ++a)
+      for (int c = 0; c < RW; ++c) {
+        const int ga = gidx<JB>(r0 + a, Pi, Qi), gc = gidx<JB>(c0 + c, Pj, Qj);
+        if (ga < m && gc < m) {
+          H[(int64_t)ga * m + gc] = acc[a][c];
+          if (i != j) H[(int64_t)gc * m + ga] = conj(acc[a][c]);
+        }
+      }
+  }
+}
+
+// Pair of round r that holds block x (inverse of block_pair: the circle keeps block 0
+// in pair 0 and rotates the others through R = nbp - 1 positions).
+__device__ inline int bj_pair_of(int x, int r, int nbp) {
+  if (x == 0) return 0;
+  const int R = nbp - 1, npr = nbp / 2;
+  const int d = ((x - 1 - r) % R + R) % R;
+  return d <= npr - 2 ? d + 1 : R - 1 - d;
+}
+
+// Super-block (i, j), i <= j, of round r is read by the subproblems of the next round rn
+// (before which it must be updated) if i == j or some pair of round rn joins a block of
+// pair i with one of pair j.  The others can be updated beside those subproblems.
+__device__ inline bool bj_sb_critical(int i, int j, int r, int rn, int nbp) {
+  if (i == j) return true;
+  int ai, bi, aj, bj, pa, qa, pb, qb;
+  block_pair(i, r, nbp, ai, bi);
+  block_pair(j, r, nbp, aj, bj);
+  block_pair(bj_pair_of(ai, rn, nbp), rn, nbp, pa, qa);
+  block_pair(bj_pair_of(bi, rn, nbp), rn, nbp, pb, qb);
+  const int na = pa == ai ? qa : pa, nb = pb == bi ? qb : pb;  // next-round partners
+  return na == aj || na == bj || nb == aj || nb == bj;
+}
+
+// (i, j), i <= j, from the linear index of the npr (npr + 1) / 2 super-blocks
+__device__ inline void bj_sb_index(int bid, int npr, int& i, int& j) {
+  i = 0;
+  while (bid >= npr - i) {
+    bid -= npr - i;
+    ++i;
+  }
+  j = i + bid;
+}
+
 // One cyclic sweep of the 2JB x 2JB subproblem.  S is double-buffered so that a round
 // needs one barrier: every thread computes the one or two rotations its own items need
 // from the current buffer (redundantly with other threads) and writes the rotated
 // values to the other buffer.  Items: the (JS/2)^2 2 x 2 blocks of S and the JS x JS/2
 // column pairs of U.
-// Workgroups [0, nsub) run the subproblems of round `round`; the ones after them apply
-// the unitaries Uv of the previous round `vround` to V (V is not read by the
-// subproblems, so its update runs beside them instead of on the path between rounds).
+// Workgroups [0, nsub) run the subproblems of round `round`; the ones after them finish
+// the previous round `vround` with its unitaries Uv: first V (read by no subproblem),
+// then the super-blocks of H that no subproblem of `round` reads (the others were
+// updated before this launch), so that only the latter lie on the path between rounds.
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int nsub, const T* __restrict__ H,
+__global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int nsub, T* __restrict__ H,
                                                 T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol,
                                                 int vround, T* __restrict__ V, const T* __restrict__ Uv) {
   constexpr int JS = 2 * JB;
@@ -152,7 +247,17 @@ __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int n
   __shared__ int s_total;
   __shared__ double s_dmax;
   if ((int)blockIdx.x >= nsub) {
-    bj_v_update<T, JB>(m, nbp, vround, (int)blockIdx.x - nsub, V, Uv, S[0], S[1]);
+    const int npr = nbp / 2;
+    const int nvi = ((m + JS - 1) / JS) * npr;
+    const int b = (int)blockIdx.x - nsub;
+    if (b < nvi) {
+      bj_v_update<T, JB>(m, nbp, vround, b, V, Uv, S[0], S[1]);
+    } else {
+      int i, j;
+      bj_sb_index(b - nvi, npr, i, j);
+      if (!bj_sb_critical(i, j, vround, (vround + 1) % (nbp - 1), nbp))
+        bj_h_update<T, JB>(m, nbp, vround, i, j, H, Uv, S[0], S[1]);
+    }
     return;
   }
   const int tid = threadIdx.x;
@@ -239,76 +344,26 @@ __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int n
 }
 
 // ---------------------------------------------------------------------------
-// Apply the round's U's to H: one workgroup per super-block pair i <= j (the (j, i)
-// block is written as the conjugate transpose).
+// The super-blocks of round `round` that the next round's subproblems read: 2 npr
+// workgroups, (b, b) for b < npr, then per next-round pair the super-block that couples
+// its two blocks (none when both lie in one pair, which only happens for a single pair).
 template <typename T, int JB>
-__global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, T* __restrict__ H,
+__global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, int rn, T* __restrict__ H,
                                                const T* __restrict__ Ubuf) {
   constexpr int JS = 2 * JB;
-  constexpr int RW = JS / 16;  // rows (and columns) of the result per thread: 16 x 16 threads
   __shared__ T X[JS][JS + 1];
   __shared__ T Um[JS][JS + 1];
-  const int tid = threadIdx.x;
   const int npr = nbp / 2;
-  const int nh = npr * (npr + 1) / 2;
-  int bid = blockIdx.x;
-  // each thread owns an RW x RW tile of the JS x JS result
-  const int r0 = (tid >> 4) * RW, c0 = (tid & 15) * RW;
-  T acc[RW][RW];
-  {
-    // (i, j) with i <= j from the linear index
-    int i = 0;
-    while (bid >= npr - i) {
-      bid -= npr - i;
-      ++i;
-    }
-    const int j = i + bid;
-    int Pi, Qi, Pj, Qj;
-    block_pair(i, round, nbp, Pi, Qi);
-    block_pair(j, round, nbp, Pj, Qj);
-    const T* Ui = Ubuf + (int64_t)i * JS * JS;
-    const T* Uj = Ubuf + (int64_t)j * JS * JS;
-    for (int e = tid; e < JS * JS; e += JT) {
-      const int a = e / JS, c = e % JS;
-      const int ga = gidx<JB>(a, Pi, Qi), gc = gidx<JB>(c, Pj, Qj);
-      X[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
-      Um[a][c] = Uj[e];
-    }
-    __syncthreads();
-    // T = X Uj
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
-    for (int k = 0; k < JS; ++k) {
-      T xa[RW], ub[RW];
-      for (int a = 0; a < RW; ++a) xa[a] = X[r0 + a][k];
-      for (int c = 0; c < RW; ++c) ub[c] = Um[k][c0 + c];
-      for (int a = 0; a < RW; ++a)
-        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + xa[a] * ub[c];
-    }
-    __syncthreads();
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) X[r0 + a][c0 + c] = acc[a][c];
-    for (int e = tid; e < JS * JS; e += JT) Um[e / JS][e % JS] = Ui[e];
-    __syncthreads();
-    // out = Ui^H T
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
-    for (int k = 0; k < JS; ++k) {
-      T ua[RW], xb[RW];
-      for (int a = 0; a < RW; ++a) ua[a] = conj(Um[k][r0 + a]);
-      for (int c = 0; c < RW; ++c) xb[c] = X[k][c0 + c];
-      for (int a = 0; a < RW; ++a)
-        for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + ua[a] * xb[c];
-    }
-    for (int a = 0; a < RW; ++a)
-      for (int c = 0; c < RW; ++c) {
-        const int ga = gidx<JB>(r0 + a, Pi, Qi), gc = gidx<JB>(c0 + c, Pj, Qj);
-        if (ga < m && gc < m) {
-          H[(int64_t)ga * m + gc] = acc[a][c];
-          if (i != j) H[(int64_t)gc * m + ga] = conj(acc[a][c]);
-        }
-      }
+  const int b = blockIdx.x;
+  if (b < npr) {
+    bj_h_update<T, JB>(m, nbp, round, b, b, H, Ubuf, X, Um);
+    return;
   }
+  int P, Q;
+  block_pair(b - npr, rn, nbp, P, Q);
+  const int i = bj_pair_of(P, round, nbp), j = bj_pair_of(Q, round, nbp);
+  if (i == j) return;
+  bj_h_update<T, JB>(m, nbp, round, min(i, j), max(i, j), H, Ubuf, X, Um);
 }
 
 template <typename T>
@@ -351,12 +406,12 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
   for (; sweep < max_sweeps; ++sweep) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
     const int nr = nbp - 1;
-    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + (vpend >= 0 ? nvi : 0)), dim3(JT), 0, s, m, nbp, 0, npr, H,
-                       Ub[g & 1], counter, 1.0e-15, vpend, V, Ub[(g + 1) & 1]);
+    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + (vpend >= 0 ? nvi + nh : 0)), dim3(JT), 0, s, m, nbp, 0, npr,
+                       H, Ub[g & 1], counter, 1.0e-15, vpend, V, Ub[(g + 1) & 1]);
     for (int r = 0; r < nr; ++r, ++g) {
-      hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(nh), dim3(JT), 0, s, m, nbp, r, H, Ub[g & 1]);
+      hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(2 * npr), dim3(JT), 0, s, m, nbp, r, (r + 1) % nr, H, Ub[g & 1]);
       if (r + 1 < nr) {
-        hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + nvi), dim3(JT), 0, s, m, nbp, r + 1, npr, H,
+        hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + nvi + nh), dim3(JT), 0, s, m, nbp, r + 1, npr, H,
                            Ub[(g + 1) & 1], counter, 1.0e-15, r, V, Ub[g & 1]);
       } else {
         vpend = r;
@@ -367,8 +422,8 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
     if (hcount == 0) break;
   }
   if (vpend >= 0)
-    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(nvi), dim3(JT), 0, s, m, nbp, 0, 0, H, Ub[g & 1], counter, 1.0e-15,
-                       vpend, V, Ub[(g + 1) & 1]);
+    hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(nvi + nh), dim3(JT), 0, s, m, nbp, 0, 0, H, Ub[g & 1], counter,
+                       1.0e-15, vpend, V, Ub[(g + 1) & 1]);
   hipLaunchKernelGGL((k_diag_out<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, H, evals, counter + 1);
   int sw = sweep + 1;
   if (hipMemcpyAsync(sweeps_out, &sw, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
