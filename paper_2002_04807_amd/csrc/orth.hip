@@ -56,20 +56,29 @@ __global__ __launch_bounds__(256) void k_chol_diag(int m, int jb, T* A, T* Linv,
     }
     __syncthreads();
   }
-  // pseudo-inverse of the lower-triangular block: column c by forward substitution,
-  // rows and columns of dropped indices are zero
+  // pseudo-inverse of the lower-triangular block: column c by forward substitution (the
+  // column in registers; same order of the terms), rows and columns of dropped indices
+  // are zero
   if (tid < CH_NB) {
     const int c = tid;
+    T xr[CH_NB];
+    bool kp[CH_NB];
+#pragma unroll
+    for (int k = 0; k < CH_NB; ++k) kp[k] = s_keep[k] != 0;
+#pragma unroll
     for (int i = 0; i < CH_NB; ++i) {
       T v = T(0.0);
-      if (i < bc && c < bc && i >= c && s_keep[i] && s_keep[c]) {
+      if (i < bc && c < bc && i >= c && kp[i] && kp[c]) {
         v = (i == c) ? T(1.0) : T(0.0);
-        for (int k = c; k < i; ++k)
-          if (s_keep[k]) v = v - a[i][k] * x[k][c];
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+          if (k >= c && kp[k]) v = v - a[i][k] * xr[k];
         v = (1.0 / real_part(a[i][i])) * v;
       }
-      x[i][c] = v;
+      xr[i] = v;
     }
+#pragma unroll
+    for (int i = 0; i < CH_NB; ++i) x[i][c] = xr[i];
   }
   __syncthreads();
   for (int e = tid; e < CH_NB * CH_NB; e += 256) {
