@@ -27,7 +27,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(int m, int jb, T* A, T* Linv, int* keep, double tau) {
   __shared__ T a[CH_NB][CH_NB + 1];
   __shared__ T x[CH_NB][CH_NB + 1];
-  __shared__ double s_d;
   __shared__ int s_keep[CH_NB];
   const int tid = threadIdx.x;
   const int bc = min(CH_NB, m - jb);
@@ -37,18 +36,16 @@ __global__ __launch_bounds__(256) void k_chol_diag(int m, int jb, T* A, T* Linv,
   }
   __syncthreads();
   for (int j = 0; j < bc; ++j) {
-    if (tid == 0) {
-      const double d = real_part(a[j][j]);
-      const int k = (d > tau) ? 1 : 0;
-      s_keep[j] = k;
-      s_d = k ? sqrt(d) : 0.0;
-    }
-    __syncthreads();
-    const double ljj = s_d;
+    // every thread takes the pivot itself (no broadcast round); a[j][j] is overwritten only
+    // in the trailing-update phase below, which does not read it
+    const double d = real_part(a[j][j]);
+    const int kj = (d > tau) ? 1 : 0;
+    const double ljj = kj ? sqrt(d) : 0.0;
+    if (tid == 0) s_keep[j] = kj;
     // column j below the diagonal
     if (tid > j && tid < bc) a[tid][j] = (ljj > 0.0) ? (1.0 / ljj) * a[tid][j] : T(0.0);
-    if (tid == 0) a[j][j] = T(ljj);
     __syncthreads();
+    if (tid == 0) a[j][j] = T(ljj);
     // trailing update of the block's lower triangle
     for (int e = tid; e < CH_NB * CH_NB; e += 256) {
       const int i = e / CH_NB, k = e % CH_NB;
