@@ -459,7 +459,7 @@ def bench_count(args, mf, torch, np, gen):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
               "(the contour nodes would shard across GPUs with one all-reduce of Q per iteration)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
