@@ -66,6 +66,8 @@ struct mfeast_ctx {
   size_t pinned_cap = 0;
   int* pinned_i = nullptr;  // column states of the batched BiCGSTAB
   size_t pinned_i_cap = 0;
+  char* pinned_aux = nullptr;  // small transfers of a call: contour nodes, LU flags, outputs
+  size_t pinned_aux_cap = 0;
   mf::CsrWork csrA, csrB;
   std::vector<mfeast_ctx*> workers;  // batched calls: one handle and stream per worker thread
   bool owns_stream = false;
@@ -116,6 +118,16 @@ struct mfeast_ctx {
       pinned_cap = bytes;
     }
     return pinned;
+  }
+  char* host_aux(size_t bytes) {
+    if (pinned_aux_cap < bytes) {
+      if (pinned_aux) (void)hipHostFree(pinned_aux);
+      pinned_aux = nullptr;
+      pinned_aux_cap = 0;
+      if (hipHostMalloc((void**)&pinned_aux, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      pinned_aux_cap = bytes;
+    }
+    return pinned_aux;
   }
   int* host_ints(size_t count) {
     const size_t bytes = count * sizeof(int) + 64;

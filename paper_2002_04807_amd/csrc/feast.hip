@@ -252,7 +252,14 @@ struct DenseOp : Operator<T> {
         ldbf = n;
       }
     }
-    MF_HIP_CHECK(hipMemcpyAsync(zdev, z.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+    // nodes up and factorization flags down through the handle's pinned area (nodes first,
+    // flags after them)
+    char* hx = h->host_aux((size_t)ne * (sizeof(c64) + 4) + 64);
+    if (!hx) return -2;
+    c64* hz = reinterpret_cast<c64*>(hx);
+    int* hinfo = reinterpret_cast<int*>(hx + (size_t)ne * sizeof(c64));
+    for (int j = 0; j < ne; ++j) hz[j] = z[j];
+    MF_HIP_CHECK(hipMemcpyAsync(zdev, hz, ne * sizeof(c64), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
     {
       const int tok = prof_begin(s);
@@ -265,8 +272,7 @@ struct DenseOp : Operator<T> {
       MF_TRY(panel_inverses<C>(s, n, ne, LU, Dinv, Pinv));
       prof_end(tok, s, K_OTHER, 0.0, 0.0);
     }
-    std::vector<int> hinfo(ne);
-    MF_HIP_CHECK(hipMemcpyAsync(hinfo.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(hinfo, linfo, ne * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     for (int j = 0; j < ne; ++j)
       if (hinfo[j] != 0) return -2;
@@ -901,8 +907,11 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   }
 
   if (info != 4 && info != 5 && info != -3 && info != -2) {
-    // copy eigenpairs to the caller's layout in the reported order
-    std::vector<double> e_out(m0), r_out(m0);
+    // copy eigenpairs to the caller's layout in the reported order (values through the
+    // handle's pinned area)
+    double* e_out = reinterpret_cast<double*>(h->host_aux(2 * (size_t)m0 * sizeof(double) + 64));
+    if (!e_out) return -2;
+    double* r_out = e_out + m0;
     for (int i = 0; i < m0; ++i) {
       h_perm[i] = order[i];
       e_out[i] = lam_cur[order[i]];
@@ -910,8 +919,8 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     }
     MF_HIP_CHECK(hipMemcpyAsync(d_perm, h_perm, m0 * sizeof(int), hipMemcpyHostToDevice, s));
     MF_TRY(copy_rm_to_cm<T>(s, n, m0, Xw, m0, Xu, ldx, d_perm));
-    MF_HIP_CHECK(hipMemcpyAsync(E, e_out.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out.data(), m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(E, e_out, m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out, m0 * sizeof(double), hipMemcpyHostToDevice, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     *m0p = m0;
   }
@@ -1084,6 +1093,7 @@ int mfeast_destroy(mfeast_handle h) {
   h->release_aux();
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->pinned_i) (void)hipHostFree(h->pinned_i);
+  if (h->pinned_aux) (void)hipHostFree(h->pinned_aux);
   delete h;
   return 0;
 }
