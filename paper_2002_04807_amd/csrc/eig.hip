@@ -239,7 +239,8 @@ __device__ inline void bj_sb_index(int bid, int npr, int& i, int& j) {
 template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int nsub, T* __restrict__ H,
                                                 T* __restrict__ Ubuf, int* __restrict__ rotcount, double tol,
-                                                int vround, T* __restrict__ V, const T* __restrict__ Uv) {
+                                                double big_rel, int vround, T* __restrict__ V,
+                                                const T* __restrict__ Uv) {
   constexpr int JS = 2 * JB;
   constexpr int NSI = (JS / 2) * (JS / 2), NUI = JS * (JS / 2);
   __shared__ T S[2][JS][JS + 1];
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int n
   }
   __syncthreads();
   const double abs_floor = 4.440892098500626e-16 * s_dmax + 1e-300;
-  const double big_floor = 1.0e-10 * s_dmax;
+  const double big_floor = big_rel * s_dmax;
   int my_big = 0;
   int cur = 0;
   for (int r = 0; r < JS - 1; ++r) {
@@ -387,7 +388,7 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 // 2 ints.
 template <typename T, int JB>
 static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
-                           int max_sweeps) {
+                           int max_sweeps, double big_rel) {
   constexpr int JS = 2 * JB;
   const int nb = (m + JB - 1) / JB;
   const int nbp = nb + (nb & 1);
@@ -407,12 +408,12 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, counter);
     const int nr = nbp - 1;
     hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + (vpend >= 0 ? nvi + nh : 0)), dim3(JT), 0, s, m, nbp, 0, npr,
-                       H, Ub[g & 1], counter, 1.0e-15, vpend, V, Ub[(g + 1) & 1]);
+                       H, Ub[g & 1], counter, 1.0e-15, big_rel, vpend, V, Ub[(g + 1) & 1]);
     for (int r = 0; r < nr; ++r, ++g) {
       hipLaunchKernelGGL((k_bj_upd<T, JB>), dim3(2 * npr), dim3(JT), 0, s, m, nbp, r, (r + 1) % nr, H, Ub[g & 1]);
       if (r + 1 < nr) {
         hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(npr + nvi + nh), dim3(JT), 0, s, m, nbp, r + 1, npr, H,
-                           Ub[(g + 1) & 1], counter, 1.0e-15, r, V, Ub[g & 1]);
+                           Ub[(g + 1) & 1], counter, 1.0e-15, big_rel, r, V, Ub[g & 1]);
       } else {
         vpend = r;
       }
@@ -423,7 +424,7 @@ static int block_jacobi_jb(hipStream_t s, int m, T* H, T* V, double* evals, int*
   }
   if (vpend >= 0)
     hipLaunchKernelGGL((k_bj_sub<T, JB>), dim3(nvi + nh), dim3(JT), 0, s, m, nbp, 0, 0, H, Ub[g & 1], counter,
-                       1.0e-15, vpend, V, Ub[(g + 1) & 1]);
+                       1.0e-15, big_rel, vpend, V, Ub[(g + 1) & 1]);
   hipLaunchKernelGGL((k_diag_out<T>), dim3((m + 255) / 256), dim3(256), 0, s, m, H, evals, counter + 1);
   int sw = sweep + 1;
   if (hipMemcpyAsync(sweeps_out, &sw, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess) return -2;
@@ -440,9 +441,10 @@ static int bj_width() {
 
 template <typename T>
 int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
-                 int max_sweeps) {
-  if (bj_width() == 8) return block_jacobi_jb<T, 8>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
-  return block_jacobi_jb<T, 16>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps);
+                 int max_sweeps, double big_rel) {
+  if (bj_width() == 8)
+    return block_jacobi_jb<T, 8>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps, big_rel);
+  return block_jacobi_jb<T, 16>(s, m, H, V, evals, sweeps_out, ubuf, counter, max_sweeps, big_rel);
 }
 
 size_t block_jacobi_work_bytes(int m, size_t elem) {
@@ -452,7 +454,7 @@ size_t block_jacobi_work_bytes(int m, size_t elem) {
   return 2 * (u8 > u16 ? u8 : u16) * elem + 64;
 }
 
-template int block_jacobi<double>(hipStream_t, int, double*, double*, double*, int*, double*, int*, int);
-template int block_jacobi<c64>(hipStream_t, int, c64*, c64*, double*, int*, c64*, int*, int);
+template int block_jacobi<double>(hipStream_t, int, double*, double*, double*, int*, double*, int*, int, double);
+template int block_jacobi<c64>(hipStream_t, int, c64*, c64*, double*, int*, c64*, int*, int, double);
 
 }  // namespace mf

@@ -128,11 +128,15 @@ int gram_equilibrate(hipStream_t s, int m, T* S, T* Tm, double* d, int* flag);
 // Hermitian eigensolver of the m x m row-major H (destroyed): V eigenvectors (columns),
 // evals unsorted.  m <= 64: one cooperative scalar Jacobi launch; larger m: block
 // Jacobi.  work: jacobi_work_bytes(m, sizeof(T)) bytes.
+// big_rel: a block-Jacobi sweep in which no rotation exceeds big_rel * max|diag(H)| is
+// the last one (1e-10 for results that are returned; the off-diagonal left behind is of
+// the order of big_rel^2 max|diag(H)|).
 template <typename T>
-int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work);
+int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work,
+                double big_rel = 1.0e-10);
 template <typename T>
 int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
-                 int max_sweeps);
+                 int max_sweeps, double big_rel);
 size_t block_jacobi_work_bytes(int m, size_t elem);
 inline size_t jacobi_work_bytes(int m, size_t elem) {
   const size_t a = (size_t)m * m * elem, b = block_jacobi_work_bytes(m, elem);

@@ -241,13 +241,13 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, T* Ha, T* Hb, T* V, doubl
 }
 
 template <typename T>
-int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work) {
+int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work, double big_rel) {
   if (m > 2 * JAC_MAXPAIR) return -2;
   if (m > 64 || !coop_allowed()) {
     // block Jacobi (eig.hip); work holds the round's unitaries, then a counter
     T* ubuf = reinterpret_cast<T*>(work);
     int* counter = reinterpret_cast<int*>(reinterpret_cast<char*>(work) + block_jacobi_work_bytes(m, sizeof(T)) - 64);
-    return block_jacobi<T>(s, m, H, V, evals, sweeps_out, ubuf, counter, 40);
+    return block_jacobi<T>(s, m, H, V, evals, sweeps_out, ubuf, counter, 40, big_rel);
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -2;
@@ -530,7 +530,7 @@ int scatter_rows(hipStream_t s, int rows, int cols, const T* src, const int* p, 
 #define MF_RR_INST(T)                                                                                          \
   template int col_absmax<T>(hipStream_t, int64_t, int, const T*, int64_t, double*);                           \
   template int gram_equilibrate<T>(hipStream_t, int, T*, T*, double*, int*);                                   \
-  template int jacobi_eigh<T>(hipStream_t, int, T*, T*, double*, int*, double*);                               \
+  template int jacobi_eigh<T>(hipStream_t, int, T*, T*, double*, int*, double*, double);                               \
   template int gather_scale_cols<T>(hipStream_t, int, int, const T*, int, const int*, const double*, T*, int); \
   template int scale_rows_permute_cols<T>(hipStream_t, int, int, const T*, int, const double*, const int*, T*, \
                                           int);                                                                \
