@@ -803,7 +803,9 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       double* ev_oo = d_gs;  // unused eigenvalues of C_OO
       T* Coo_o = Cm + (int64_t)mi * kk2 + mi;  // C_OO in place, leading dimension kk2
       MF_TRY(copy_block<T>(s, mo, mo, Coo_o, kk2, Coo, mo, false));
-      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw));
+      // (V_OO only prepares the full sweeps below, whose 1e-10 test decides the accuracy,
+      // so its own sweeps stop at rotations below 1e-4 max|diag|)
+      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw, 1.0e-4));
       // the rotated blocks are formed from the original C (V_OO^H C_OO V_OO keeps what the
       // eigensolver left off the diagonal, which the full sweeps below then remove)
       T* IOr = TG;                        // mi x mo
