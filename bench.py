@@ -31,9 +31,9 @@ TRAFFIC = {
     "contour_solve": {"bytes": 14.05e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
                       "sha256_16": "c3fcf19cca226602"},
-    "reduced_eig": {"bytes": 4.18e9,
+    "reduced_eig": {"bytes": 3.73e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip"],
-                    "sha256_16": "c9401cc08db9e0ca"},
+                    "sha256_16": "6da79370437ec863"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
