@@ -345,23 +345,23 @@ __global__ __launch_bounds__(NT) void k_leaf(int64_t n, int64_t ld, int k, int j
     const bool is_perm = (tid == LU_NB);
     const int cc = tid;
     const int64_t col = is_perm ? 0 : ((cc < jb) ? (k + cc) : (k + cc + ibc));
-    // all the gathers are issued before the first one is used
-    C gv[2 * IB];
-    int gp[2 * IB];
+    // all the gathers are issued before the first one is used; every slot loads (slots
+    // past nr repeat the first touched row, nr >= 1) so that the staging arrays stay in
+    // registers, and only the nr real ones are kept
+    if (is_perm) {
+      int gp[2 * IB];
 #pragma unroll
-    for (int e = 0; e < 2 * IB; ++e) {
-      if (e < nr) {
-        const int64_t row = row0 + s_rows[e];
-        if (is_perm) gp[e] = perm[row];
-        else gv[e] = LU[row * ld + col];
-      }
-    }
+      for (int e = 0; e < 2 * IB; ++e) gp[e] = perm[row0 + s_rows[e < nr ? e : 0]];
 #pragma unroll
-    for (int e = 0; e < 2 * IB; ++e) {
-      if (e < nr) {
-        if (is_perm) opv[e] = gp[e];
-        else oval[e][cc] = gv[e];
-      }
+      for (int e = 0; e < 2 * IB; ++e)
+        if (e < nr) opv[e] = gp[e];
+    } else {
+      C gv[2 * IB];
+#pragma unroll
+      for (int e = 0; e < 2 * IB; ++e) gv[e] = LU[(row0 + s_rows[e < nr ? e : 0]) * ld + col];
+#pragma unroll
+      for (int e = 0; e < 2 * IB; ++e)
+        if (e < nr) oval[e][cc] = gv[e];
     }
     for (int j = 0; j < ibc; ++j) {
       const int a = s_swa[j], b = s_swb[j];
