@@ -540,32 +540,42 @@ __global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int64_t ld, int k, 
   const int64_t col = (int64_t)k + LU_NB + (int64_t)blockIdx.x * CW + c;
   const bool live = blockIdx.x * CW + c < rest;
   __shared__ C Ls[LU_NB][LU_NB + 1];
-  __shared__ C rowbuf[2][CW];
+  __shared__ C rowbuf[2][RPT][CW];
   for (int e = tid; e < LU_NB * LU_NB; e += 256) {
     const int i = e / LU_NB, j = e % LU_NB;
     Ls[i][j] = LU[((int64_t)k + i) * ld + k + j];
   }
+  // row group w holds the RPT consecutive rows w*RPT .. w*RPT + RPT - 1 of its column
   C v[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) v[q] = live ? LU[((int64_t)k + w + RG * q) * ld + col] : C(0);
+  for (int q = 0; q < RPT; ++q) v[q] = live ? LU[((int64_t)k + w * RPT + q) * ld + col] : C(0);
   __syncthreads();
-  for (int i = 0; i < LU_NB - 1; ++i) {
-    if (w == i % RG) {
+  // block b: its owner finishes the substitution inside the block in registers and
+  // publishes the block's rows; the groups below apply them.  Every row receives the
+  // terms of the rows above it in increasing order, as in a row-by-row substitution.
+  for (int b = 0; b < RG; ++b) {
+    if (w == b) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == i / RG) rowbuf[i & 1][c] = v[q];
+      for (int qs = 0; qs < RPT; ++qs) {
+        const C x = v[qs];
+#pragma unroll
+        for (int q = qs + 1; q < RPT; ++q) v[q] = v[q] - Ls[b * RPT + q][b * RPT + qs] * x;
+        rowbuf[b & 1][qs][c] = x;
+      }
     }
     __syncthreads();
-    const C x = rowbuf[i & 1][c];
+    if (w > b) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = w + RG * q;
-      if (r > i) v[q] = v[q] - Ls[r][i] * x;
+      for (int qs = 0; qs < RPT; ++qs) {
+        const C x = rowbuf[b & 1][qs][c];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) v[q] = v[q] - Ls[w * RPT + q][b * RPT + qs] * x;
+      }
     }
   }
   if (live) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) LU[((int64_t)k + w + RG * q) * ld + col] = v[q];
+    for (int q = 0; q < RPT; ++q) LU[((int64_t)k + w * RPT + q) * ld + col] = v[q];
   }
 }
 
