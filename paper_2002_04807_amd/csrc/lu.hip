@@ -580,23 +580,71 @@ __global__ __launch_bounds__(256) void k_trsm_u12(int64_t n, int64_t ld, int k, 
 }
 
 // ---------------------------------------------------------------------------
+// Row interchanges of a panel (rows k + j <-> ipiv[k + j], j = 0 .. nbc - 1, in order) on the
+// columns outside the panel.  The net effect on the touched rows is a permutation: each
+// workgroup builds it once (slots 0 .. nbc - 1 are rows k .. k + nbc - 1, then the
+// distinct pivot rows below the panel; the swap sequence is replayed on slot labels),
+// then gathers the touched rows of its LSW_COLS columns into LDS and writes them back
+// permuted, instead of a chain of nbc dependent swaps per column.
+constexpr int LSW_COLS = 64;
+
 template <typename C>
-__global__ void k_laswp(int64_t n, int64_t ld, int k, int nbc, C* __restrict__ LUall, const int* __restrict__ ipiv_all) {
-  __shared__ int sp[LU_NB];
+__global__ __launch_bounds__(256) void k_laswp(int64_t n, int64_t ld, int k, int nbc, C* __restrict__ LUall,
+                                               const int* __restrict__ ipiv_all) {
+  __shared__ C buf[2 * LU_NB][LSW_COLS];
+  __shared__ int s_row[2 * LU_NB];    // row of each slot
+  __shared__ int s_lab[2 * LU_NB];    // slot whose original content ends in each slot
+  __shared__ int s_sb[LU_NB];         // slot of the pivot row of interchange j
+  __shared__ int s_nslot;
   const int node = blockIdx.y;
-  if (threadIdx.x < nbc) sp[threadIdx.x] = ipiv_all[(int64_t)node * n + k + threadIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    // lane j: interchange j; pivot rows below the panel get slots nbc, nbc + 1, ... in
+    // order of first appearance
+    const int j = tid;
+    const int b = j < nbc ? ipiv_all[(int64_t)node * n + k + j] : -1;
+    const bool below = j < nbc && b >= k + nbc;
+    int first = j;
+#pragma unroll 8
+    for (int f = 0; f < LU_NB; ++f) {
+      const int bf = __shfl(b, f);
+      if (f < first && below && bf == b) first = f;
+    }
+    const bool is_first = below && first == j;
+    const unsigned long long firsts = __ballot(is_first);
+    const int my_slot = nbc + __popcll(firsts & ((1ull << j) - 1ull));
+    const int slot_first = __shfl(my_slot, first);
+    if (j < nbc) {
+      s_row[j] = k + j;
+      s_sb[j] = below ? slot_first : b - k;
+    }
+    if (is_first) s_row[my_slot] = b;
+    if (j == 0) s_nslot = nbc + __popcll(firsts);
+  }
   __syncthreads();
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= n || (c >= k && c < k + nbc)) return;
-  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
-  for (int j = 0; j < nbc; ++j) {
-    const int64_t a = k + j, b = sp[j];
-    if (a != b) {
-      const C t0 = LU[a * ld + c];
-      LU[a * ld + c] = LU[b * ld + c];
-      LU[b * ld + c] = t0;
+  const int ns = s_nslot;
+  if (tid == 0) {
+    for (int q = 0; q < ns; ++q) s_lab[q] = q;
+    for (int j = 0; j < nbc; ++j) {
+      const int a = j, bb = s_sb[j];
+      const int t0 = s_lab[a];
+      s_lab[a] = s_lab[bb];
+      s_lab[bb] = t0;
     }
   }
+  __syncthreads();
+  const int cl = tid % LSW_COLS, g = tid / LSW_COLS;  // column in the workgroup, row group
+  const int64_t c = (int64_t)blockIdx.x * LSW_COLS + cl;
+  const bool live = c < n && !(c >= k && c < k + nbc);
+  C* __restrict__ LU = LUall + (int64_t)node * n * ld;
+  if (live)
+    for (int q = g; q < ns; q += 256 / LSW_COLS) buf[q][cl] = LU[(int64_t)s_row[q] * ld + c];
+  __syncthreads();
+  if (live)
+    for (int q = g; q < ns; q += 256 / LSW_COLS) {
+      const int from = s_lab[q];
+      if (from != q) LU[(int64_t)s_row[q] * ld + c] = buf[from][cl];
+    }
 }
 
 __global__ void k_perm_inverse(int64_t n, int ne, const int* __restrict__ perm, int* __restrict__ perm_inv) {
@@ -618,7 +666,8 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
     if (launch_leaves<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
     // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
     prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);
-    hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ld, (int)k, nbc, LU, ipiv);
+    hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + LSW_COLS - 1) / LSW_COLS), ne), dim3(256), 0, s, n, ld, (int)k,
+                       nbc, LU, ipiv);
     const int64_t rest = n - k - nbc;
     if (rest > 0) {
       // U12 = L11^-1 A12 in place (nbc == LU_NB whenever columns remain to the right)
