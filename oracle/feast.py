@@ -29,16 +29,19 @@ Readings where the guide is silent (each is listed with its reason in the
 design notes of the repository):
   R-spur    a Ritz pair (theta, x), x B-normalized, counts as found (one of the M)
             when theta lies in [Emin, Emax], its relative residual is below
-            SPURIOUS_RES = 0.1, and its absolute residual r = ||A x - theta B x||
-            satisfies r^2 < (Emax - theta)(theta - Emin).  Ritz values inside the
+            SPURIOUS_RES = 0.1, and its residual r = A x - theta B x satisfies
+            r^H B^-1 r < (Emax - theta)(theta - Emin).  Ritz values inside the
             interval that fail either test are spurious: their Ritz vectors mix
             eigenvectors from both sides of the interval whose filter weights are
             small and nearly equal, so they carry no eigenvalue; they are listed with
-            the outside values.  The second test is the Kato-Temple bound: a unit
-            vector orthogonal to every eigenvector in the interval (the interval then
-            holds no eigenvalue of A restricted to its complement) has
-            r^2 >= (Emax - theta)(theta - Emin), so a pair below it is not such a
-            mixture.  M, the trace and the convergence test use the found pairs only.
+            the outside values.  The second test is the Kato-Temple bound for the
+            operator B^-1 A, self-adjoint in the B inner product, whose residual norm
+            for x is ||B^-1 r||_B = (r^H B^-1 r)^(1/2): a B-unit vector B-orthogonal
+            to every eigenvector in the interval (the pencil restricted to their
+            complement has no eigenvalue there) has r^H B^-1 r >= (Emax - theta)
+            (theta - Emin), so a pair below it is not such a mixture.  The test is
+            unchanged under (A, B) -> (beta A, beta B), as the eigenpairs are.
+            M, the trace and the convergence test use the found pairs only.
   R-order   E(1:M) are the found Ritz values ascending, followed by all others
             ascending; X columns follow E.
   R-closed  the interval is closed.
@@ -148,14 +151,15 @@ def expand_uplo(A, uplo):
     return T + T.conj().T + D
 
 
-def _ordered(lam, res, emin, emax, rabs):
+def _ordered(lam, res, emin, emax, rbinv2):
     """Permutation: found pairs (R-spur) ascending, then all others ascending.
 
-    rabs: absolute residual norms ||A x - lambda B x|| of the B-normalized Ritz vectors.
+    rbinv2: r^H B^-1 r per column, r = A x - lambda B x of the B-normalized Ritz
+    vectors (||r||^2 for B = I).
     Returns (perm, M, n_inside) with n_inside the count of Ritz values in the
     interval regardless of their residual."""
     inside = (lam >= emin) & (lam <= emax)
-    certified = rabs ** 2 < (emax - lam) * (lam - emin)
+    certified = rbinv2 < (emax - lam) * (lam - emin)
     found = inside & (res < SPURIOUS_RES) & certified
     idx_in = np.where(found)[0]
     idx_out = np.where(~found)[0]
@@ -192,6 +196,21 @@ def rayleigh_ritz(Q, A, B):
     lam, Z = np.linalg.eigh(C)
     W = d[:, None] * (G @ Z)
     return lam, W, 0
+
+
+def kato_temple_terms(R, b_solve=None):
+    """r^H B^-1 r for every column r of R (R-spur); b_solve(R) = B^-1 R, None for B = I."""
+    if b_solve is None:
+        return np.sum(np.abs(R) ** 2, axis=0)
+    return np.real(np.sum(np.conj(R) * b_solve(R), axis=0))
+
+
+def _dense_b_solver(B):
+    """B^-1 rhs by a Cholesky factorization of the positive definite B (library routine)."""
+    if B is None:
+        return None
+    cf = sla.cho_factor(B, lower=True)
+    return lambda rhs: sla.cho_solve(cf, rhs)
 
 
 class _Factored:
@@ -266,7 +285,8 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
         B = expand_uplo(np.asarray(B), uplo).astype(dt)
     z, w = _nodes(emin, emax, fpm, zne, wne)
     facts = [_Factored(zj, A, B) for zj in z]
-    return iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, facts, form)
+    return iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, facts, form,
+                   b_solve=_dense_b_solver(B))
 
 
 def _empty(info, m0):
@@ -281,13 +301,17 @@ def _nodes(emin, emax, fpm, zne, wne):
     return np.asarray(zne, np.complex128), np.asarray(wne, np.complex128)
 
 
-def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form="residual"):
+def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form="residual",
+            b_solve=None):
     """The subspace iteration shared by the dense and the sparse drivers.
 
     A, B: objects supporting ``@`` with an n x m block (B None means identity).
     solvers[j]: object with solve(rhs) for (z_j B - A)^-1 rhs and, for complex
     Hermitian problems, solve_h(rhs) for (z_j B - A)^-H rhs.
+    b_solve: B^-1 applied to a block (needed when B is given; R-spur).
     """
+    if B is not None and b_solve is None:
+        raise ValueError("a B^-1 solver is needed for the found-pair test when B is given")
     f = lambda i: int(fpm[i - 1])  # noqa: E731
     dt = np.float64 if real_problem else np.complex128
     out = _empty(0, m0)
@@ -321,16 +345,15 @@ def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form=
         X = Q @ W
         BX = X if B is None else B @ X
         R = A @ X - BX * lam[None, :]
-        rabs = np.linalg.norm(R, axis=0)
-        res = rabs / (alpha * np.linalg.norm(BX, axis=0))
-        perm, M, n_inside = _ordered(lam, res, emin, emax, rabs)
+        res = np.linalg.norm(R, axis=0) / (alpha * np.linalg.norm(BX, axis=0))
+        perm, M, n_inside = _ordered(lam, res, emin, emax, kato_temple_terms(R, b_solve))
         lam_sorted, X, res = lam[perm], X[:, perm], res[perm]
         trace = float(np.sum(lam_sorted[:M]))
         epsout = 1.0 if trace_prev is None else abs(trace - trace_prev) / alpha
         trace_prev = trace
         maxres = float(np.max(res[:M])) if M > 0 else 0.0
         out["history"].append({"it": k, "M": M, "trace": trace, "epsout": epsout,
-                               "maxres": maxres, "m0": X.shape[1]})
+                               "maxres": maxres, "m0": X.shape[1], "E": lam_sorted[:M].copy()})
         out.update(E=lam_sorted, X=X, M=M, res=res, epsout=epsout, loop=k, m0=X.shape[1])
         if n_inside == 0:
             out["info"] = 1

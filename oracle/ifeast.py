@@ -24,6 +24,7 @@ Readings where the guide is silent:
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .feast import _empty, _nodes, feastinit, iterate, validate
 
@@ -119,6 +120,10 @@ def feast_csr(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None, form=
     counter = [0]
     tol = 10.0 ** (-f(45))
     solvers = [_ShiftedBiCG(zj, A, Bm, tol, f(46), counter) for zj in z]
-    out = iterate(A, Bm, n, True, emin, emax, m0, fpm, X0, z, w, solvers, form)
+    b_solve = None
+    if Bm is not None:
+        lu = spla.splu(Bm.tocsc())
+        b_solve = lambda rhs: lu.solve(np.asarray(rhs, dtype=np.float64))  # noqa: E731
+    out = iterate(A, Bm, n, True, emin, emax, m0, fpm, X0, z, w, solvers, form, b_solve=b_solve)
     out["fpm60"] = counter[0]
     return out
