@@ -284,9 +284,13 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
     if B is not None:
         B = expand_uplo(np.asarray(B), uplo).astype(dt)
     z, w = _nodes(emin, emax, fpm, zne, wne)
+    try:
+        b_solve = _dense_b_solver(B)
+    except np.linalg.LinAlgError:
+        return _empty(-3, m0)  # Table tab_info -3: B may not be positive definite
     facts = [_Factored(zj, A, B) for zj in z]
     return iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, facts, form,
-                   b_solve=_dense_b_solver(B))
+                   b_solve=b_solve)
 
 
 def _empty(info, m0):

@@ -122,7 +122,10 @@ def feast_csr(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None, form=
     solvers = [_ShiftedBiCG(zj, A, Bm, tol, f(46), counter) for zj in z]
     b_solve = None
     if Bm is not None:
-        lu = spla.splu(Bm.tocsc())
+        try:
+            lu = spla.splu(Bm.tocsc())
+        except RuntimeError:
+            return _empty(-3, m0)  # B singular (Table tab_info -3)
         b_solve = lambda rhs: lu.solve(np.asarray(rhs, dtype=np.float64))  # noqa: E731
     out = iterate(A, Bm, n, True, emin, emax, m0, fpm, X0, z, w, solvers, form, b_solve=b_solve)
     out["fpm60"] = counter[0]
