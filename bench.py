@@ -496,6 +496,7 @@ def main():
         outs, times, _ = run_steps(mf, torch, h, At, Bt, True, args.profile_steps, False)
         print("bench: profile run %s s, M=%s" % (["%.3f" % t for t in times], [o["M"] for o in outs]),
               file=sys.stderr, flush=True)
+        h.close()
         return
 
     run_steps(mf, torch, h, At, Bt, True, args.warmup, False)

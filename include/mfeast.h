@@ -203,10 +203,14 @@ int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, int64_t lda,
                        const double* gX, int64_t ldgx, int32_t precision, double* gA,
                        int64_t ldga, double* gdiag);
 
-/* Timing of the last call in seconds, host clock around synchronized phases (the
- * guide's "FEAST-RCI timing" split, Section 2.4): out[0] factorization, [1] contour
- * solves, [2] Rayleigh-Ritz products and residuals, [3] reduced eigensolver, [4] other,
- * [5] total, [6] number of subspace iterations, [7] reserved.  out: host, 8 doubles. */
+/* Timing of the last call in seconds, host clock around synchronized phases, split as
+ * the guide's "FEAST-RCI timing" table (Section 2.4): out[0] Fact. (shift-form and LU of
+ * every node), [1] Solve (contour solves with their right-hand-side preparation and the
+ * quadrature sum), [2] A*x (the products A Q), [3] B*x (B Y, B Q, and the B^-1 products
+ * of the found-pair test; 0 for B = I), [4] Misc. (Gram products, B-orthonormalization,
+ * reduced eigensolver, residuals and the host's decisions), [5] total, [6] number of
+ * subspace iterations (loop + 1), [7] the reduced eigensolver's part of [4].
+ * out: host, 8 doubles.  The batched entry point reports only [5] and [6] (problems). */
 int mfeast_get_timing(mfeast_handle h, double* out);
 
 /* Device timing by kernel class of the last call, recorded with HIP events on the

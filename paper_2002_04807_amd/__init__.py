@@ -10,6 +10,7 @@ read the module), but every call raises: there is no fallback implementation.
 """
 
 import ctypes
+import sys
 import os
 
 import numpy as np
@@ -155,6 +156,10 @@ class Handle:
         self.ptr = None
 
     def __del__(self):
+        # no HIP call while the interpreter shuts down: the runtime (and a profiler's tool
+        # library) may already be finalized; the process exit releases the device memory
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

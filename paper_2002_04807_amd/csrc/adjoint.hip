@@ -217,6 +217,7 @@ extern "C" int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, i
   if (gA == nullptr && gdiag == nullptr) return -113;
   if (gA != nullptr && ldga < n) return -114;
   if (hipSetDevice(h->device) != hipSuccess) return -900;
+  GemmScratchScope scratch_scope(h);
   prof_enable(false);
   if (precision == 1) return adjoint_run<c32>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 4);
   return adjoint_run<c64>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 1);

@@ -18,6 +18,7 @@ enum Slot {
   S_BI_VEC, S_BI_BH, S_BI_COL, S_BI_TILES, S_BI_PART, S_BI_BUF,
   S_ADJ_AD, S_ADJ_XR, S_ADJ_R, S_ADJ_Y, S_ADJ_T, S_ADJ_SMALL,
   S_IR_XF, S_IR_YC, S_IR_T, S_IR_AX, S_IR_BX,
+  S_SPLITK,
   S_NSLOTS
 };
 
@@ -140,4 +141,20 @@ struct mfeast_ctx {
     }
     return pinned_i;
   }
+};
+
+// split-K scratch of a handle's GEMMs: its own slot, grown after the device is idle (earlier
+// launches may still read the old buffer)
+inline void* ctx_splitk_scratch(void* owner, size_t bytes) {
+  mfeast_ctx* c = static_cast<mfeast_ctx*>(owner);
+  if (c->cap[mf::S_SPLITK] < bytes && c->buf[mf::S_SPLITK] != nullptr) (void)hipDeviceSynchronize();
+  return c->ws(mf::S_SPLITK, bytes);
+}
+
+// binds a handle's split-K scratch to the calling thread for the duration of an entry point
+struct GemmScratchScope {
+  explicit GemmScratchScope(mfeast_ctx* c) { mf::set_gemm_scratch(&ctx_splitk_scratch, c); }
+  ~GemmScratchScope() { mf::set_gemm_scratch(nullptr, nullptr); }
+  GemmScratchScope(const GemmScratchScope&) = delete;
+  GemmScratchScope& operator=(const GemmScratchScope&) = delete;
 };

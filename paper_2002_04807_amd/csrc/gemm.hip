@@ -16,7 +16,6 @@
 // n x M0) split K over several workgroups per tile: each writes its partial tile to a
 // scratch buffer and a second kernel adds the partials in split order (deterministic).
 #include <algorithm>
-#include <map>
 
 #include "kernels.hpp"
 
@@ -343,38 +342,20 @@ __global__ void k_gemm_splitk_sum(GemmArgs g, int nsplit, const R* __restrict__ 
   if constexpr (CPLX) C[off + 1] = vi;
 }
 
-// scratch for split-K partials: grown on demand, one buffer per host thread and device,
-// released when the thread ends
+// scratch for split-K partials, supplied by the handle the calling thread works for
+// (bound by the entry points; without one the products run without splitting K)
 namespace {
-struct SplitScratch {
-  std::map<int, std::pair<void*, size_t>> bufs;
-  ~SplitScratch() {
-    for (auto& kv : bufs)
-      if (kv.second.first) {
-        (void)hipSetDevice(kv.first);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(kv.second.first);
-      }
-  }
-};
+thread_local ScratchFn g_scratch_fn = nullptr;
+thread_local void* g_scratch_owner = nullptr;
 }  // namespace
 
+void set_gemm_scratch(ScratchFn fn, void* owner) {
+  g_scratch_fn = fn;
+  g_scratch_owner = owner;
+}
+
 static void* splitk_scratch(size_t bytes) {
-  thread_local SplitScratch scratch;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  auto& b = scratch.bufs[dev];
-  if (b.second < bytes) {
-    if (b.first) {
-      (void)hipDeviceSynchronize();  // earlier launches may still read the old buffer
-      (void)hipFree(b.first);
-    }
-    b.first = nullptr;
-    b.second = 0;
-    if (hipMalloc(&b.first, bytes) != hipSuccess) return nullptr;
-    b.second = bytes;
-  }
-  return b.first;
+  return g_scratch_fn != nullptr ? g_scratch_fn(g_scratch_owner, bytes) : nullptr;
 }
 
 template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int BM, int BN, int BK, bool G3M>

@@ -35,6 +35,10 @@ template <typename R, bool CPLX>
 int gemm_op(hipStream_t s, GemmOp opa, GemmOp opb, const GemmArgs& g, int batch);
 template <typename R, bool CPLX>
 int gemm(hipStream_t s, bool a_mcontig, bool conj_a, const GemmArgs& g, int batch);
+// Device scratch for the split-K partial sums of the calling host thread: fn(owner, bytes)
+// returns a buffer of at least `bytes` (or nullptr: the product then runs unsplit).
+using ScratchFn = void* (*)(void* owner, size_t bytes);
+void set_gemm_scratch(ScratchFn fn, void* owner);
 // complex FP32 products of the calling host thread use Gauss's three-product scheme
 // (default on; fpm(53) = 1 selects the four-product scheme for a call)
 void set_gemm_3m(bool on);
@@ -58,11 +62,12 @@ template <typename T>
 int expand_full(hipStream_t s, char uplo, int64_t n, const T* src, int64_t lds, T* dst);
 
 // LU_j = z_j * B - A, row-major with row stride lu_ld(n) (n x lu_ld(n) entries per
-// node), for j = 0..ne-1 (B == nullptr means identity); also sets perm_j = identity.
-// A, B: full storage column-major (ld).
+// node), for j = 0..ne-1 (B == nullptr means identity); with b_node, matrix ne is B
+// itself (factored beside the shifted matrices for B^-1 products); also sets perm_j =
+// identity for every matrix written.  A, B: full storage column-major (ld).
 template <typename T, typename C>
 int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
-               const c64* z_dev, int ne, C* LU, int* perm);
+               const c64* z_dev, int ne, C* LU, int* perm, bool b_node = false);
 
 // Blocked right-looking LU with partial pivoting of all ne matrices (P A = L U).
 // ipiv (n per node, global row indices), perm (n per node: (PA)[i] = A[perm[i]]),
@@ -113,6 +118,13 @@ int gather_rows_c64(hipStream_t s, int64_t n, int m, int ne, const c64* src, con
 template <typename T, typename C>
 int ir_residual(hipStream_t s, int64_t n, int m, int ne, const T* rhs, int64_t ld, const double* cs, const c64* z,
                 bool conj_z, const int* perm, const c64* AX, const c64* BX, C* out);
+
+// out[c] = Re(sum_r conj(R[r][c]) X[r][c]) / cs[c] for row-major n x m blocks R (FP64)
+// and X (solve precision), both with leading dimension m; partial: ceil(n / 256) * m
+// doubles.  With X = B^-1 R diag(cs) this is r_c^H B^-1 r_c.
+template <typename T, typename C>
+int col_dots_mixed(hipStream_t s, int64_t n, int m, const T* R, const C* X, const double* cs, double* out,
+                   double* partial);
 
 // Q = (resid ? X*diag(rho) : 0) + diag-scaled sum over nodes (see accumulate in solve.hip).
 template <typename T, typename C>
@@ -250,6 +262,11 @@ int bicgstab_batched(hipStream_t s, const BiSys<C>& sys, int maxit, double tol, 
 // bh = rhs .* colscale (row-major n x m0), in the BiCGSTAB precision
 template <typename R>
 int bi_rhs(hipStream_t s, int64_t n, int m0, const double* rhs, const double* cs, R* bh);
+// out[c] = sign * Re(sum_i R[i][c] x(i, c)) / cs[c]; R row-major n x m FP64, x tile-major
+// (m columns of one node); partial: ceil(n / 256) * m doubles
+template <typename C>
+int bi_coldots(hipStream_t s, int64_t n, int m, const double* R, const C* x, const double* cs, double sign,
+               double* out, double* partial);
 // quadrature sum of the sparse path, see sparse.hip (mode 0: set, 1: set + rho X, 2: add)
 template <typename C>
 int bi_accumulate(hipStream_t s, int64_t n, int m0, int nj, int j0, const C* x, const c64* cf, const double* rho,

@@ -56,7 +56,7 @@ int expand_full(hipStream_t s, char uplo, int64_t n, const T* src, int64_t lds, 
 // ---------------------------------------------------------------------------
 template <typename T, typename C>
 __global__ void k_shift_form(int64_t n, int64_t ld, const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-                             int64_t ldb, const c64* __restrict__ z, int ne, C* __restrict__ LU,
+                             int64_t ldb, const c64* __restrict__ z, int ne, int bnode, C* __restrict__ LU,
                              int* __restrict__ perm) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t i = blockIdx.y;
@@ -71,15 +71,17 @@ __global__ void k_shift_form(int64_t n, int64_t ld, const T* __restrict__ A, int
     const c64 v = z[j] * b - a;
     LU[(int64_t)j * n * ld + i * ld + c] = convert<C, c64>(v);
   }
+  if (bnode) LU[(int64_t)ne * n * ld + i * ld + c] = convert<C, c64>(b);
   if (i == 0)
-    for (int j = 0; j < ne; ++j) perm[(int64_t)j * n + c] = (int)c;
+    for (int j = 0; j < ne + bnode; ++j) perm[(int64_t)j * n + c] = (int)c;
 }
 
 template <typename T, typename C>
 int shift_form(hipStream_t s, int64_t n, const T* A, int64_t lda, const T* B, int64_t ldb,
-               const c64* z_dev, int ne, C* LU, int* perm) {
+               const c64* z_dev, int ne, C* LU, int* perm, bool b_node) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-  hipLaunchKernelGGL((k_shift_form<T, C>), grid, dim3(256), 0, s, n, lu_ld(n), A, lda, B, ldb, z_dev, ne, LU, perm);
+  hipLaunchKernelGGL((k_shift_form<T, C>), grid, dim3(256), 0, s, n, lu_ld(n), A, lda, B, ldb, z_dev, ne,
+                     b_node ? 1 : 0, LU, perm);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -697,10 +699,10 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
 
 template int expand_full<double>(hipStream_t, char, int64_t, const double*, int64_t, double*);
 template int expand_full<c64>(hipStream_t, char, int64_t, const c64*, int64_t, c64*);
-template int shift_form<double, c32>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, c32*, int*);
-template int shift_form<double, c64>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, c64*, int*);
-template int shift_form<c64, c32>(hipStream_t, int64_t, const c64*, int64_t, const c64*, int64_t, const c64*, int, c32*, int*);
-template int shift_form<c64, c64>(hipStream_t, int64_t, const c64*, int64_t, const c64*, int64_t, const c64*, int, c64*, int*);
+template int shift_form<double, c32>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, c32*, int*, bool);
+template int shift_form<double, c64>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, c64*, int*, bool);
+template int shift_form<c64, c32>(hipStream_t, int64_t, const c64*, int64_t, const c64*, int64_t, const c64*, int, c32*, int*, bool);
+template int shift_form<c64, c64>(hipStream_t, int64_t, const c64*, int64_t, const c64*, int64_t, const c64*, int, c64*, int*, bool);
 template int lu_factor<c32>(hipStream_t, int64_t, int, c32*, int*, int*, int*, int*, c32*);
 template int lu_factor<c64>(hipStream_t, int64_t, int, c64*, int*, int*, int*, int*, c64*);
 

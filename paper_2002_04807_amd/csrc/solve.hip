@@ -41,6 +41,46 @@ int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const
 }
 
 // ---------------------------------------------------------------------------
+// Column dot products of an FP64 block with a block in the solve precision, in
+// 256-row chunks (one partial per chunk and column), then one ordered sum per column.
+constexpr int DOT_ROWS = 256;
+
+template <typename T, typename C>
+__global__ void k_coldot_mixed_partial(int64_t n, int m, const T* __restrict__ R, const C* __restrict__ X,
+                                       double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (c >= m) return;
+  double acc = 0.0;
+  const int64_t r1 = ((chunk + 1) * DOT_ROWS < n) ? (chunk + 1) * DOT_ROWS : n;
+  for (int64_t r = chunk * DOT_ROWS; r < r1; ++r) {
+    const c64 a = convert<c64, T>(R[r * m + c]);
+    const c64 x = convert<c64, C>(X[r * m + c]);
+    acc += a.re * x.re + a.im * x.im;
+  }
+  part[chunk * m + c] = acc;
+}
+
+__global__ void k_coldot_mixed_final(int m, int nchunk, const double* __restrict__ part,
+                                     const double* __restrict__ cs, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  double acc = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) acc += part[(int64_t)ch * m + c];
+  out[c] = acc / cs[c];
+}
+
+template <typename T, typename C>
+int col_dots_mixed(hipStream_t s, int64_t n, int m, const T* R, const C* X, const double* cs, double* out,
+                   double* partial) {
+  const int nchunk = (int)((n + DOT_ROWS - 1) / DOT_ROWS);
+  hipLaunchKernelGGL((k_coldot_mixed_partial<T, C>), dim3((m + 255) / 256, nchunk), dim3(256), 0, s, n, m, R, X,
+                     partial);
+  hipLaunchKernelGGL(k_coldot_mixed_final, dim3((m + 255) / 256), dim3(256), 0, s, m, nchunk, partial, cs, out);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ---------------------------------------------------------------------------
 // Blocked triangular solves, two levels.  The rows are cut into panels of TRSM_PH =
 // TRSM_SUB * LU_NB rows.  Once per factorization the inverse of every panel's
 // diagonal block of L and of U is formed (panel_inverses); a solve then takes two
@@ -394,5 +434,14 @@ template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*,
 template int accumulate<double, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
 template int accumulate<c64, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int);
 template int accumulate<c64, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int);
+
+template int col_dots_mixed<double, c32>(hipStream_t, int64_t, int, const double*, const c32*, const double*,
+                                         double*, double*);
+template int col_dots_mixed<double, c64>(hipStream_t, int64_t, int, const double*, const c64*, const double*,
+                                         double*, double*);
+template int col_dots_mixed<c64, c32>(hipStream_t, int64_t, int, const c64*, const c32*, const double*, double*,
+                                      double*);
+template int col_dots_mixed<c64, c64>(hipStream_t, int64_t, int, const c64*, const c64*, const double*, double*,
+                                      double*);
 
 }  // namespace mf

@@ -882,6 +882,45 @@ template int csr_full<float>(hipStream_t, int64_t, const double*, const int32_t*
                              CsrWork&, CsrMat<float>&, int*);
 template int csr_full<double>(hipStream_t, int64_t, const double*, const int32_t*, const int32_t*, int, char,
                               CsrWork&, CsrMat<double>&, int*);
+// out[c] = sign * Re(sum_i R[i][c] x(i, c)) / cs[c]: R row-major n x m FP64 (ld m), x
+// tile-major (one node of m columns); 256-row partials, then one ordered sum per column
+template <typename C>
+__global__ void k_bi_coldot_partial(int64_t n, int m, const double* __restrict__ R, const C* __restrict__ x,
+                                    double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (c >= m) return;
+  double acc = 0.0;
+  const int64_t r1 = ((chunk + 1) * 256 < n) ? (chunk + 1) * 256 : n;
+  for (int64_t i = chunk * 256; i < r1; ++i) {
+    const c64 d = convert<c64, C>(x[(((int64_t)c >> 6) * n + i) * 64 + (c & 63)]);
+    acc += R[i * m + c] * d.re;
+  }
+  part[chunk * m + c] = acc;
+}
+
+__global__ void k_bi_coldot_final(int m, int nchunk, const double* __restrict__ part, const double* __restrict__ cs,
+                                  double sign, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  double acc = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) acc += part[(int64_t)ch * m + c];
+  out[c] = sign * acc / cs[c];
+}
+
+template <typename C>
+int bi_coldots(hipStream_t s, int64_t n, int m, const double* R, const C* x, const double* cs, double sign,
+               double* out, double* partial) {
+  const int nchunk = (int)((n + 255) / 256);
+  hipLaunchKernelGGL((k_bi_coldot_partial<C>), dim3((m + 255) / 256, nchunk), dim3(256), 0, s, n, m, R, x, partial);
+  hipLaunchKernelGGL(k_bi_coldot_final, dim3((m + 255) / 256), dim3(256), 0, s, m, nchunk, partial, cs, sign, out);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template int bi_coldots<c32>(hipStream_t, int64_t, int, const double*, const c32*, const double*, double, double*,
+                             double*);
+template int bi_coldots<c64>(hipStream_t, int64_t, int, const double*, const c64*, const double*, double, double*,
+                             double*);
 template int bicgstab_batched<c32>(hipStream_t, const BiSys<c32>&, int, double, std::vector<int>&, int*, int*);
 template int bicgstab_batched<c64>(hipStream_t, const BiSys<c64>&, int, double, std::vector<int>&, int*, int*);
 template int bi_rhs<float>(hipStream_t, int64_t, int, const double*, const double*, float*);
