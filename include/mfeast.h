@@ -63,18 +63,40 @@ int mfeast_set_stream(mfeast_handle h, void* hip_stream);
  * residual of every node's system and solves it again with the FP32 factors),
  * fpm(51) seed of the random starting block, fpm(52) = 1 records per-class kernel
  * timings for mfeast_get_profile, fpm(53) = 1 forms complex FP32 products with four
- * real products instead of Gauss's three (default 0: three). */
+ * real products instead of Gauss's three (default 0: three), fpm(54) = 1..99 the flat
+ * band of the Zolotarev rule in percent of the half-width (default 90; see
+ * mfeast_zolotarev).  Return 154 from the drivers: fpm(16)=2 with fpm(54) outside 1..99. */
 void mfeast_init(int32_t* fpm);
 
 /* Half-contour nodes and weights (zfeast_contour; Section 4.2 "Search contour",
  * Table tab_contour).  Ellipse through Emin and Emax centred on the real axis with
  * axis ratio ratio_pct/100; rule 0 Gauss-Legendre (ne in 1..20, 24, 32, 40, 48, 56),
- * 1 trapezoidal (ne >= 1).  zne, wne: host arrays of 2*ne doubles (re, im) receiving
+ * 1 trapezoidal (ne >= 1), 2 Zolotarev (fpm(16)=2; ne as for Gauss; ratio_pct is then
+ * the flat band fpm(54) in 1..99, and the rule's constant term is returned by
+ * mfeast_zolotarev).  zne, wne: host arrays of 2*ne doubles (re, im) receiving
  * the upper-half nodes z_j (j = 1 nearest Emin) and weights w_j such that the spectral
  * projector is approximated by sum_j [w_j f(z_j) + conj(w_j) f(conj z_j)].
- * Returns 0, 200, 102, 116, 118 or -(100+i) for a NULL array. */
+ * Returns 0, 200, 102, 116, 118, 154 or -(100+i) for a NULL array. */
 int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct,
                    double* zne, double* wne);
+
+/* Zolotarev rule (fpm(16)=2, Table tab_fpm: Hermitian problems only; the guide cites
+ * Guettel, Polizzi, Tang and Viaud 2015 for it).  Zolotarev's best uniform approximation
+ * Z of sign(x) on [-1,-l] u [l,1] by an odd rational function of type (2ne-1, 2ne),
+ * composed with the map x = kappa (1 + t)/(1 - t), t = (lambda - c)/r, gives the filter
+ * f(lambda) = (1 + Z)/2 of the interval [emin, emax] (centre c, half-width r): within
+ * delta/2 of 1 for |t| <= a and of 0 for |t| >= 1/a, exactly 1/2 at emin and emax, with
+ * a = band_pct/100, kappa = (1 - a)/(1 + a), l = kappa^2 and delta Zolotarev's error.
+ * Its ne poles in the upper half plane lie on the circle through emin and emax.  In
+ * partial fractions f(lambda) = c_inf + sum_j 2 Re(w_j / (z_j - lambda)).
+ *  zne, wne  host, 2*ne doubles each: nodes z_j (ascending real part) and weights w_j
+ *  c_inf     host, 1 double: the constant term f(infinity) (of size delta/2); the
+ *            drivers apply it to the block itself (c_inf Y in the first contour, and
+ *            inside the filter of the residual form)
+ * Returns 0, 200 (emin >= emax), 102 (ne not a permitted Gauss count), 154 (band_pct
+ * outside 1..99), or -(100+i) for a NULL array argument i. */
+int mfeast_zolotarev(double emin, double emax, int32_t ne, int32_t band_pct, double* zne, double* wne,
+                     double* c_inf);
 
 /* Dense real symmetric problem (dfeast_sygv / dfeast_syev and their {x} forms).
  *  h       handle
@@ -96,7 +118,8 @@ int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t r
  *  epsout  host: relative trace change |trace_k - trace_{k-1}| / alpha
  *  loop    host: index of the last subspace iteration (0 = first contour)
  *  zne,wne host, 2*fpm(2) doubles each, or both NULL: custom nodes and half-contour
- *          weights (expert mode); NULL = generated from fpm(2), fpm(16), fpm(18)
+ *          weights (expert mode, no constant term); NULL = generated from fpm(2),
+ *          fpm(16), fpm(18), and fpm(54) for the Zolotarev rule (fpm(16)=2)
  * fpm(42)=1 (default) factors and solves the shifted systems in complex FP32 with the
  * FP64 residual form of the iteration (plus fpm(50) refinement steps of each solve);
  * fpm(42)=0 uses complex FP64 throughout.  Return 150: fpm(50) outside 0..8; 153:

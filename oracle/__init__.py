@@ -8,7 +8,8 @@ meet on seeded inputs produced by ``workloads/``.
 
 Every function follows a passage of the FEAST v4.0 User Guide (arXiv:2002.04807)
 and is written to be checked against that text by eye: the contour quadrature
-(Section "Search contour", Table tab_contour), the Hermitian subspace iteration
+(Section "Search contour", Table tab_contour; the Zolotarev rule fpm(16)=2 in
+zolotarev.py), the Hermitian subspace iteration
 with Rayleigh-Ritz (Section 1.1 "The FEAST Algorithm", Section 3.2 "FEAST
 Hermitian", Tables tab-common1 and tab-rci1, the Hermitian RCI templates), the
 residual inverse iteration of v4.0 (Section 1.2, Section 3.1 "Tips"), the
@@ -17,6 +18,7 @@ Readings taken where the guide is silent are listed in each module header.
 """
 
 from .contour import half_contour, rational_filter, gauss_legendre_rule
+from .zolotarev import zolotarev_contour, zolotarev_filter, zolotarev_sign
 from .splitmix import splitmix64_uniform, initial_subspace
 from .ifeast import bicgstab_block, feast_csr, ifeastinit
 from . import adjoint
@@ -33,6 +35,9 @@ __all__ = [
     "half_contour",
     "rational_filter",
     "gauss_legendre_rule",
+    "zolotarev_contour",
+    "zolotarev_filter",
+    "zolotarev_sign",
     "splitmix64_uniform",
     "initial_subspace",
     "feastinit",

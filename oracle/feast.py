@@ -65,6 +65,7 @@ import scipy.linalg as sla
 
 from .contour import GAUSS_ALLOWED, half_contour, rational_filter
 from .splitmix import initial_subspace
+from .zolotarev import zolotarev_contour
 
 RANK_TOL = 1.0e-13
 SPURIOUS_RES = 1.0e-1
@@ -98,6 +99,7 @@ def feastinit():
     fpm[44] = 1    # fpm(45) BiCGStab accuracy 1e-1
     fpm[45] = 40   # fpm(46) BiCGStab max iterations
     fpm[50] = 0    # fpm(51) seed of the random starting block (project slot)
+    fpm[53] = 90   # fpm(54) Zolotarev flat band, percent of the half-width (project slot)
     return fpm
 
 
@@ -111,14 +113,16 @@ def validate(n, m0, emin, emax, fpm, have_expert_contour=False):
         return 200
     f = lambda i: int(fpm[i - 1])  # noqa: E731  (1-based access as in the guide)
     if not have_expert_contour:
-        if f(16) not in (0, 1):
+        if f(16) not in (0, 1, 2):
             return 116
-        if f(16) == 0 and f(2) not in GAUSS_ALLOWED:
+        if f(16) in (0, 2) and f(2) not in GAUSS_ALLOWED:
             return 102
         if f(16) == 1 and f(2) < 1:
             return 102
         if f(18) <= 0:
             return 118
+        if f(16) == 2 and not (1 <= f(54) <= 99):
+            return 154
     elif f(2) < 1:
         return 102
     if not (0 <= f(3) <= 16):
@@ -229,10 +233,13 @@ class _Factored:
         return sla.lu_solve(self.lu, rhs, trans=2)
 
 
-def _contour_classic(facts, z, w, BY, real_problem):
-    """Q = sum_j [w_j (z_j B - A)^-1 BY + conj(w_j) (z_j B - A)^-H BY] in node order."""
+def _contour_classic(facts, z, w, BY, real_problem, Y=None, c_inf=0.0):
+    """Q = c_inf Y + sum_j [w_j (z_j B - A)^-1 BY + conj(w_j) (z_j B - A)^-H BY] in node
+    order (c_inf: the constant term of the Zolotarev filter, else 0)."""
     n, m = BY.shape
     Q = np.zeros((n, m), dtype=np.float64 if real_problem else np.complex128)
+    if c_inf != 0.0:
+        Q += c_inf * Y
     for j in range(len(z)):
         Qj = facts[j].solve(BY.astype(np.complex128))
         if real_problem:
@@ -244,9 +251,10 @@ def _contour_classic(facts, z, w, BY, real_problem):
     return Q
 
 
-def _contour_residual(facts, z, w, X, lam, R, real_problem):
-    """Residual form of the same contour sum (identity in the module docstring)."""
-    rho = rational_filter(lam, z, w)
+def _contour_residual(facts, z, w, X, lam, R, real_problem, c_inf=0.0):
+    """Residual form of the same contour sum (identity in the module docstring); the
+    constant term c_inf acts on X exactly, so it only enters rho."""
+    rho = rational_filter(lam, z, w) + c_inf
     Q = X * rho[None, :]
     Q = Q.astype(np.float64 if real_problem else np.complex128)
     for j in range(len(z)):
@@ -283,14 +291,14 @@ def feast_dense(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None,
     A = expand_uplo(A, uplo).astype(dt)
     if B is not None:
         B = expand_uplo(np.asarray(B), uplo).astype(dt)
-    z, w = _nodes(emin, emax, fpm, zne, wne)
+    z, w, c_inf = _nodes(emin, emax, fpm, zne, wne)
     try:
         b_solve = _dense_b_solver(B)
     except np.linalg.LinAlgError:
         return _empty(-3, m0)  # Table tab_info -3: B may not be positive definite
     facts = [_Factored(zj, A, B) for zj in z]
     return iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, facts, form,
-                   b_solve=b_solve)
+                   b_solve=b_solve, c_inf=c_inf)
 
 
 def _empty(info, m0):
@@ -299,20 +307,26 @@ def _empty(info, m0):
 
 
 def _nodes(emin, emax, fpm, zne, wne):
+    """(z, w, c_inf): the rule of fpm(16) (Zolotarev with its constant term), or the
+    caller's expert nodes and weights (no constant term)."""
     f = lambda i: int(fpm[i - 1])  # noqa: E731
     if zne is None:
-        return half_contour(emin, emax, f(2), rule=f(16), ratio_pct=f(18))
-    return np.asarray(zne, np.complex128), np.asarray(wne, np.complex128)
+        if f(16) == 2:
+            return zolotarev_contour(emin, emax, f(2), f(54))
+        z, w = half_contour(emin, emax, f(2), rule=f(16), ratio_pct=f(18))
+        return z, w, 0.0
+    return np.asarray(zne, np.complex128), np.asarray(wne, np.complex128), 0.0
 
 
 def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form="residual",
-            b_solve=None):
+            b_solve=None, c_inf=0.0):
     """The subspace iteration shared by the dense and the sparse drivers.
 
     A, B: objects supporting ``@`` with an n x m block (B None means identity).
     solvers[j]: object with solve(rhs) for (z_j B - A)^-1 rhs and, for complex
     Hermitian problems, solve_h(rhs) for (z_j B - A)^-H rhs.
     b_solve: B^-1 applied to a block (needed when B is given; R-spur).
+    c_inf: constant term of the filter (Zolotarev rule), applied to the block itself.
     """
     if B is not None and b_solve is None:
         raise ValueError("a B^-1 solver is needed for the found-pair test when B is given")
@@ -334,11 +348,11 @@ def iterate(A, B, n, real_problem, emin, emax, m0, fpm, X0, z, w, solvers, form=
     while True:
         if k == 0 or form == "classic":
             BY = X if B is None else B @ X
-            Q = _contour_classic(facts, z, w, BY, real_problem)
+            Q = _contour_classic(facts, z, w, BY, real_problem, Y=X, c_inf=c_inf)
         else:
             BX = X if B is None else B @ X
             R = A @ X - BX * lam_sorted[None, :]
-            Q = _contour_residual(facts, z, w, X, lam_sorted, R, real_problem)
+            Q = _contour_residual(facts, z, w, X, lam_sorted, R, real_problem, c_inf=c_inf)
         if f(14) == 1:
             out.update(info=4, X=Q, loop=0, m0=Q.shape[1])
             return out

@@ -116,7 +116,7 @@ def feast_csr(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None, form=
     if info:
         return _empty(info, m0)
     Bm = None if B is None else sp.csr_matrix(B, dtype=np.float64)
-    z, w = _nodes(emin, emax, fpm, zne, wne)
+    z, w, c_inf = _nodes(emin, emax, fpm, zne, wne)
     counter = [0]
     tol = 10.0 ** (-f(45))
     solvers = [_ShiftedBiCG(zj, A, Bm, tol, f(46), counter) for zj in z]
@@ -127,6 +127,6 @@ def feast_csr(A, B, emin, emax, m0, fpm=None, X0=None, zne=None, wne=None, form=
         except RuntimeError:
             return _empty(-3, m0)  # B singular (Table tab_info -3)
         b_solve = lambda rhs: lu.solve(np.asarray(rhs, dtype=np.float64))  # noqa: E731
-    out = iterate(A, Bm, n, True, emin, emax, m0, fpm, X0, z, w, solvers, form, b_solve=b_solve)
+    out = iterate(A, Bm, n, True, emin, emax, m0, fpm, X0, z, w, solvers, form, b_solve=b_solve, c_inf=c_inf)
     out["fpm60"] = counter[0]
     return out

@@ -25,6 +25,7 @@ import numpy as np
 from .contour import half_contour
 from .feast import _Factored, _contour_classic, feastinit
 from .splitmix import rademacher_block
+from .zolotarev import zolotarev_contour
 
 
 def stochasticinit():
@@ -39,21 +40,26 @@ def stochasticinit():
     return fpm
 
 
-def filtered_trace(A, B, Y, z, w):
+def filtered_trace(A, B, Y, z, w, c_inf=0.0):
     """Re(trace(Y^H Q)) with Q the first contour of FEAST applied to the block Y
-    (nodes z, half-contour weights w; B None for B = I)."""
+    (nodes z, half-contour weights w, constant term c_inf; B None for B = I)."""
     real_problem = np.isrealobj(A) and (B is None or np.isrealobj(B))
     facts = [_Factored(zj, A, B) for zj in z]
     BY = Y if B is None else B @ Y
-    Q = _contour_classic(facts, z, w, BY, real_problem)
+    Q = _contour_classic(facts, z, w, BY, real_problem, Y=Y, c_inf=c_inf)
     return float(np.real(np.sum(np.conj(Y) * Q)))
 
 
-def stochastic_count(A, B, emin, emax, m0, ne=3, rule=0, ratio_pct=30, seed=0):
+def stochastic_count(A, B, emin, emax, m0, ne=3, rule=0, ratio_pct=30, seed=0, band_pct=90):
     """(estimate, M) for the pencil (A, B) on [emin, emax] with m0 Rademacher probes
-    drawn with the given seed (fpm(51)) and ne half-contour nodes."""
+    drawn with the given seed (fpm(51)) and ne half-contour nodes (rule 2: Zolotarev
+    with flat band band_pct, fpm(54))."""
     n = A.shape[0]
-    z, w = half_contour(emin, emax, ne, rule, ratio_pct)
+    if rule == 2:
+        z, w, c_inf = zolotarev_contour(emin, emax, ne, band_pct)
+    else:
+        z, w = half_contour(emin, emax, ne, rule, ratio_pct)
+        c_inf = 0.0
     Y = rademacher_block(n, m0, seed)
-    est = filtered_trace(A, B, Y, z, w) / m0
+    est = filtered_trace(A, B, Y, z, w, c_inf) / m0
     return est, max(0, int(np.floor(est + 0.5)))

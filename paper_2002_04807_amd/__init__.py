@@ -23,7 +23,7 @@ _lib_error = None
 
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
-    "mfeast_init_stochastic", "mfeast_contour", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
+    "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
     "mfeast_dsygv_batched", "mfeast_get_timing", "mfeast_get_profile",
 )
 
@@ -53,6 +53,9 @@ def _load():
     lib.mfeast_contour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, c_dp, c_dp]
     lib.mfeast_contour.restype = c_int
+    lib.mfeast_zolotarev.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, c_dp, c_dp,
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.mfeast_zolotarev.restype = c_int
     dense = [c_vp, ctypes.c_char, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.c_double, ctypes.c_double,
              c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
     for name in ("mfeast_dsygv", "mfeast_zhegv"):
@@ -131,6 +134,16 @@ def mfeast_contour(emin, emax, ne, rule=0, ratio_pct=30):
     info = _load().mfeast_contour(float(emin), float(emax), int(ne), int(rule), int(ratio_pct),
                                   zb.ctypes.data, wb.ctypes.data)
     return info, zb.view(np.complex128)[:ne].copy(), wb.view(np.complex128)[:ne].copy()
+
+
+def mfeast_zolotarev(emin, emax, ne, band_pct=90):
+    """(info, z, w, c_inf): Zolotarev nodes, half-contour weights and constant term."""
+    zb = np.zeros(2 * max(int(ne), 1), dtype=np.float64)
+    wb = np.zeros_like(zb)
+    c = ctypes.c_double(0.0)
+    info = _load().mfeast_zolotarev(float(emin), float(emax), int(ne), int(band_pct), zb.ctypes.data,
+                                    wb.ctypes.data, ctypes.byref(c))
+    return info, zb.view(np.complex128)[:ne].copy(), wb.view(np.complex128)[:ne].copy(), c.value
 
 
 class Handle:

@@ -110,14 +110,113 @@ static void make_contour(double emin, double emax, int ne, int rule, int ratio_p
 }
 
 // ---------------------------------------------------------------------------
+// Zolotarev rule (fpm(16) = 2; the guide cites Guettel, Polizzi, Tang and Viaud 2015 and
+// prints no construction).  Zolotarev's best approximation of sign(x) on [-1,-l] u [l,1]
+// of odd type (2m-1, 2m),
+//   Z(x) = C x prod_{q<m} (x^2 + c_{2q}) / prod_{q<=m} (x^2 + c_{2q-1}),
+//   c_i = l^2 sn^2(i K'/(2m); l') / cn^2(i K'/(2m); l'),   l' = sqrt(1 - l^2),
+// equioscillates on [l, 1] at x_k = l / dn(k K'/(2m); l'); the filter of the interval
+// is f(t) = (1 + Z(kappa (1 + t)/(1 - t)))/2 in t = (lambda - c)/r, with kappa =
+// (1 - a)/(1 + a), l = kappa^2 and a = fpm(54)/100 the half-width (relative) inside
+// which f stays within delta/2 of 1 (and beyond 1/a within delta/2 of 0).  Its m poles
+// in the upper half plane lie on the unit circle; partial fractions give the nodes, the
+// half-contour weights and the constant term f(inf) = (1 + Z(-kappa))/2.
+
+// Jacobi elliptic functions of modulus k = sqrt(1 - kp^2), given by its complementary
+// modulus kp (0 < kp <= 1, exact for moduli near 1), by the arithmetic-geometric mean
+// (descending Landen) method; also K(k) = pi / (2 a_N).
+static void jacobi_agm(double u, double kp, double& sn, double& cn, double& dn, double* Kout) {
+  double a[64], c[64];
+  a[0] = 1.0;
+  double b = kp;
+  c[0] = std::sqrt((1.0 - kp) * (1.0 + kp));
+  int N = 0;
+  while (N < 62 && std::fabs(c[N]) > 1e-17 * a[N]) {
+    a[N + 1] = 0.5 * (a[N] + b);
+    c[N + 1] = 0.5 * (a[N] - b);
+    b = std::sqrt(a[N] * b);
+    ++N;
+  }
+  if (Kout) *Kout = M_PI / (2.0 * a[N]);
+  double phi = std::ldexp(a[N] * u, N), phi1 = phi;
+  for (int n = N; n >= 1; --n) {
+    phi1 = phi;
+    phi = 0.5 * (phi + std::asin(c[n] * std::sin(phi) / a[n]));
+  }
+  sn = std::sin(phi);
+  cn = std::cos(phi);
+  dn = (N >= 1) ? cn / std::cos(phi1 - phi) : 1.0;
+}
+
+// x prod_{q<m} (x^2 + c_{2q}) / prod_{q<=m} (x^2 + c_{2q-1}) as a product of ratios
+// (cs[i] = c_{i+1})
+static std::complex<double> zolo_product(std::complex<double> x, const std::vector<double>& cs, int m) {
+  std::complex<double> out = x / (x * x + cs[2 * m - 2]);
+  for (int q = 1; q < m; ++q) out *= (x * x + cs[2 * q - 1]) / (x * x + cs[2 * q - 2]);
+  return out;
+}
+
+static void zolotarev_contour(double emin, double emax, int m, int band_pct, std::vector<c64>& z,
+                              std::vector<c64>& w, double& c_inf) {
+  const double a = band_pct / 100.0;
+  const double kappa = (1.0 - a) / (1.0 + a);
+  const double l = kappa * kappa;  // the modulus of the functions is l', its complement l
+  double sn, cn, dn, Kp;
+  jacobi_agm(0.0, l, sn, cn, dn, &Kp);
+  // c_i for i <= m from the functions; c_{2m-i} = l^2 / c_i (quarter-period reflection),
+  // which keeps the large coefficients accurate
+  std::vector<double> cs(2 * m - 1);
+  for (int i = 1; i <= m && i <= 2 * m - 1; ++i) {
+    jacobi_agm(i * Kp / (2.0 * m), l, sn, cn, dn, nullptr);
+    cs[i - 1] = l * l * sn * sn / (cn * cn);
+  }
+  for (int i = m + 1; i <= 2 * m - 1; ++i) cs[i - 1] = l * l / cs[2 * m - i - 1];
+  // normalization from the first two alternation points x_0 = l, x_1 = l / dn(K'/(2m))
+  jacobi_agm(Kp / (2.0 * m), l, sn, cn, dn, nullptr);
+  const double z0 = zolo_product(l, cs, m).real(), z1 = zolo_product(l / dn, cs, m).real();
+  const double C = 2.0 / (z0 + z1);
+  const double cen = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
+  std::vector<std::pair<double, std::pair<c64, c64>>> nodes;
+  for (int q = 0; q < m; ++q) {
+    const double p = cs[2 * q];  // c_{2q+1}: the squared modulus of this pole pair
+    // residue of Z at i sqrt(p): C N(-p) / (2 D'(-p)), as a product of ratios
+    double ratio = 1.0;
+    int e = 0;
+    for (int o = 0; o < m; ++o) {
+      if (o == q) continue;
+      ratio *= (cs[2 * e + 1] - p) / (cs[2 * o] - p);
+      ++e;
+    }
+    const double res_x = C * ratio / 2.0;
+    const double y = std::sqrt(p) / kappa;
+    const std::complex<double> tq((y * y - 1.0) / (y * y + 1.0), 2.0 * y / (y * y + 1.0));
+    const std::complex<double> res_t = 0.5 * res_x * (1.0 - tq) * (1.0 - tq) / (2.0 * kappa);
+    const std::complex<double> zq = cen + r * tq, wq = -r * res_t;
+    nodes.push_back({tq.real(), {c64(zq.real(), zq.imag()), c64(wq.real(), wq.imag())}});
+  }
+  std::stable_sort(nodes.begin(), nodes.end(),
+                   [](const std::pair<double, std::pair<c64, c64>>& A, const std::pair<double, std::pair<c64, c64>>& B) {
+                     return A.first < B.first;
+                   });
+  z.resize(m);
+  w.resize(m);
+  for (int q = 0; q < m; ++q) {
+    z[q] = nodes[q].second.first;
+    w[q] = nodes[q].second.second;
+  }
+  c_inf = 0.5 * (1.0 + C * zolo_product(-kappa, cs, m).real());
+}
+
+// ---------------------------------------------------------------------------
 // argument checks shared by the dense drivers (Table tab_info order)
 static int check_fpm(const int32_t* fpm, bool expert) {
   auto f = [&](int i) { return fpm[i - 1]; };
   if (!expert) {
-    if (f(16) != 0 && f(16) != 1) return 116;
-    if (f(16) == 0 && !gauss_allowed(f(2))) return 102;
+    if (f(16) < 0 || f(16) > 2) return 116;
+    if ((f(16) == 0 || f(16) == 2) && !gauss_allowed(f(2))) return 102;
     if (f(16) == 1 && f(2) < 1) return 102;
     if (f(18) <= 0) return 118;
+    if (f(16) == 2 && (f(54) < 1 || f(54) > 99)) return 154;
   } else if (f(2) < 1) {
     return 102;
   }
@@ -541,7 +640,8 @@ struct CsrOp : Operator<double> {
 template <typename T>
 static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, double emin, double emax,
                       int32_t* m0p, double* E, T* Xu, int64_t ldx, int32_t* Mout, double* res_out,
-                      double* epsout, int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w) {
+                      double* epsout, int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w,
+                      double c_inf) {
   constexpr bool CPLX = is_cplx<T>::value;
   Timer total_t, ph;
   total_t.start();
@@ -692,8 +792,10 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
         }
       }
     }
+    // the filter at the Ritz values (residual form); its constant term (Zolotarev rule)
+    // acts on the block itself, also in the first contour (classic form: Q = c_inf Y + ...)
     for (int c = 0; c < m0; ++c) {
-      double rho = 0.0;
+      double rho = c_inf;
       if (resid) {
         for (int j = 0; j < ne; ++j) {
           const std::complex<double> zj(z[j].re, z[j].im), wj(w[j].re, w[j].im);
@@ -710,7 +812,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     MF_HIP_CHECK(hipMemcpyAsync(d_cc, h_cc, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
     {
       const Coef kc{d_cs, d_us, d_rho, d_cf, d_cc};
-      MF_TRY(op.contour(s, m0, rhs, kc, Xw, Q, resid));
+      MF_TRY(op.contour(s, m0, rhs, kc, Xw, Q, resid || c_inf != 0.0));
     }
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_solve += ph.stop();
@@ -1026,10 +1128,12 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
 }
 
 // ---------------------------------------------------------------------------
-// nodes from fpm(2), fpm(16), fpm(18), or the caller's expert contour
+// nodes from fpm(2), fpm(16), fpm(18) (fpm(54) for the Zolotarev rule, whose constant
+// term is returned in c_inf), or the caller's expert contour (no constant term)
 static void nodes_for(const int32_t* fpm, double emin, double emax, const double* zne, const double* wne,
-                      std::vector<c64>& z, std::vector<c64>& w) {
+                      std::vector<c64>& z, std::vector<c64>& w, double& c_inf) {
   const int ne = fpm[1];
+  c_inf = 0.0;
   if (zne != nullptr) {
     z.resize(ne);
     w.resize(ne);
@@ -1037,6 +1141,8 @@ static void nodes_for(const int32_t* fpm, double emin, double emax, const double
       z[j] = c64(zne[2 * j], zne[2 * j + 1]);
       w[j] = c64(wne[2 * j], wne[2 * j + 1]);
     }
+  } else if (fpm[15] == 2) {
+    zolotarev_contour(emin, emax, ne, fpm[53], z, w, c_inf);
   } else {
     make_contour(emin, emax, ne, fpm[15], fpm[17], z, w);
   }
@@ -1046,10 +1152,10 @@ static void nodes_for(const int32_t* fpm, double emin, double emax, const double
 template <typename T>
 static int run_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, double emin, double emax,
                     int32_t* m0, double* E, T* X, int64_t ldx, int32_t* M, double* res, double* epsout,
-                    int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w) {
+                    int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w, double c_inf) {
   prof_enable(fpm[51] == 1);
   for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
-  const int info = feast_loop<T>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+  const int info = feast_loop<T>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w, c_inf);
   if (prof_on()) {
     (void)hipStreamSynchronize(h->stream);
     prof_collect(h->prof);
@@ -1090,15 +1196,16 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   const T* Bt = reinterpret_cast<const T*>(B);
   T* Xt = reinterpret_cast<T*>(X);
   std::vector<c64> z, w;
-  nodes_for(fpm, emin, emax, zne, wne, z, w);
+  double c_inf = 0.0;
+  nodes_for(fpm, emin, emax, zne, wne, z, w, c_inf);
   set_gemm_3m(fpm[52] == 0);
   if (fpm[41] == 1) {
     DenseOp<T, c32> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
     op.ir_steps = fpm[49];
-    return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w);
+    return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w, c_inf);
   }
   DenseOp<T, c64> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
-  return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w);
+  return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w, c_inf);
 }
 
 static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, const int32_t* ia, const int32_t* ja,
@@ -1134,7 +1241,8 @@ static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, con
   if (hipSetDevice(h->device) != hipSuccess) return -900;
   GemmScratchScope scratch_scope(h);
   std::vector<c64> z, w;
-  nodes_for(fpm, emin, emax, zne, wne, z, w);
+  double c_inf = 0.0;
+  nodes_for(fpm, emin, emax, zne, wne, z, w, c_inf);
   set_gemm_3m(fpm[52] == 0);
   const double tol = std::pow(10.0, -fpm[44]);
   fpm[59] = 0;
@@ -1142,11 +1250,11 @@ static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, con
   int64_t its;
   if (fpm[41] == 1) {
     CsrOp<c32> op(h, uplo, n, a, ia, ja, base, b, ib, jb, z, *m0, fpm[45], tol);
-    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w, c_inf);
     its = op.iterations;
   } else {
     CsrOp<c64> op(h, uplo, n, a, ia, ja, base, b, ib, jb, z, *m0, fpm[45], tol);
-    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w);
+    info = run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w, c_inf);
     its = op.iterations;
   }
   fpm[59] = (int32_t)std::min<int64_t>(its, INT32_MAX);
@@ -1219,17 +1327,43 @@ void mfeast_init(int32_t* fpm) {
   fpm[50] = 0;   // fpm(51) seed of the random starting block
   fpm[51] = 0;   // fpm(52) per-class kernel timing (mfeast_get_profile) off
   fpm[52] = 0;   // fpm(53) complex FP32 products: 0 three-product scheme, 1 four-product
+  fpm[53] = 90;  // fpm(54) Zolotarev rule: flat band, percent of the half-width
 }
 
 int mfeast_contour(double emin, double emax, int32_t ne, int32_t rule, int32_t ratio_pct, double* zne, double* wne) {
   if (!(emin < emax)) return 200;
-  if (rule != 0 && rule != 1) return 116;
-  if ((rule == 0 && !gauss_allowed(ne)) || ne < 1) return 102;
+  if (rule < 0 || rule > 2) return 116;
+  if (((rule == 0 || rule == 2) && !gauss_allowed(ne)) || ne < 1) return 102;
   if (ratio_pct <= 0) return 118;
+  if (rule == 2 && ratio_pct > 99) return 154;
   if (zne == nullptr) return -106;
   if (wne == nullptr) return -107;
   std::vector<c64> z, w;
-  make_contour(emin, emax, ne, rule, ratio_pct, z, w);
+  if (rule == 2) {
+    double c_inf = 0.0;
+    zolotarev_contour(emin, emax, ne, ratio_pct, z, w, c_inf);
+  } else {
+    make_contour(emin, emax, ne, rule, ratio_pct, z, w);
+  }
+  for (int j = 0; j < ne; ++j) {
+    zne[2 * j] = z[j].re;
+    zne[2 * j + 1] = z[j].im;
+    wne[2 * j] = w[j].re;
+    wne[2 * j + 1] = w[j].im;
+  }
+  return 0;
+}
+
+int mfeast_zolotarev(double emin, double emax, int32_t ne, int32_t band_pct, double* zne, double* wne,
+                     double* c_inf) {
+  if (!(emin < emax)) return 200;
+  if (!gauss_allowed(ne)) return 102;
+  if (band_pct < 1 || band_pct > 99) return 154;
+  if (zne == nullptr) return -105;
+  if (wne == nullptr) return -106;
+  if (c_inf == nullptr) return -107;
+  std::vector<c64> z, w;
+  zolotarev_contour(emin, emax, ne, band_pct, z, w, *c_inf);
   for (int j = 0; j < ne; ++j) {
     zne[2 * j] = z[j].re;
     zne[2 * j + 1] = z[j].im;

@@ -51,8 +51,34 @@ def test_contour_errors():
     assert mf.mfeast_contour(1.0, 1.0, 8)[0] == 200
     assert mf.mfeast_contour(0.0, 1.0, 21, 0)[0] == 102
     assert mf.mfeast_contour(0.0, 1.0, 21, 1)[0] == 0
-    assert mf.mfeast_contour(0.0, 1.0, 8, 2)[0] == 116
+    assert mf.mfeast_contour(0.0, 1.0, 8, 3)[0] == 116
+    assert mf.mfeast_contour(0.0, 1.0, 21, 2, 90)[0] == 102
+    assert mf.mfeast_contour(0.0, 1.0, 8, 2, 100)[0] == 154
     assert mf.mfeast_contour(0.0, 1.0, 8, 0, 0)[0] == 118
+    assert mf.mfeast_zolotarev(0.0, 1.0, 8, 0)[0] == 154
+    assert mf.mfeast_zolotarev(0.0, 1.0, 9, 90)[0] == 0
+    assert mf.mfeast_zolotarev(0.0, 1.0, 21, 90)[0] == 102
+
+
+@pytest.mark.parametrize("ne,band", [(1, 90), (2, 50), (4, 90), (8, 90), (8, 75), (16, 95), (56, 90)])
+def test_zolotarev_matches_oracle(ne, band):
+    """The library's Zolotarev rule (its own elliptic functions by the arithmetic-geometric
+    mean) against the oracle's (SciPy's elliptic functions): nodes, weights, constant."""
+    info, z, w, ci = mf.mfeast_zolotarev(-0.7, 2.2, ne, band)
+    assert info == 0
+    zo, wo, co = oracle.zolotarev_contour(-0.7, 2.2, ne, band)
+    # The oracle hands SciPy the parameter m = 1 - l^2 of the Jacobi functions, rounded
+    # in FP64: a relative error of about 1e-16 / l^2 in the complementary parameter l^2
+    # (l = 0.0028 for a 90% band, 1.7e-4 for 95%), which moves the coefficients by up to
+    # about 1e-10; the library starts from the complementary modulus l itself.
+    tol = 1e-10
+    np.testing.assert_allclose(z, zo, rtol=0, atol=tol)
+    np.testing.assert_allclose(w, wo, rtol=0, atol=tol)
+    assert abs(ci - co) <= tol
+    info, z2, w2 = mf.mfeast_contour(-0.7, 2.2, ne, 2, band)
+    assert info == 0
+    np.testing.assert_array_equal(z2, z)
+    np.testing.assert_array_equal(w2, w)
 
 
 def _call(name, n=10, m0=4, emin=0.0, emax=1.0, fpm=None, handle=None, **kw):
@@ -75,7 +101,7 @@ def test_argument_checks_in_table_order(name):
     assert _call(name, m0=11) == 201
     assert _call(name, emin=1.0, emax=1.0) == 200
     for idx, val, code in [(1, 21, 102), (2, 17, 103), (3, -1, 104), (4, 2, 105), (5, 2, 106),
-                           (13, 3, 114), (15, 2, 116), (17, 0, 118), (41, 2, 142), (49, 9, 150),
+                           (13, 3, 114), (15, 3, 116), (17, 0, 118), (41, 2, 142), (49, 9, 150),
                            (49, -1, 150), (52, 2, 153)]:
         f = oracle.feastinit().astype(np.int32)
         f[idx] = val

@@ -340,7 +340,7 @@ def test_argument_errors():
     assert oracle.feast_dense(A, None, 0, 1, 0, fpm)["info"] == 201
     assert oracle.feast_dense(A, None, 1, 1, 4, fpm)["info"] == 200
     for idx, val, code in [(1, 21, 102), (2, 17, 103), (3, -1, 104), (4, 2, 105),
-                           (5, 2, 106), (13, 3, 114), (15, 2, 116), (17, 0, 118), (41, 2, 142)]:
+                           (5, 2, 106), (13, 3, 114), (15, 3, 116), (17, 0, 118), (41, 2, 142)]:
         f = fpm.copy()
         f[idx] = val
         assert oracle.feast_dense(A, None, 0, 1, 4, f)["info"] == code, (idx, val)
