@@ -129,6 +129,26 @@ int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
                  double* epsout, int32_t* loop, const double* zne, const double* wne);
 
+/* Allocation-free variant of mfeast_dsygv, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, semantics and results as mfeast_dsygv; every workspace
+ * buffer of the call (stored LU factors, solve blocks, Rayleigh-Ritz blocks, reduction
+ * partials, split-K partials) is carved from one static device array of 64 MiB per GPU
+ * (held by each GPU the library runs on until the process ends), host staging uses
+ * ordinary host memory, and the call makes no hipMalloc, hipHostMalloc, hipFree,
+ * stream or event creation.  The handle supplies the device and stream only; its own
+ * workspace is neither used nor grown.  fpm(52) is ignored (no per-class timing).
+ * The array is shared by every call on a GPU and keeps the last call's contents (the
+ * call clears what it needs): calls that overlap on one GPU, from any thread or handle,
+ * race and must be serialized by the caller.
+ * Returns the codes of mfeast_dsygv, and -901 when the call's workspace does not fit the
+ * array (detected before any kernel runs; about n <= 256 with m0 <= 96 fit in FP64
+ * with B, larger n with FP32 solves, B = NULL or a smaller m0). */
+int mfeast_dsygv_noalloc(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, int32_t* fpm, double emin, double emax,
+                         int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
+                         double* epsout, int32_t* loop, const double* zne, const double* wne);
+
 /* Dense complex Hermitian problem (zfeast_hegv / zfeast_heev).  Same arguments as
  * mfeast_dsygv with A, B, X complex (interleaved doubles).  The conjugate contour node
  * is handled by a solve with (z B - A)^H that reuses the factorization of z B - A

@@ -23,8 +23,9 @@ _lib_error = None
 
 EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
-    "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint",
-    "mfeast_dsygv_batched", "mfeast_get_timing", "mfeast_get_profile",
+    "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_dsygv_noalloc",
+    "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint", "mfeast_dsygv_batched", "mfeast_get_timing",
+    "mfeast_get_profile",
 )
 
 
@@ -58,7 +59,7 @@ def _load():
     lib.mfeast_zolotarev.restype = c_int
     dense = [c_vp, ctypes.c_char, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.c_double, ctypes.c_double,
              c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
-    for name in ("mfeast_dsygv", "mfeast_zhegv"):
+    for name in ("mfeast_dsygv", "mfeast_zhegv", "mfeast_dsygv_noalloc"):
         fn = getattr(lib, name)
         fn.argtypes = dense
         fn.restype = c_int
@@ -221,6 +222,13 @@ def _dense_call(name, h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx
 def mfeast_dsygv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
     """C mfeast_dsygv; A, B, E, X, res are device tensors (column-major A, B, X)."""
     return _dense_call("mfeast_dsygv", h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne, wne)
+
+
+def mfeast_dsygv_noalloc(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):
+    """C mfeast_dsygv_noalloc: mfeast_dsygv with its workspace in the library's static
+    device array (no device allocation); -901 when the problem does not fit it."""
+    return _dense_call("mfeast_dsygv_noalloc", h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res,
+                       zne, wne)
 
 
 def mfeast_zhegv(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, res, zne=None, wne=None):

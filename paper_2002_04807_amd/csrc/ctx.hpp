@@ -78,9 +78,29 @@ struct mfeast_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double timing[8] = {};
   double prof[mf::K_NCLASS * 4] = {};
+  // Allocation-free mode (mfeast_dsygv_noalloc): every workspace slot is carved from a
+  // caller-supplied device region (a static device array), host staging uses ordinary
+  // host memory, and nothing is ever freed.  A request that does not fit sets
+  // arena_overflow and returns nullptr.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
+  bool arena_overflow = false;
+  std::vector<char> arena_host[3];
 
   void* ws(mf::Slot s, size_t bytes) {
     if (bytes == 0) bytes = 16;
+    if (arena != nullptr) {
+      if (cap[s] >= bytes) return buf[s];
+      const size_t off = (arena_off + 255) / 256 * 256;
+      if (off > arena_cap || bytes > arena_cap - off) {
+        arena_overflow = true;
+        return nullptr;
+      }
+      buf[s] = arena + off;
+      cap[s] = bytes;
+      arena_off = off + bytes;
+      return buf[s];
+    }
     if (cap[s] < bytes) {
       if (buf[s]) (void)hipFree(buf[s]);
       buf[s] = nullptr;
@@ -91,6 +111,7 @@ struct mfeast_ctx {
     return buf[s];
   }
   bool ensure_aux() {
+    if (arena != nullptr) return false;  // no stream creation in the allocation-free mode
     if (aux != nullptr) return true;
     if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
       aux = nullptr;
@@ -111,6 +132,10 @@ struct mfeast_ctx {
     aux = nullptr;
   }
   char* host(size_t bytes) {
+    if (arena != nullptr) {
+      if (arena_host[0].size() < bytes) arena_host[0].resize(bytes);
+      return arena_host[0].data();
+    }
     if (pinned_cap < bytes) {
       if (pinned) (void)hipHostFree(pinned);
       pinned = nullptr;
@@ -121,6 +146,10 @@ struct mfeast_ctx {
     return pinned;
   }
   char* host_aux(size_t bytes) {
+    if (arena != nullptr) {
+      if (arena_host[1].size() < bytes) arena_host[1].resize(bytes);
+      return arena_host[1].data();
+    }
     if (pinned_aux_cap < bytes) {
       if (pinned_aux) (void)hipHostFree(pinned_aux);
       pinned_aux = nullptr;
@@ -132,6 +161,10 @@ struct mfeast_ctx {
   }
   int* host_ints(size_t count) {
     const size_t bytes = count * sizeof(int) + 64;
+    if (arena != nullptr) {
+      if (arena_host[2].size() < bytes) arena_host[2].resize(bytes);
+      return reinterpret_cast<int*>(arena_host[2].data());
+    }
     if (pinned_i_cap < bytes) {
       if (pinned_i) (void)hipHostFree(pinned_i);
       pinned_i = nullptr;
@@ -147,6 +180,14 @@ struct mfeast_ctx {
 // launches may still read the old buffer)
 inline void* ctx_splitk_scratch(void* owner, size_t bytes) {
   mfeast_ctx* c = static_cast<mfeast_ctx*>(owner);
+  if (c->arena != nullptr) {
+    // allocation-free mode: carve it if it fits (a miss runs the product unsplit and is
+    // not an error)
+    const bool before = c->arena_overflow;
+    void* p = c->ws(mf::S_SPLITK, bytes);
+    if (p == nullptr) c->arena_overflow = before;
+    return p;
+  }
   if (c->cap[mf::S_SPLITK] < bytes && c->buf[mf::S_SPLITK] != nullptr) (void)hipDeviceSynchronize();
   return c->ws(mf::S_SPLITK, bytes);
 }

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mfeast.h"
@@ -1261,6 +1262,28 @@ static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, con
   return info;
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free entry point's workspace: one static device array per GPU (each
+// device holds its own copy at its own address until the process ends).  Host code
+// never passes the array's name to a kernel: its device address is looked up once per
+// device, with that device current, and kept.
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+// device address of `scratch` on the current device `device` (nullptr on failure)
+static void* noalloc_scratch(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
 extern "C" {
 
 int mfeast_create(mfeast_handle* h, int device, void* hip_stream) {
@@ -1378,6 +1401,35 @@ int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  double* res, double* epsout, int32_t* loop, const double* zne, const double* wne) {
   return dense_entry<double>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, zne,
                              wne);
+}
+
+int mfeast_dsygv_noalloc(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
+                         int64_t ldb, int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X,
+                         int64_t ldx, int32_t* M, double* res, double* epsout, int32_t* loop, const double* zne,
+                         const double* wne) {
+  if (h == nullptr || fpm == nullptr) {
+    // argument errors only: the checks of mfeast_dsygv, in the table's order
+    return dense_entry<double>(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop,
+                               zne, wne);
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  void* arena = noalloc_scratch(h->device);
+  if (arena == nullptr) return -900;
+  // a call-local context: same device and stream, workspace carved from the array, no
+  // per-class timing (its events would be created on first use)
+  int32_t f[64];
+  for (int i = 0; i < 64; ++i) f[i] = fpm[i];
+  f[51] = 0;
+  mfeast_ctx tmp;
+  tmp.device = h->device;
+  tmp.stream = h->stream;
+  tmp.arena = static_cast<char*>(arena);
+  tmp.arena_cap = NOALLOC_BYTES;
+  int info = dense_entry<double>(&tmp, uplo, n, A, lda, B, ldb, f, emin, emax, m0, E, X, ldx, M, res, epsout, loop,
+                                 zne, wne);
+  if (tmp.arena_overflow) info = -901;
+  for (int i = 0; i < 8; ++i) h->timing[i] = tmp.timing[i];
+  return info;
 }
 
 int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
