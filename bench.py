@@ -38,6 +38,14 @@ TRAFFIC = {
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
 RES_BAR = 1e-10
+# the classes of the contour step: shift-form and quadrature sums (other), LU, block solves
+CONTOUR_CLASSES = ("lu_trailing_gemm", "lu_panel", "lu_rows", "contour_solve", "other")
+# Issued MFMA work of the block solves per unit of algorithmic work: each 256-row panel
+# step multiplies by the panel's full 256 x 256 inverse (16 panels at n = 4096: 136 x 256^2
+# complex multiply-adds per right-hand side and triangle against n^2 / 2 = 128 x 256^2),
+# and a complex multiply-add is three real products (6 flops) in the three-product
+# scheme against the 8 flops counted
+SOLVE_ISSUED_PER_ALG = (136.0 / 128.0) * (6.0 / 8.0)
 
 
 def parse():
@@ -101,7 +109,14 @@ KERNELS = {
     # class -> (kernel, bound, peak key or None, what one launch processes)
     "bicgstab_vector": ("k_bi_sweep_c (+ column sums)", "hbm", "hbm", "one BiCGSTAB update sweep over the active tiles"),
     "bicgstab_spmv": ("k_bi_sweep_a / k_bi_sweep_b", "hbm", "hbm", "one shifted sparse product sweep"),
-    "lu_panel": ("k_leaf + k_leaf_update (recursive panel)", "alu", "fp32_vector", "one 64-column panel of all 8 nodes"),
+    "lu_panel": ("k_leaf + k_leaf_update (recursive panel)", "alu", "fp32_vector",
+                 "one 64-column panel of every factored matrix"),
+    "lu_rows": ("k_laswp + k_trsm_u12 (per panel), k_invert_diag, panel inverses", "alu", "fp32_vector",
+                "one panel's row interchanges and U12 substitution, or the inverses after the last panel"),
+    "orth": ("k_chol_diag / Newton-Schulz (B-orthonormalization)", "alu", "fp64_vector",
+             "one B-orthonormalization pass"),
+    "resid": ("residual norms, B^-1 products of the found-pair test", "hbm", "hbm", "one residual evaluation"),
+    "other": ("shift-form, right-hand sides, quadrature sums", "hbm", "hbm", "one small-kernel group"),
     "lu_trailing_gemm": ("k_gemm (LU trailing update)", "mfma", "fp32_mfma", "one trailing update, all nodes"),
     "contour_solve": ("k_gemm (panel-inverse products and updates of the block solves)", "mfma", "fp32_mfma",
                       "one contour's block solves, all 8 nodes: the forward (L, U) and the "
@@ -152,6 +167,26 @@ def roofline_of(prof, rank=0):
             "classes_ms_per_step": {c: round(prof[c]["ms"], 3) for c in prof}}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def classes_summary(prof, ms_per_step):
+    """Per-class device milliseconds of one call, their sum, and what no class covers
+    (host round trips between synchronized phases and launch gaps).  The forward and the
+    conjugate-transpose solves overlap on two streams, so the sum can exceed the span."""
+    total = sum(v["ms"] for v in prof.values())
+    return {"classes_ms": {c: round(v["ms"], 3) for c, v in prof.items() if v["ms"] > 0},
+            "classes_sum_ms": round(total, 3), "call_ms": round(ms_per_step, 3),
+            "unattributed_ms": round(ms_per_step - total, 3)}
+
+
 def cpu_baseline(A, B, lam_in, loops):
     """The oracle's own steps timed on a bounded sample: one node's complex128 LU, one
     forward and one conjugate-transpose solve with M0 right-hand sides, and one
@@ -186,7 +221,7 @@ def cpu_baseline(A, B, lam_in, loops):
     iters = loops + 1
     t_est = t_lu + iters * (t_solve2 + t_rr)
     m = lam_in.size
-    return {"value": m / t_est, "unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle",
+    return {"value": m / t_est, "unit": "eigenpairs/s", "cores": int(cores), "cpu": _cpu_model(), "kind": "oracle",
             "sample": "the first subspace iteration's factorizations and solves: the 8 node LUs "
                       "(complex128, n=4096) with one forward and one conjugate solve of 600 right-hand "
                       "sides each, plus one Rayleigh-Ritz step (A Q, B Q, Grams, eigh 600), %.1f s; "
@@ -265,7 +300,7 @@ def bench_sparse(args, mf, torch, np, gen):
         col_its = float(out["fpm60"]) * m0
         est = ts / float(ncol * nit) * col_its
         result["cpu_baseline"] = {"value": m_conv / est if est > 0 else None, "unit": "eigenpairs/s",
-                                  "cores": _cores(), "kind": "oracle",
+                                  "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
                                   "sample": "oracle BiCGSTAB, %d columns x %d iterations (%.1f s) scaled to "
                                             "fpm(60) x M0 = %.0f column-iterations (outer steps not counted): "
                                             "est. %.0f s per call" % (ncol, nit, ts, col_its, est)}
@@ -298,6 +333,16 @@ def bench_batched(args, mf, torch, np, gen):
         times.append(time.perf_counter() - t0)
         last = (ret, outs)
     ret, outs = last
+    # one more call with per-class device timing (summed over the 128 problems' calls)
+    h.set_profiling(True)
+    mf.feast_batched(As, emins, emaxs, m0s, fpm=fpm, handle=h)
+    torch.cuda.synchronize()
+    prof = h.profile()
+    h.set_profiling(False)
+    roofline = roofline_of(prof)
+    if roofline is not None:
+        roofline["note"] = ("per-launch averages over all 128 problems' launches; the problems run on 8 "
+                            "concurrent streams, so each launch shares the GPU with others")
     m_conv, exact_ok, max_err = 0, 0, 0.0
     for o, p in zip(outs, probs):
         c = p["count"]
@@ -319,7 +364,10 @@ def bench_batched(args, mf, torch, np, gen):
         "accuracy": {"problems_exact": exact_ok, "problems": len(probs), "max_abs_eig_err": max_err,
                      "loops": np.bincount([o["loop"] for o in outs]).tolist(), "ret": ret},
         "lu_tflops": 8.0 * (8.0 / 3.0) * sum_n3 / t / 1e12,
-        "roofline": None,
+        "lu_tflops_kind": "algorithmic LU flops of all problems and nodes over the whole call's wall time",
+        "roofline": roofline,
+        "roofline_next": roofline_of(prof, 1),
+        "classes_ms_summed_over_problems": {c: round(v["ms"], 3) for c, v in prof.items() if v["ms"] > 0},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -333,7 +381,7 @@ def bench_batched(args, mf, torch, np, gen):
             n3 += float(probs[k]["A"].shape[0]) ** 3
         ts = time.perf_counter() - t0
         est = ts * sum_n3 / n3
-        result["cpu_baseline"] = {"value": m_conv / est, "unit": "eigenpairs/s", "cores": _cores(), "kind": "oracle",
+        result["cpu_baseline"] = {"value": m_conv / est, "unit": "eigenpairs/s", "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
                                   "sample": "oracle FEAST on %d of the 128 problems (n = %s, %.1f s), scaled by "
                                             "sum n^3: est. %.0f s for all" % (len(sample), [probs[k]["A"].shape[0]
                                                                                             for k in sample], ts, est)}
@@ -369,6 +417,17 @@ def bench_adjoint(args, mf, torch, np, gen):
         g = step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    # one more step with per-class device timing of the forward call and of the adjoint
+    hp = mf.Handle(0)
+    hp.set_profiling(True)
+    vt = torch.tensor(v, dtype=torch.float64, device=dev, requires_grad=True)
+    E, X = mf.feast_eigh(A0 + torch.diag(vt), emin, emax, 16, precision=1, handle=hp)
+    prof_f = hp.profile()
+    (E.sum() + (ct[:, None] * X * X).sum()).backward()
+    torch.cuda.synchronize()
+    prof_b = hp.profile()
+    hp.close()
+    prof = {c: {k: prof_f[c][k] + prof_b[c][k] for k in prof_f[c]} for c in prof_f}
     t0 = time.perf_counter()
     Lr, gr, lamS, _ = adj.loss_and_grad_v(v, c, emin, emax)
     t_cpu = time.perf_counter() - t0
@@ -382,8 +441,11 @@ def bench_adjoint(args, mf, torch, np, gen):
         "config": {"workload": "tridiag(-1,2+v,-1) n=4096 dense, v~U[0,1] seed 3, [0,0.2], M0=16, "
                                "L=sum lambda + sum c_k x_k^2", "pairs": int(lamS.size)},
         "accuracy": {"max_rel_grad_err_vs_oracle": err},
-        "roofline": None,
-        "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "gradients/s", "cores": _cores(), "kind": "oracle",
+        "roofline": roofline_of(prof),
+        "roofline_next": roofline_of(prof, 1),
+        "classes_ms": {"forward": {c: round(p["ms"], 3) for c, p in prof_f.items() if p["ms"] > 0},
+                       "adjoint": {c: round(p["ms"], 3) for c, p in prof_b.items() if p["ms"] > 0}},
+        "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "gradients/s", "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
                          "sample": "the whole oracle gradient (dense eigh n=4096 + eigen-sum), %.1f s" % t_cpu},
     }
 
@@ -444,7 +506,7 @@ def bench_count(args, mf, torch, np, gen):
         t0 = time.perf_counter()
         est_ref, _ = stochastic_count(A, B, EMIN, EMAX, 64, ne=3, seed=0)
         t_cpu = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "estimates/s", "cores": _cores(), "kind": "oracle",
+        result["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "estimates/s", "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
                                   "sample": "the whole oracle estimate with 64 probes (3 complex128 LUs of n=4096 "
                                             "and their solves), %.1f s; 600 probes cost more" % t_cpu}
         fpm = mf.mfeast_init_stochastic()
@@ -507,11 +569,14 @@ def main():
     m_conv = min(a["converged_pairs"] for a in acc)
     value = m_conv / t_step
 
-    # contour-solve TFLOP/s from the device profile of the timed steps
+    # contour-solve TFLOP/s from the device profile of the timed steps: algorithmic flops of
+    # the factorizations and of every contour's solves (8 per complex multiply-add) over
+    # the device time of shift-form, LU (panel, row operations, inverses, trailing update),
+    # block solves and quadrature sums
     loops = outs[-1]["loop"] + 1
     f_alg = NE * (8.0 / 3.0) * N ** 3 + loops * (2 * NE) * 8.0 * N * N * M0
     prof = profs[-1]
-    t_contour = sum(prof[c]["ms"] for c in ("lu_trailing_gemm", "lu_panel", "contour_solve", "other")) / 1e3
+    t_contour = sum(prof[c]["ms"] for c in CONTOUR_CLASSES) / 1e3
     contour_tflops = f_alg / t_contour / 1e12 if t_contour > 0 else None
 
     roofline = roofline_of(prof)
@@ -519,6 +584,10 @@ def main():
     # the second one's roofline is reported beside the first
     roofline_next = roofline_of(prof, 1)
 
+    if roofline is not None and roofline["kernel_class"] == "contour_solve":
+        roofline["rate"] = ("effective: algorithmic flops (8 per complex multiply-add) over time; the kernel "
+                            "issues Gauss's three real products per complex multiply-add and full panel inverses")
+        roofline["issued_mfma_frac"] = roofline["frac"] * SOLVE_ISSUED_PER_ALG
     result = {
         "metric": METRIC, "value": value, "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -527,6 +596,8 @@ def main():
                                "interval [-1,1], res<=1e-10, FP32+IR (fpm42=1)",
                    "n": N, "m0": M0, "nodes": NE, "seed": SEED},
         "contour_tflops": contour_tflops,
+        "contour_tflops_kind": "effective (algorithmic flops; three-product complex FP32 MFMA)",
+        "time_split": classes_summary(prof, float(np.median(times)) * 1e3),
         "accuracy": acc[-1],
         "roofline": roofline,
         "roofline_next": roofline_next,
@@ -542,10 +613,10 @@ def main():
         loops64 = outs64[-1]["loop"] + 1
         f64_alg = NE * (8.0 / 3.0) * N ** 3 + loops64 * (2 * NE) * 8.0 * N * N * M0
         p64 = profs64[-1]
-        t64c = sum(p64[c]["ms"] for c in ("lu_trailing_gemm", "lu_panel", "contour_solve", "other")) / 1e3
+        t64c = sum(p64[c]["ms"] for c in CONTOUR_CLASSES) / 1e3
         result["fp64_plain"] = {"value": v64, "ms_per_step": t64 * 1e3, "accuracy": acc64[-1],
                                 "contour_tflops": f64_alg / t64c / 1e12 if t64c > 0 else None,
-                                "classes_ms_per_step": {c: round(p64[c]["ms"], 3) for c in p64}}
+                                "time_split": classes_summary(p64, t64 * 1e3)}
         result["speedup_fp32ir_vs_fp64"] = value / v64 if v64 > 0 else None
         loops_cpu = outs64[-1]["loop"]
     else:

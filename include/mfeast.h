@@ -101,12 +101,13 @@ int mfeast_zolotarev(double emin, double emax, int32_t ne, int32_t band_pct, dou
 /* Dense real symmetric problem (dfeast_sygv / dfeast_syev and their {x} forms).
  *  h       handle
  *  uplo    'F', 'L' or 'U': which part of A (and B) is referenced (Table tab-spec1)
- *  n       order of the system
+ *  n       order of the system (1 <= n <= 16384: the dense LU kernels' limit; else 202)
  *  A       device, n x n column-major, leading dimension lda >= n
  *  B       device, n x n column-major (ldb >= n), or NULL for B = I (standard problem)
  *  fpm     host, 64 int32 (in/out; fpm(60) unused here)
  *  emin, emax  search interval (closed)
- *  m0      host, in: subspace size M0 (1 <= M0 <= n); out: possibly reduced M0
+ *  m0      host, in: subspace size M0 (1 <= M0 <= min(n, 1024): the reduced eigensolver's
+ *          limit; else 201); out: possibly reduced M0
  *  E       device, m0 doubles: eigenvalues, inside pairs first (ascending), then outside
  *          (in: initial guess when fpm(5)=1)
  *  X       device, n x m0 column-major (ldx >= n): eigenvectors following E, or the
@@ -257,14 +258,26 @@ int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, int64_t lda,
 int mfeast_get_timing(mfeast_handle h, double* out);
 
 /* Device timing by kernel class of the last call, recorded with HIP events on the
- * handle's stream when fpm(52)=1 was set for that call (project slot, reserved in the
- * guide).  For class c: out[4c+0] launches (or launch groups), [4c+1] milliseconds,
- * [4c+2] algorithmic flops (8 per complex multiply-add), [4c+3] algorithmic bytes.
- * Classes: 0 LU trailing update, 1 LU panel, 2 contour solves (per direction),
- * 3 FP64 Rayleigh-Ritz products, 4 reduced eigensolver, 5 other kernels,
- * 6 sparse shifted products inside BiCGSTAB, 7 BiCGSTAB vector updates and reductions.
- * out: host, `count` doubles (32 cover all classes). */
+ * handle's streams when fpm(52)=1 was set for that call (project slot, reserved in the
+ * guide) or mfeast_set_profiling(h, 1) is in effect (the only switch for
+ * mfeast_dsy_adjoint).  For class c: out[4c+0] launches (or launch groups), [4c+1]
+ * milliseconds, [4c+2] algorithmic flops (8 per complex multiply-add), [4c+3]
+ * algorithmic bytes.  Classes: 0 LU trailing update, 1 LU panel (leaves and their
+ * updates), 2 contour solves (per direction), 3 FP64 Rayleigh-Ritz products, 4 reduced
+ * eigensolver, 5 other kernels (shift-form, right-hand sides, quadrature sum, small
+ * copies), 6 sparse shifted products inside
+ * BiCGSTAB, 7 BiCGSTAB vector updates and reductions, 8 B-orthonormalization
+ * (equilibration, Cholesky with column drops, Newton-Schulz), 9 LU row interchanges,
+ * U12 substitution and the inverses of the diagonal blocks and panels, 10 residual
+ * norms and the B^-1 products of the found-pair test.  For the
+ * batched entry point the classes are summed over all problems (their streams run
+ * concurrently, so the times may add up to more than the call's wall time).
+ * out: host, `count` doubles (44 cover all classes). */
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count);
+
+/* Per-class timing (see mfeast_get_profile) for every later call on the handle:
+ * on = 1 enables, 0 disables (then fpm(52) decides per call).  Returns 0, -101, -102. */
+int mfeast_set_profiling(mfeast_handle h, int32_t on);
 
 #ifdef __cplusplus
 }

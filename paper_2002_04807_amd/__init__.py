@@ -25,7 +25,7 @@ EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
     "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_dsygv_noalloc",
     "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint", "mfeast_dsygv_batched", "mfeast_get_timing",
-    "mfeast_get_profile",
+    "mfeast_get_profile", "mfeast_set_profiling",
 )
 
 
@@ -78,6 +78,8 @@ def _load():
     lib.mfeast_dsygv_batched.restype = c_int
     lib.mfeast_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_get_timing.restype = c_int
+    lib.mfeast_set_profiling.argtypes = [c_vp, ctypes.c_int32]
+    lib.mfeast_set_profiling.restype = c_int
     lib.mfeast_get_profile.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     lib.mfeast_get_profile.restype = c_int
     _lib = lib
@@ -185,7 +187,13 @@ class Handle:
         return list(out)
 
     PROFILE_CLASSES = ("lu_trailing_gemm", "lu_panel", "contour_solve", "rr_gemm", "reduced_eig", "other",
-                       "bicgstab_spmv", "bicgstab_vector")
+                       "bicgstab_spmv", "bicgstab_vector", "orth", "lu_rows", "resid")
+
+    def set_profiling(self, on=True):
+        """Per-class device timing of every later call on this handle (mfeast_set_profiling)."""
+        info = _load().mfeast_set_profiling(self.ptr, 1 if on else 0)
+        if info != 0:
+            raise RuntimeError("mfeast_set_profiling failed with info %d" % info)
 
     def profile(self):
         """Per-class device timing of the last call made with fpm[51] = 1."""

@@ -218,7 +218,14 @@ extern "C" int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, i
   if (gA != nullptr && ldga < n) return -114;
   if (hipSetDevice(h->device) != hipSuccess) return -900;
   GemmScratchScope scratch_scope(h);
-  prof_enable(false);
-  if (precision == 1) return adjoint_run<c32>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 4);
-  return adjoint_run<c64>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 1);
+  prof_enable(h->prof_all);
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
+  const int rc = precision == 1 ? adjoint_run<c32>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 4)
+                                : adjoint_run<c64>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 1);
+  if (prof_on()) {
+    (void)hipStreamSynchronize(h->stream);
+    prof_collect(h->prof);
+    prof_enable(false);
+  }
+  return rc;
 }

@@ -78,6 +78,8 @@ struct mfeast_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double timing[8] = {};
   double prof[mf::K_NCLASS * 4] = {};
+  bool prof_all = false;  // per-class timing of every later call (mfeast_set_profiling)
+  double prof_sum[mf::K_NCLASS * 4] = {};  // batched workers: classes summed over their calls
   // Allocation-free mode (mfeast_dsygv_noalloc): every workspace slot is carved from a
   // caller-supplied device region (a static device array), host staging uses ordinary
   // host memory, and nothing is ever freed.  A request that does not fit sets

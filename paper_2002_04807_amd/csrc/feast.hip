@@ -45,6 +45,10 @@ constexpr double RANK_TOL = 1.0e-13;  // kept directions of the equilibrated ove
 // (mixtures of weakly filtered eigenvectors from both sides of the interval) and are not
 // counted among the M eigenvalues found.
 constexpr double SPURIOUS_RES = 1.0e-1;
+// Sizes the kernels support: the dense LU up to n = 16384 rows, the reduced eigensolver up
+// to M0 = 1024 (larger values are reported as invalid N / M0, Table tab_info 202 / 201)
+constexpr int64_t MAX_DENSE_N = 16384;
+constexpr int MAX_M0 = 1024;
 
 }  // namespace
 
@@ -376,7 +380,7 @@ struct DenseOp : Operator<T> {
     {
       const int tok = prof_begin(s);
       MF_TRY(panel_inverses<C>(s, n, nf, LU, Dinv, Pinv));
-      prof_end(tok, s, K_OTHER, 0.0, 0.0);
+      prof_end(tok, s, K_LU_ROWS, 0.0, 0.0);
     }
     MF_HIP_CHECK(hipMemcpyAsync(hinfo, linfo, nf * 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -396,7 +400,7 @@ struct DenseOp : Operator<T> {
     MF_TRY(lu_solve<C>(s, n, m, 1, LU + (int64_t)ne * n * ld, Pinv + (size_t)ne * panel_inverse_entries(n), Wf,
                        nullptr, Wy, nullptr));
     MF_TRY(col_dots_mixed<T, C>(s, n, m, R, Wf, cs, out, partial));
-    prof_end(tok, s, K_OTHER, 8.0 * (double)n * n * m, 0.0);
+    prof_end(tok, s, K_RESID, 8.0 * (double)n * n * m, 0.0);
     return 0;
   }
 
@@ -883,10 +887,12 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       MF_TRY(copy_block<T>(s, m0, m0, Cm, m0, Sm, m0, false));
     }
     MF_HIP_CHECK(hipMemsetAsync(dflag, 0, 16, s));
+    int otok = prof_begin(s);
     MF_TRY(gram_equilibrate<T>(s, m0, Sm, Tm, d_dscale, dflag));
     // pass 1: Cholesky of the equilibrated overlap with column dropping (d_perm = keep mask)
     const double tau = 32.0 * m0 * 2.220446049250313e-16;
     MF_TRY(chol_drop<T>(s, m0, Sm, Hw, d_perm, tau, TG));
+    prof_end(otok, s, K_ORTH, 0.0, 0.0);
     MF_HIP_CHECK(hipMemcpyAsync(h_perm, d_perm, m0 * sizeof(int), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipMemcpyAsync(h_flag, dflag, 4, hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -915,7 +921,9 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     MF_TRY(rm_gemm<T>(s, kk, kk, (int)n, Q1, kk, true, true, AQ1, kk, Tm, kk));
     MF_TRY(hermitian_part<T>(s, kk, Sm));
     MF_TRY(hermitian_part<T>(s, kk, Tm));
+    otok = prof_begin(s);
     MF_TRY(dev_from_identity<T>(s, kk, Sm, part, d_bn));
+    prof_end(otok, s, K_ORTH, 0.0, 0.0);
     double dev_f = 0.0;
     MF_HIP_CHECK(hipMemcpyAsync(&h_bn[0], d_bn, sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -928,8 +936,11 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     if (dev_f < 0.5) {
       int iters = 1;
       for (double e = dev_f; e > 1e-18 && iters < 12; ++iters) e = 0.75 * e * e + 1e-300;
+      otok = prof_begin(s);
       MF_TRY(ns_invsqrt<T>(s, kk, Sm, V, iters, TG));
       MF_TRY(hermitian_part<T>(s, kk, V));
+      prof_end(otok, s, K_ORTH, 8.0 * (is_cplx<T>::value ? 4.0 : 1.0) * 3.0 * iters * (double)kk * kk * kk / 4.0,
+               0.0);
     } else {
       // far from orthonormal: eigen-decompose S1 and drop its weak directions
       MF_TRY(eig_timed<T>(s, kk, Sm, Zm, d_evals, d_sweeps, (double*)Hw));
@@ -1021,7 +1032,11 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, AQ1, kk, false, false, W, kk2, AXn, kk2));
     if (hasB) MF_TRY(rm_gemm<T>(s, (int)n, kk2, kk, BQ1, kk, false, false, W, kk2, BXn, kk2));
     m0 = kk2;
-    MF_TRY(residual_norms<T>(s, n, m0, AXn, BXn, d_lam, R, d_rn, d_bn, part));
+    {
+      const int rtok = prof_begin(s);
+      MF_TRY(residual_norms<T>(s, n, m0, AXn, BXn, d_lam, R, d_rn, d_bn, part));
+      prof_end(rtok, s, K_RESID, 0.0, (double)n * m0 * 3.0 * sizeof(T));
+    }
     MF_HIP_CHECK(hipMemcpyAsync(h_rn, d_rn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipMemcpyAsync(h_bn, d_bn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
@@ -1154,7 +1169,7 @@ template <typename T>
 static int run_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, double emin, double emax,
                     int32_t* m0, double* E, T* X, int64_t ldx, int32_t* M, double* res, double* epsout,
                     int32_t* loop, const std::vector<c64>& z, const std::vector<c64>& w, double c_inf) {
-  prof_enable(fpm[51] == 1);
+  prof_enable(fpm[51] == 1 || h->prof_all);
   for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
   const int info = feast_loop<T>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w, c_inf);
   if (prof_on()) {
@@ -1171,9 +1186,9 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
                        int64_t ldx, int32_t* M, double* res, double* epsout, int32_t* loop, const double* zne,
                        const double* wne) {
   // Table tab_info order: N, M0, interval, fpm, then argument positions
-  if (n < 1) return 202;
+  if (n < 1 || n > MAX_DENSE_N) return 202;
   if (m0 == nullptr) return -111;
-  if (*m0 < 1 || *m0 > n) return 201;
+  if (*m0 < 1 || *m0 > n || *m0 > MAX_M0) return 201;
   if (!(emin < emax)) return 200;
   if (fpm == nullptr) return -108;
   if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -119 : -120;
@@ -1215,7 +1230,7 @@ static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, con
                      double* epsout, int32_t* loop, const double* zne, const double* wne) {
   if (n < 1) return 202;
   if (m0 == nullptr) return -114;
-  if (*m0 < 1 || *m0 > n) return 201;
+  if (*m0 < 1 || *m0 > n || *m0 > MAX_M0) return 201;
   if (!(emin < emax)) return 200;
   if (fpm == nullptr) return -111;
   if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -122 : -123;
@@ -1492,6 +1507,8 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
   for (int p = 0; p < nprob; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
   std::atomic<int> next(0);
+  for (mfeast_ctx* w : h->workers)
+    for (int i = 0; i < K_NCLASS * 4; ++i) w->prof_sum[i] = 0.0;
   auto work = [&](mfeast_ctx* w) {
     (void)hipSetDevice(w->device);
     set_coop_allowed(false);
@@ -1501,11 +1518,12 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
       const int p = order[t];
       int32_t f[64];
       for (int i = 0; i < 64; ++i) f[i] = fpm[i];
-      f[51] = 0;
+      f[51] = (fpm[51] == 1 || h->prof_all) ? 1 : 0;
       const double* Bp = B ? B[p] : nullptr;
       const int64_t ldbp = B ? ldb[p] : n[p];
       info[p] = dense_entry<double>(w, 'F', n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p], X[p],
                                     ldx[p], &M[p], res[p], &epsout[p], &loop[p], nullptr, nullptr);
+      for (int i = 0; i < K_NCLASS * 4; ++i) w->prof_sum[i] += w->prof[i];
     }
     (void)hipStreamSynchronize(w->stream);
     set_coop_allowed(true);
@@ -1514,6 +1532,11 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
   for (int i = 1; i < nw; ++i) threads.emplace_back(work, h->workers[i]);
   work(h->workers[0]);
   for (std::thread& t : threads) t.join();
+  // per-class timings: the sum over the workers' last calls is not meaningful, so each
+  // worker keeps a running sum of its calls' classes (see work above) and they are added
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
+  for (int wi = 0; wi < nw; ++wi)
+    for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] += h->workers[wi]->prof_sum[i];
   int worst = 0;
   for (int p = 0; p < nprob; ++p)
     if (info[p] < 0 && (worst >= 0 || info[p] < worst)) worst = info[p];
@@ -1541,6 +1564,13 @@ void mfeast_init_stochastic(int32_t* fpm) {
   fpm[7] = 6;    // fpm(8)  full-contour nodes (non-Hermitian, unused)
   fpm[13] = 2;   // fpm(14) stochastic estimate of the count
   fpm[14] = 1;   // fpm(15) one-sided contour
+}
+
+int mfeast_set_profiling(mfeast_handle h, int32_t on) {
+  if (h == nullptr) return -101;
+  if (on != 0 && on != 1) return -102;
+  h->prof_all = on == 1;
+  return 0;
 }
 
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count) {

@@ -668,6 +668,8 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
     if (launch_leaves<C>(s, n, (int)k, nbc, ne, LU, ipiv, perm, info)) return -2;
     // panel flops: (n-k) nbc^2 / 2 complex multiply-adds per node
     prof_end(tok, s, K_LU_PANEL, 8.0 * 0.5 * (double)(n - k) * nbc * nbc * ne, 2.0 * sizeof(C) * (n - k) * nbc * ne);
+    // row interchanges outside the panel and U12 = L11^-1 A12
+    tok = prof_begin(s);
     hipLaunchKernelGGL((k_laswp<C>), dim3((unsigned)((n + LSW_COLS - 1) / LSW_COLS), ne), dim3(256), 0, s, n, ld, (int)k,
                        nbc, LU, ipiv);
     const int64_t rest = n - k - nbc;
@@ -676,6 +678,10 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
       constexpr int CW = u12_cols<C>::value;
       hipLaunchKernelGGL((k_trsm_u12<C>), dim3((unsigned)((rest + CW - 1) / CW), ne), dim3(256), 0, s, n, ld, (int)k,
                          (int)rest, LU);
+    }
+    prof_end(tok, s, K_LU_ROWS, 8.0 * 0.5 * (double)nbc * nbc * (rest > 0 ? rest : 0) * ne,
+             2.0 * sizeof(C) * (double)ne * nbc * n);
+    if (rest > 0) {
       // A22 -= L21 U12
       GemmArgs t{};
       t.M = (int)rest; t.N = (int)rest; t.K = nbc;
@@ -692,8 +698,10 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
   }
   // inverses of every diagonal block, for the solves
   const int64_t nblk = (n + LU_NB - 1) / LU_NB;
+  const int tok = prof_begin(s);
   hipLaunchKernelGGL((k_invert_diag<C>), dim3((unsigned)nblk, ne), dim3(256), 0, s, n, ld, 0, (int)nblk, LU, Dinv);
   hipLaunchKernelGGL(k_perm_inverse, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, s, n, ne, perm, perm_inv);
+  prof_end(tok, s, K_LU_ROWS, 0.0, 0.0);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -19,7 +19,10 @@ enum KClass {
   K_OTHER = 5,     // shift-form, right-hand sides, quadrature sum, small kernels
   K_SPMV = 6,      // sparse shifted products inside BiCGSTAB
   K_BICG = 7,      // BiCGSTAB vector updates and reductions
-  K_NCLASS = 8
+  K_ORTH = 8,      // B-orthonormalization: equilibration, Cholesky with drops, Newton-Schulz
+  K_LU_ROWS = 9,   // LU row interchanges, U12 substitution, diagonal-block and panel inverses
+  K_RESID = 10,    // residual norms and the B^-1 products of the found-pair test
+  K_NCLASS = 11
 };
 
 bool prof_on();

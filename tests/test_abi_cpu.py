@@ -99,6 +99,9 @@ def test_argument_checks_in_table_order(name):
     assert _call(name, n=0) == 202
     assert _call(name, m0=0) == 201
     assert _call(name, m0=11) == 201
+    # the kernels' limits: n <= 16384 (dense LU), M0 <= 1024 (reduced eigensolver)
+    assert _call(name, n=16385, m0=4) == 202
+    assert _call(name, n=2000, m0=1025) == 201
     assert _call(name, emin=1.0, emax=1.0) == 200
     for idx, val, code in [(1, 21, 102), (2, 17, 103), (3, -1, 104), (4, 2, 105), (5, 2, 106),
                            (13, 3, 114), (15, 3, 116), (17, 0, 118), (41, 2, 142), (49, 9, 150),
