@@ -395,12 +395,14 @@ struct DenseOp : Operator<T> {
   int binv_dots(hipStream_t s, int m, const T* R, const double* cs, double* out, double* partial) override {
     if (nf == ne) return -2;
     const int64_t ld = lu_ld(n);
-    const int tok = prof_begin(s);
+    int tok = prof_begin(s);
     MF_TRY(rhs_prepare<T, C>(s, n, m, R, m, cs, 1, perm + (int64_t)ne * n, Wf, nullptr));
+    prof_end(tok, s, K_RESID, 0.0, (double)n * m * (sizeof(T) + sizeof(C)));
     MF_TRY(lu_solve<C>(s, n, m, 1, LU + (int64_t)ne * n * ld, Pinv + (size_t)ne * panel_inverse_entries(n), Wf,
-                       nullptr, Wy, nullptr));
+                       nullptr, Wy, nullptr, K_RESID));
+    tok = prof_begin(s);
     MF_TRY(col_dots_mixed<T, C>(s, n, m, R, Wf, cs, out, partial));
-    prof_end(tok, s, K_RESID, 8.0 * (double)n * n * m, 0.0);
+    prof_end(tok, s, K_RESID, 0.0, (double)n * m * (sizeof(T) + sizeof(C)));
     return 0;
   }
 
@@ -1041,18 +1043,6 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     MF_HIP_CHECK(hipMemcpyAsync(h_bn, d_bn, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_prod += ph.stop();
-    // Kato-Temple terms of the found-pair test: r^H B^-1 r (||r||^2 for B = I)
-    if (hasB) {
-      ph.start();
-      for (int c = 0; c < m0; ++c) h_kcs[c] = (h_rn[c] > 0.0 && std::isfinite(h_rn[c])) ? 1.0 / std::sqrt(h_rn[c]) : 1.0;
-      MF_HIP_CHECK(hipMemcpyAsync(d_kcs, h_kcs, m0 * sizeof(double), hipMemcpyHostToDevice, s));
-      MF_TRY(op.binv_dots(s, m0, R, d_kcs, d_kt, part));
-      MF_HIP_CHECK(hipMemcpyAsync(h_kt, d_kt, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
-      MF_HIP_CHECK(hipStreamSynchronize(s));
-      t_bx += ph.stop();
-    } else {
-      for (int c = 0; c < m0; ++c) h_kt[c] = h_rn[c];
-    }
     res_h.assign(m0, 0.0);
     bool finite = true;
     for (int i = 0; i < m0; ++i) {
@@ -1060,6 +1050,36 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       if (!std::isfinite(res_h[i])) finite = false;
     }
     if (!finite) { info = -2; break; }
+    // Kato-Temple terms of the found-pair test: r^H B^-1 r (||r||^2 for B = I), needed only
+    // for the candidates (inside the interval, relative residual below SPURIOUS_RES); their
+    // residual columns are gathered into Q (free at this point), scaled by 1/||r||
+    if (hasB) {
+      ph.start();
+      int kc = 0;
+      for (int c = 0; c < m0; ++c) {
+        h_kt[c] = 0.0;
+        const double l = lam_cur[c];
+        if (l >= emin && l <= emax && res_h[c] < SPURIOUS_RES) {
+          h_idx[kc] = c;
+          h_kcs[kc] = h_rn[c] > 0.0 ? 1.0 / std::sqrt(h_rn[c]) : 1.0;
+          ++kc;
+        }
+      }
+      if (kc > 0) {
+        for (int q = 0; q < kc; ++q) h_gs[q] = 1.0;
+        MF_HIP_CHECK(hipMemcpyAsync(d_idx, h_idx, kc * sizeof(int), hipMemcpyHostToDevice, s));
+        MF_HIP_CHECK(hipMemcpyAsync(d_kcs, h_kcs, kc * sizeof(double), hipMemcpyHostToDevice, s));
+        MF_HIP_CHECK(hipMemcpyAsync(d_gs, h_gs, kc * sizeof(double), hipMemcpyHostToDevice, s));
+        MF_TRY(gather_scale_cols<T>(s, (int)n, kc, R, m0, d_idx, d_kcs, Q, kc));
+        MF_TRY(op.binv_dots(s, kc, Q, d_gs, d_kt, part));
+        MF_HIP_CHECK(hipMemcpyAsync(h_gs, d_kt, kc * sizeof(double), hipMemcpyDeviceToHost, s));
+        MF_HIP_CHECK(hipStreamSynchronize(s));
+        for (int q = 0; q < kc; ++q) h_kt[h_idx[q]] = h_gs[q] / (h_kcs[q] * h_kcs[q]);
+      }
+      t_bx += ph.stop();
+    } else {
+      for (int c = 0; c < m0; ++c) h_kt[c] = h_rn[c];
+    }
     // found pairs: inside the interval with a residual below the spurious threshold
     int n_inside = 0;
     M = 0;

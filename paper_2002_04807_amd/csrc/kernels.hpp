@@ -106,7 +106,7 @@ struct SolveSide {
 };
 template <typename C>
 int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y,
-             const SolveSide<C>* side = nullptr);
+             const SolveSide<C>* side = nullptr, int cls = K_SOLVE_GEMM);
 
 // Refinement of the FP32 contour solves (fpm(50)): dst = (add ? dst : 0) + widen(src);
 // row gather dst_j[r] = src_j[perm_inv_j[r]]; residual of node j's system (z_j B - A) x

@@ -220,7 +220,7 @@ int panel_inverses(hipStream_t s, int64_t n, int ne, const C* LU, const C* Dinv,
 
 template <typename C>
 int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv, C* Wf, C* Wc, C* Y,
-             const SolveSide<C>* side) {
+             const SolveSide<C>* side, int cls) {
   using R = typename real_of<C>::type;
   const int64_t wstride = n * (int64_t)m;
   const int64_t ld = lu_ld(n);
@@ -281,18 +281,18 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
     if (hipEventRecord(side->join, side->s2) != hipSuccess) return -2;
     if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
     if (hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return -2;
-    prof_end(tok, s, K_SOLVE_GEMM, 2.0 * dir_flops, 2.0 * dir_bytes);
+    prof_end(tok, s, cls, 2.0 * dir_flops, 2.0 * dir_bytes);
     return 0;
   }
   // forward direction: L (W -> Y) then U (Y -> W)
   int tok = prof_begin(s);
   if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
-  prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
+  prof_end(tok, s, cls, dir_flops, dir_bytes);
   if (Wc == nullptr) return 0;
   // conjugate-transpose direction: U^H (lower) then L^H (unit upper)
   tok = prof_begin(s);
   if (sweep(s, Wc, Y, false, true) || sweep(s, Y, Wc, true, true)) return -2;
-  prof_end(tok, s, K_SOLVE_GEMM, dir_flops, dir_bytes);
+  prof_end(tok, s, cls, dir_flops, dir_bytes);
   return 0;
 }
 
@@ -425,9 +425,9 @@ template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, 
 template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*);
 template int rhs_prepare<c64, c64>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c64*, c64*);
 template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*, c32*,
-                          const SolveSide<c32>*);
+                          const SolveSide<c32>*, int);
 template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*, c64*,
-                          const SolveSide<c64>*);
+                          const SolveSide<c64>*, int);
 template int panel_inverses<c32>(hipStream_t, int64_t, int, const c32*, const c32*, c32*);
 template int panel_inverses<c64>(hipStream_t, int64_t, int, const c64*, const c64*, c64*);
 template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
