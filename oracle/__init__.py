@@ -22,6 +22,7 @@ from .zolotarev import zolotarev_contour, zolotarev_filter, zolotarev_sign
 from .splitmix import splitmix64_uniform, initial_subspace
 from .ifeast import bicgstab_block, feast_csr, ifeastinit
 from . import adjoint
+from . import nonhermitian
 from . import stochastic
 from .feast import (
     feastinit,
@@ -49,5 +50,6 @@ __all__ = [
     "feast_csr",
     "ifeastinit",
     "adjoint",
+    "nonhermitian",
     "stochastic",
 ]

@@ -151,3 +151,30 @@ def differentiation_problem(n=4096, seed=3):
     c = rng.standard_normal(n)
     A = 2.0 * np.eye(n) + np.diag(v) - np.eye(n, k=1) - np.eye(n, k=-1)
     return v, c, A
+
+
+def prescribed_nonnormal(n, seed, generalized=False, spread=2.0, coupling=0.3):
+    """Complex general matrix (pencil) with a known spectrum and known eigenvectors.
+
+    Draw order from default_rng(seed): lambda (real parts, then imaginary parts, each
+    U[-spread, spread]), then G (complex Gaussian n x n) for V = I + coupling G / sqrt(n),
+    then, for a pencil, C (complex Gaussian n x n) for B = I + 0.1 C C^H / n.
+    A = B V diag(lambda) V^-1 (B = I for the standard problem), so the right
+    eigenvectors are the columns of V and the left ones, y_i^H A = lambda_i y_i^H B, the
+    columns of Y = (V^-1 B^-1)^H.  Returns (A, B or None, lambda, V, Y)."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(-spread, spread, n) + 1j * rng.uniform(-spread, spread, n)
+    G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    V = np.eye(n) + coupling * G / np.sqrt(n)
+    Vinv = np.linalg.inv(V)
+    if generalized:
+        C = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+        B = np.eye(n) + 0.1 * (C @ C.conj().T) / n
+        B = 0.5 * (B + B.conj().T)
+    else:
+        B = None
+    K = (V * lam[None, :]) @ Vinv
+    A = K if B is None else B @ K
+    Binv = np.eye(n) if B is None else np.linalg.inv(B)
+    Y = (Vinv @ Binv).conj().T
+    return A, B, lam, V, Y
