@@ -159,6 +159,57 @@ int mfeast_zhegv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
                  double* epsout, int32_t* loop, const double* zne, const double* wne);
 
+/* Non-Hermitian FEAST (Section 3.3 "FEAST Non-Hermitian"; Tables tab-common2, tab-rci2)
+ * ---------------------------------------------------------------------------------------
+ * mfeast_init_general: mfeast_init, then the non-Hermitian defaults of Table tab_fpm:
+ * fpm(15)=0 (two-sided: right and left eigenvectors), fpm(16)=1 (trapezoidal),
+ * fpm(18)=100 (circle); fpm(8)=16 full-contour nodes is common. */
+void mfeast_init_general(int32_t* fpm);
+
+/* Full-contour nodes and weights (zfeast_gcontour; Section 4.2 "Search contour"): the
+ * ellipse z(t) = Emid + e^{i phi} (r cos t + i e r sin t), t in [0, 2 pi), with e =
+ * ratio_pct/100 and phi = angle_deg degrees (counter-clockwise; 0 keeps the axes on the
+ * real and imaginary directions), ne nodes: rule 1 trapezoidal (t_j = 2 pi (j - 1/2)/ne,
+ * ne >= 2), rule 0 Gauss-Legendre in t (ne in 2..40, 48, 64, 80, 96, 112).  The filter
+ * of an eigenvalue lambda is sum_j w_j / (z_j - lambda).  zne, wne: host, 2*ne doubles.
+ * Returns 0, 200 (r <= 0), 108, 116, 118, 119 (angle outside -180..180), -108, -109. */
+int mfeast_gcontour(double emid_re, double emid_im, double r, int32_t ne, int32_t rule, int32_t ratio_pct,
+                    int32_t angle_deg, double* zne, double* wne);
+
+/* Dense complex general problem A x = lambda B x (zfeast_gegv / zfeast_geev and their {x}
+ * forms; real general matrices are passed as complex): the eigenvalues inside the full
+ * contour of Emid, r, fpm(18), fpm(19) with fpm(8) nodes (or the expert nodes zne,
+ * weights wne: host, 2*fpm(8) doubles each), their right eigenvectors and, with
+ * fpm(15)=0, their left eigenvectors (y^H A = lambda y^H B).  Each node's z_j B - A is
+ * factored once; right solves use (z_j B - A)^-1 and left solves (z_j B - A)^-H with the
+ * same factors (RCI cases 10/11/20/21).  fpm(42)=1 factors and solves in complex FP32
+ * with the FP64 residual form, fpm(42)=0 in complex FP64.
+ *  A, B    device, n x n complex column-major (lda, ldb >= n); B NULL for B = I
+ *  fpm     host, 64 int32 (fpm(14) must be 0)
+ *  epsout  host: |trace_k - trace_{k-1}| / alpha, alpha = |Emid| + r
+ *  loop    host: index of the last iteration
+ *  emid    host, 2 doubles (re, im): centre of the ellipse; r > 0 its horizontal radius
+ *  m0      host, in: subspace size (1 <= M0 <= min(n, 512)); out: possibly reduced
+ *  E       device, 2*m0 doubles: complex eigenvalues, the M inside the contour first, then
+ *          the others (each group by real part, then imaginary part)
+ *  X       device, complex column-major (ldx >= n): right eigenvectors (unit 2-norm) in
+ *          columns 0..m0-1 following E; with fpm(15)=0 left eigenvectors, scaled so that
+ *          y_i^H B x_i = 1, in columns M0..M0+m0-1 (M0 the value on entry), so X holds
+ *          2*M0 columns.  With fpm(5)=1 the same columns hold the starting blocks.
+ *  M       host: number of eigenvalues inside the contour
+ *  res     device: ||A x_i - lambda_i B x_i|| / ||alpha B x_i|| in res[0..m0-1]; with
+ *          fpm(15)=0 ||A^H y_i - conj(lambda_i) B^H y_i|| / ||alpha B^H y_i|| in
+ *          res[M0..M0+m0-1] (2*M0 doubles)
+ * The reduced pencil (Q~^H A Q, Q~^H B Q on orthonormal, rank-truncated bases of the two
+ * subspaces) is solved on the device in one workgroup.  Returns Table tab_info codes:
+ * 202 (n), 201 (M0), 200 (r or Emid), 1xx (fpm(i)), -(100+i) for argument i, 1 (no
+ * eigenvalue inside), 2 (no convergence), 3 (M0 too small), -2, -3 (reduced pencil
+ * singular or its eigensolver did not converge), -900. */
+int mfeast_zgegv(mfeast_handle h, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 int32_t* fpm, double* epsout, int32_t* loop, const double* emid, double r, int32_t* m0,
+                 double* E, double* X, int64_t ldx, int32_t* M, double* res, const double* zne,
+                 const double* wne);
+
 /* Many independent dense real symmetric problems in one call (the first of the three
  * levels of parallelism of Section 1.1, independent search intervals or problems): the
  * arguments of mfeast_dsygv as arrays over nprob problems.  n, lda, ldb, ldx, emin, emax,

@@ -25,7 +25,7 @@ EXPORTED = (
     "mfeast_create", "mfeast_destroy", "mfeast_set_stream", "mfeast_init", "mfeast_init_ifeast",
     "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_dsygv_noalloc",
     "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint", "mfeast_dsygv_batched", "mfeast_get_timing",
-    "mfeast_get_profile", "mfeast_set_profiling",
+    "mfeast_get_profile", "mfeast_set_profiling", "mfeast_init_general", "mfeast_gcontour", "mfeast_zgegv",
 )
 
 
@@ -57,6 +57,14 @@ def _load():
     lib.mfeast_zolotarev.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, c_dp, c_dp,
                                      ctypes.POINTER(ctypes.c_double)]
     lib.mfeast_zolotarev.restype = c_int
+    lib.mfeast_init_general.argtypes = [c_i32p]
+    lib.mfeast_init_general.restype = None
+    lib.mfeast_gcontour.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, c_dp, c_dp]
+    lib.mfeast_gcontour.restype = c_int
+    lib.mfeast_zgegv.argtypes = [c_vp, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.POINTER(ctypes.c_double), c_i32p,
+                                 c_dp, ctypes.c_double, c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, c_dp, c_dp]
+    lib.mfeast_zgegv.restype = c_int
     dense = [c_vp, ctypes.c_char, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.c_double, ctypes.c_double,
              c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
     for name in ("mfeast_dsygv", "mfeast_zhegv", "mfeast_dsygv_noalloc"):
@@ -147,6 +155,23 @@ def mfeast_zolotarev(emin, emax, ne, band_pct=90):
     info = _load().mfeast_zolotarev(float(emin), float(emax), int(ne), int(band_pct), zb.ctypes.data,
                                     wb.ctypes.data, ctypes.byref(c))
     return info, zb.view(np.complex128)[:ne].copy(), wb.view(np.complex128)[:ne].copy(), c.value
+
+
+def mfeast_init_general():
+    """fpm defaults of the non-Hermitian driver (two-sided, trapezoidal, circle)."""
+    fpm = np.zeros(64, dtype=np.int32)
+    _load().mfeast_init_general(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return fpm
+
+
+def mfeast_gcontour(emid, r, ne, rule=1, ratio_pct=100, angle_deg=0):
+    """(info, z, w): full-contour nodes and weights as complex128 arrays."""
+    zb = np.zeros(2 * max(int(ne), 1), dtype=np.float64)
+    wb = np.zeros_like(zb)
+    emid = complex(emid)
+    info = _load().mfeast_gcontour(emid.real, emid.imag, float(r), int(ne), int(rule), int(ratio_pct), int(angle_deg),
+                                   zb.ctypes.data, wb.ctypes.data)
+    return info, zb.view(np.complex128)[:ne].copy(), wb.view(np.complex128)[:ne].copy()
 
 
 class Handle:
@@ -470,3 +495,63 @@ def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None):
         out.append({"info": int(info[p]), "M": int(M[p]), "m0": m, "loop": int(loop[p]), "epsout": float(eps[p]),
                     "E": E[p][:m], "X": X[p][:, :m], "res": R[p][:m]})
     return int(ret), out, seconds
+
+
+def mfeast_zgegv(h, n, A, lda, B, ldb, fpm, emid, r, m0, E, X, ldx, res, zne=None, wne=None):
+    """C mfeast_zgegv; A, B, E, X, res device tensors (complex128 column-major A, B, X;
+    E complex128 of m0 values; res float64 of m0 or 2 m0 values)."""
+    lib = _load()
+    fpm_a = _fpm_array(fpm)
+    m0_c = ctypes.c_int32(int(m0))
+    M_c = ctypes.c_int32(0)
+    eps_c = ctypes.c_double(0.0)
+    loop_c = ctypes.c_int32(0)
+    em = np.array([complex(emid).real, complex(emid).imag], dtype=np.float64)
+    zb = wb = None
+    if zne is not None:
+        zb = np.ascontiguousarray(np.asarray(zne, dtype=np.complex128)).view(np.float64)
+        wb = np.ascontiguousarray(np.asarray(wne, dtype=np.complex128)).view(np.float64)
+    hp = h.ptr if isinstance(h, Handle) else h
+    info = lib.mfeast_zgegv(hp, int(n), _ptr(A), int(lda), _ptr(B), int(ldb),
+                            fpm_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(eps_c),
+                            ctypes.byref(loop_c), em.ctypes.data, float(r), ctypes.byref(m0_c), _ptr(E), _ptr(X),
+                            int(ldx), ctypes.byref(M_c), _ptr(res), None if zb is None else zb.ctypes.data,
+                            None if wb is None else wb.ctypes.data)
+    return {"info": int(info), "m0": int(m0_c.value), "M": int(M_c.value), "epsout": float(eps_c.value),
+            "loop": int(loop_c.value)}
+
+
+def feast_general(A, B, emid, r, m0, fpm=None, X0=None, handle=None, zne=None, wne=None):
+    """Eigenvalues of A x = lambda B x inside the full contour (Emid, r) and their right
+    (and, with fpm[14] = 0, left) eigenvectors.  A, B: GPU tensors (complex128 or real,
+    B None means identity).  X0: starting vectors, n x m0 (one-sided) or n x 2 m0 (right,
+    then left).  Returns a dict with E (complex), X (right), Y (left or None), res,
+    res_left, M, m0, loop, epsout, info."""
+    import torch
+    n = A.shape[0]
+    dev = A.device
+    fpm = mfeast_init_general() if fpm is None else _fpm_array(fpm).copy()
+    two = int(fpm[14]) == 0
+    A_, lda = colmajor(A.to(torch.complex128))
+    B_, ldb = (None, n) if B is None else colmajor(B.to(torch.complex128))
+    ncol = 2 * m0 if two else m0
+    X = torch.zeros((ncol, n), dtype=torch.complex128, device=dev).mT
+    if X0 is not None:
+        X[:, :X0.shape[1]].copy_(X0.to(torch.complex128))
+        fpm[4] = 1
+    E = torch.zeros(m0, dtype=torch.complex128, device=dev)
+    res = torch.zeros(ncol, dtype=torch.float64, device=dev)
+    own = handle is None
+    h = Handle(dev.index or 0) if own else handle
+    try:
+        out = mfeast_zgegv(h, n, A_, lda, B_, ldb, fpm, emid, r, m0, E, X, n, res, zne, wne)
+        out["timing"] = h.timing()
+        if fpm[51] == 1:
+            out["profile"] = h.profile()
+    finally:
+        if own:
+            h.close()
+    m = out["m0"]
+    out.update(E=E[:m], X=X[:, :m], Y=X[:, m0:m0 + m] if two else None, res=res[:m],
+               res_left=res[m0:m0 + m] if two else None, fpm=fpm)
+    return out

@@ -19,6 +19,9 @@ enum Slot {
   S_ADJ_AD, S_ADJ_XR, S_ADJ_R, S_ADJ_Y, S_ADJ_T, S_ADJ_SMALL,
   S_IR_XF, S_IR_YC, S_IR_T, S_IR_AX, S_IR_BX,
   S_SPLITK,
+  // non-Hermitian driver: left blocks, products with A^H and B^H, bases, reduced factors
+  S_NH_XL, S_NH_QL, S_NH_RL, S_NH_AHQ, S_NH_BHQ, S_NH_QLO, S_NH_BQO, S_NH_AHQO, S_NH_BHQO, S_NH_T3, S_NH_T4,
+  S_NH_WL, S_NH_O1, S_NH_O2, S_NH_O3, S_NH_O4, S_NH_O5, S_NH_TR, S_NH_TL,
   S_NSLOTS
 };
 

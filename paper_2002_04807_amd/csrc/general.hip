@@ -1,0 +1,1128 @@
+// Non-Hermitian FEAST for dense complex general pencils (the guide's Section 3.3).
+//
+// Eigenpairs of A x = lambda B x (A, B complex general, B = I allowed) with lambda inside a
+// full contour: an ellipse centred at Emid with horizontal radius r, axis ratio
+// fpm(18)/100 and rotation fpm(19) degrees, sampled at fpm(8) nodes (trapezoidal, the
+// non-Hermitian default fpm(16) = 1, or Gauss fpm(16) = 0).  One call runs:
+//   factor    F_j = (z_j B - A)^H for every node, blocked LU (the Hermitian kernels read a
+//             column-major matrix as its conjugate transpose, so F_j is formed with the
+//             conjugate nodes and coalesced loads); right solves M_j x = b use the
+//             conjugate-transpose sweeps of F_j, left solves M_j^H y = b its forward sweeps
+//             (RCI cases 10/11/20/21 with one factorization per node)
+//   contour   iteration 0: Q = sum_j w_j M_j^-1 B Y, Q~ = sum_j conj(w_j) M_j^-H B^H Y~;
+//             iteration k > 0: the residual form with R = A X - B X Lambda and
+//             R~ = A^H Y - B^H Y conj(Lambda): Q = X rho(Lambda) + sum_j w_j M_j^-1 R
+//             (z_j - Lambda)^-1, and the conjugate form for Q~
+//   RR        equilibrated, rank-truncated orthonormal bases of Q and Q~ (Cholesky of the
+//             Gram matrix with column drops, then Newton-Schulz), the reduced pencil
+//             Aq = Q~^H A Q, Bq = Q~^H B Q (two-sided, fpm(15) = 0; Q~ = Q one-sided,
+//             fpm(15) = 1), its eigenvalues and right and left eigenvectors in one
+//             workgroup (k_nh_eig: Gauss-Jordan for Bq^-1 Aq, Householder Hessenberg form,
+//             shifted QR to the Schur form, triangular eigenvectors), X = Q W (unit
+//             columns), Y = Q~ W~ (y_i^H B x_i = 1)
+//   stop      M = #lambda inside the ellipse; residuals ||A x - lambda B x|| / ||alpha B x||
+//             and ||A^H y - conj(lambda) B^H y|| / ||alpha B^H y||, alpha = |Emid| + r;
+//             epsout = |trace_k - trace_{k-1}| / alpha (Table tab-common2).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mfeast.h"
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using namespace mf;
+
+namespace {
+
+constexpr int NH_MAX_M0 = 512;  // the reduced eigensolver runs in one workgroup
+constexpr int NH_THREADS = 256;
+constexpr double NH_RANK_TOL = 1.0e-13;
+
+// ---------------------------------------------------------------------------
+// full contour: z(theta) = emid + e^{i phi} (r cos theta + i e r sin theta), theta in
+// [0, 2 pi); (1/2 pi i) z' dtheta = (1/2 pi) e^{i phi} (e r cos theta + i r sin theta) dtheta
+void gauss_legendre_nodes(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      pp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    pp = (n == 1) ? 1.0 : n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+bool gauss_full_allowed(int ne) { return (ne >= 2 && ne <= 40) || ne == 48 || ne == 64 || ne == 80 || ne == 96 || ne == 112; }
+
+void full_contour(std::complex<double> emid, double r, int ne, int rule, int ratio_pct, int angle_deg,
+                  std::vector<std::complex<double>>& z, std::vector<std::complex<double>>& w) {
+  const double e = ratio_pct / 100.0;
+  const std::complex<double> rot = std::polar(1.0, angle_deg * M_PI / 180.0);
+  std::vector<double> x, om;
+  if (rule == 0) gauss_legendre_nodes(ne, x, om);
+  z.resize(ne);
+  w.resize(ne);
+  for (int j = 0; j < ne; ++j) {
+    double th, sc;
+    if (rule == 0) {
+      th = M_PI * (1.0 + x[j]);
+      sc = om[j] / 2.0;
+    } else {
+      th = 2.0 * M_PI * (j + 0.5) / ne;
+      sc = 1.0 / ne;
+    }
+    z[j] = emid + rot * std::complex<double>(r * std::cos(th), e * r * std::sin(th));
+    w[j] = sc * rot * std::complex<double>(e * r * std::cos(th), r * std::sin(th));
+  }
+}
+
+bool inside_ellipse(std::complex<double> l, std::complex<double> emid, double r, int ratio_pct, int angle_deg) {
+  const std::complex<double> u = std::polar(1.0, -angle_deg * M_PI / 180.0) * (l - emid);
+  const double e = ratio_pct / 100.0;
+  const double a = u.real() / r, b = u.imag() / (e * r);
+  return a * a + b * b <= 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// right-hand sides of both directions: Wc_j (right, conjugate-transpose sweeps of F_j,
+// unpermuted) from rhsR, Wf_j (left, forward sweeps, rows gathered with perm_j) from rhsL
+template <typename C>
+__global__ void k_rhs_two(int64_t n, int m, const c64* __restrict__ rhsR, const c64* __restrict__ rhsL,
+                          const double* __restrict__ csR, const double* __restrict__ csL, int ne,
+                          const int* __restrict__ perm, C* __restrict__ Wf, C* __restrict__ Wc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (c >= m) return;
+  const int64_t blk = n * (int64_t)m;
+  const C vr = convert<C, c64>(csR[c] * rhsR[i * m + c]);
+  for (int j = 0; j < ne; ++j) Wc[j * blk + i * m + c] = vr;
+  if (Wf != nullptr)
+    for (int j = 0; j < ne; ++j) {
+      const int64_t src = perm[(int64_t)j * n + i];
+      Wf[j * blk + i * m + c] = convert<C, c64>(csL[c] * rhsL[src * m + c]);
+    }
+}
+
+// Q[r][c] = [resid: rho_c X[r][c]] + usR_c sum_j cR[j][c] Wc_j[perm_inv_j[r]][c];
+// QL[r][c] = [resid: conj(rho_c) XL[r][c]] + usL_c sum_j cL[j][c] Wf_j[r][c]
+template <typename C>
+__global__ void k_accumulate_two(int64_t n, int m, int ne, const C* __restrict__ Wf, const C* __restrict__ Wc,
+                                 const int* __restrict__ perm_inv, const c64* __restrict__ cR,
+                                 const c64* __restrict__ cL, const c64* __restrict__ rho,
+                                 const double* __restrict__ usR, const double* __restrict__ usL,
+                                 const c64* __restrict__ X, const c64* __restrict__ XL, c64* __restrict__ Q,
+                                 c64* __restrict__ QL, int resid) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (c >= m) return;
+  const int64_t blk = n * (int64_t)m;
+  c64 a(0.0, 0.0), b(0.0, 0.0);
+  for (int j = 0; j < ne; ++j) {
+    const int64_t rr = perm_inv[(int64_t)j * n + r];
+    a = a + cR[(int64_t)j * m + c] * convert<c64, C>(Wc[j * blk + rr * m + c]);
+    if (Wf != nullptr) b = b + cL[(int64_t)j * m + c] * convert<c64, C>(Wf[j * blk + r * m + c]);
+  }
+  a = usR[c] * a;
+  if (resid) a = a + rho[c] * X[r * m + c];
+  Q[r * m + c] = a;
+  if (Wf != nullptr) {
+    b = usL[c] * b;
+    if (resid) b = b + conj(rho[c]) * XL[r * m + c];
+    QL[r * m + c] = b;
+  }
+}
+
+// R = AX - BX diag(lam) (conj(lam) with conj_lam), column sums of |R|^2 and |BX|^2 in
+// 256-row chunks, then one ordered sum per column
+constexpr int NH_ROWS = 256;
+__global__ void k_nh_resid_partial(int64_t n, int m, const c64* __restrict__ AX, const c64* __restrict__ BX,
+                                   const c64* __restrict__ lam, int conj_lam, c64* __restrict__ R,
+                                   double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (c >= m) return;
+  const c64 l = conj_lam ? conj(lam[c]) : lam[c];
+  double sr = 0.0, sb = 0.0;
+  const int64_t r1 = ((chunk + 1) * NH_ROWS < n) ? (chunk + 1) * NH_ROWS : n;
+  for (int64_t r = chunk * NH_ROWS; r < r1; ++r) {
+    const c64 bx = BX[r * m + c];
+    const c64 v = AX[r * m + c] - l * bx;
+    R[r * m + c] = v;
+    sr += norm2(v);
+    sb += norm2(bx);
+  }
+  const int64_t nchunk = gridDim.y;
+  part[chunk * m + c] = sr;
+  part[(nchunk + chunk) * m + c] = sb;
+}
+
+__global__ void k_nh_resid_final(int m, int nchunk, const double* __restrict__ part, double* __restrict__ rn2,
+                                 double* __restrict__ bn2) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  double a = 0.0, b = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    a += part[(int64_t)ch * m + c];
+    b += part[(int64_t)(nchunk + ch) * m + c];
+  }
+  rn2[c] = a;
+  bn2[c] = b;
+}
+
+int nh_resid(hipStream_t s, int64_t n, int m, const c64* AX, const c64* BX, const c64* lam, bool conj_lam, c64* R,
+             double* rn2, double* bn2, double* part) {
+  const int nchunk = (int)((n + NH_ROWS - 1) / NH_ROWS);
+  hipLaunchKernelGGL(k_nh_resid_partial, dim3((m + 255) / 256, nchunk), dim3(256), 0, s, n, m, AX, BX, lam,
+                     conj_lam ? 1 : 0, R, part);
+  hipLaunchKernelGGL(k_nh_resid_final, dim3((m + 255) / 256), dim3(256), 0, s, m, nchunk, part, rn2, bn2);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// dst = conj(src), count elements
+__global__ void k_conj(int64_t count, const c64* __restrict__ src, c64* __restrict__ dst) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = conj(src[e]);
+}
+
+// dst (rows x k) = src[:, 0:k] with the leading dimension changed
+__global__ void k_take_cols(int rows, int k, const c64* __restrict__ src, int lds, c64* __restrict__ dst) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (c >= k) return;
+  dst[(int64_t)i * k + c] = src[(int64_t)i * lds + c];
+}
+
+// ---------------------------------------------------------------------------
+// The reduced non-Hermitian pencil in one workgroup (m <= NH_MAX_M0).
+__device__ inline double cabs(c64 a) { return hypot(a.re, a.im); }
+
+__device__ inline c64 csqrt(c64 z) {
+  const double r = cabs(z);
+  if (r == 0.0) return c64(0.0, 0.0);
+  if (z.re >= 0.0) {
+    const double t = sqrt(0.5 * (r + z.re));
+    return c64(t, z.im / (2.0 * t));
+  }
+  const double t = sqrt(0.5 * (r - z.re));
+  return c64(fabs(z.im) / (2.0 * t), copysign(t, z.im));
+}
+
+// block-wide max of v with its index (lowest index on ties); red arrays of NH_THREADS
+__device__ inline int block_argmax(double v, int idx, double* red_v, int* red_i) {
+  const int tid = threadIdx.x;
+  red_v[tid] = v;
+  red_i[tid] = idx;
+  __syncthreads();
+  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = red_v[tid + s];
+      const int oi = red_i[tid + s];
+      if (o > red_v[tid] || (o == red_v[tid] && oi >= 0 && (red_i[tid] < 0 || oi < red_i[tid]))) {
+        red_v[tid] = o;
+        red_i[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int r = red_i[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_sum(double v, double* red_v) {
+  const int tid = threadIdx.x;
+  red_v[tid] = v;
+  __syncthreads();
+  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) red_v[tid] += red_v[tid + s];
+    __syncthreads();
+  }
+  const double r = red_v[0];
+  __syncthreads();
+  return r;
+}
+
+// Aq, Bq: m x m row-major.  Outputs lam[m], W (right eigenvectors of the pencil, columns,
+// unit 2-norm) and, with two != 0, WL (left eigenvectors, wl_j^H Bq w_j = 1).
+// Work: G (m x 3m), H, Z, V, U (m x m each).  flag: 1 Bq singular, 2 no convergence.
+__global__ __launch_bounds__(NH_THREADS) void k_nh_eig(int m, const c64* __restrict__ Aq,
+                                                       const c64* __restrict__ Bq, int two, c64* __restrict__ G,
+                                                       c64* __restrict__ H, c64* __restrict__ Z,
+                                                       c64* __restrict__ V, c64* __restrict__ U,
+                                                       c64* __restrict__ lam, c64* __restrict__ W,
+                                                       c64* __restrict__ WL, int* __restrict__ flag) {
+  __shared__ double red_v[NH_THREADS];
+  __shared__ int red_i[NH_THREADS];
+  __shared__ c64 vec[NH_MAX_M0];
+  __shared__ c64 s_cs[2];
+  __shared__ int s_ctl[4];
+  const int tid = threadIdx.x;
+  const int m3 = 3 * m;
+  const double eps = 2.220446049250313e-16;
+  if (tid == 0) *flag = 0;
+  // ---- 1. Gauss-Jordan with partial pivoting on [Bq | Aq | I]: G = [I | Bq^-1 Aq | Bq^-1]
+  for (int64_t e = tid; e < (int64_t)m * m3; e += NH_THREADS) {
+    const int i = (int)(e / m3), c = (int)(e % m3);
+    G[e] = c < m ? Bq[(int64_t)i * m + c] : (c < 2 * m ? Aq[(int64_t)i * m + c - m] : c64(c - 2 * m == i ? 1.0 : 0.0, 0.0));
+  }
+  __syncthreads();
+  double gmax = 0.0;
+  for (int k = 0; k < m; ++k) {
+    double best = -1.0;
+    int bi = -1;
+    for (int i = k + tid; i < m; i += NH_THREADS) {
+      const double a = cabs(G[(int64_t)i * m3 + k]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    const int p = block_argmax(best, bi, red_v, red_i);
+    const c64 pv = G[(int64_t)p * m3 + k];
+    const double pa = cabs(pv);
+    gmax = fmax(gmax, pa);
+    if (!(pa > 1e-300) || pa < 1e-15 * gmax) {
+      if (tid == 0) *flag = 1;
+      return;
+    }
+    if (p != k)
+      for (int c = tid; c < m3; c += NH_THREADS) {
+        const c64 t = G[(int64_t)k * m3 + c];
+        G[(int64_t)k * m3 + c] = G[(int64_t)p * m3 + c];
+        G[(int64_t)p * m3 + c] = t;
+      }
+    __syncthreads();
+    const c64 inv = cdiv(c64(1.0, 0.0), pv);
+    for (int c = tid; c < m3; c += NH_THREADS) G[(int64_t)k * m3 + c] = inv * G[(int64_t)k * m3 + c];
+    for (int i = tid; i < m; i += NH_THREADS) vec[i] = G[(int64_t)i * m3 + k];
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)m * m3; e += NH_THREADS) {
+      const int i = (int)(e / m3), c = (int)(e % m3);
+      if (i != k) G[e] = G[e] - vec[i] * G[(int64_t)k * m3 + c];
+    }
+    __syncthreads();
+  }
+  // ---- 2. H = Bq^-1 Aq, Z = I; Householder reduction to upper Hessenberg form
+  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+    const int i = (int)(e / m), c = (int)(e % m);
+    H[e] = G[(int64_t)i * m3 + m + c];
+    Z[e] = c64(i == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    double part = 0.0;
+    for (int i = k + 1 + tid; i < m; i += NH_THREADS) part += norm2(H[(int64_t)i * m + k]);
+    const double xn2 = block_sum(part, red_v);
+    if (xn2 == 0.0) continue;
+    const c64 x0 = H[(int64_t)(k + 1) * m + k];
+    const double ax0 = cabs(x0), xn = sqrt(xn2);
+    const c64 ph = ax0 > 0.0 ? c64(x0.re / ax0, x0.im / ax0) : c64(1.0, 0.0);
+    const c64 alpha = c64(-xn * ph.re, -xn * ph.im);
+    for (int i = k + 1 + tid; i < m; i += NH_THREADS) vec[i] = (i == k + 1) ? x0 - alpha : H[(int64_t)i * m + k];
+    const double vn2 = xn2 - ax0 * ax0 + norm2(x0 - alpha);
+    const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    __syncthreads();
+    // left: rows k+1.., columns k..m-1 (one thread per column)
+    for (int c = k + tid; c < m; c += NH_THREADS) {
+      c64 sc(0.0, 0.0);
+      for (int i = k + 1; i < m; ++i) sc = sc + conj(vec[i]) * H[(int64_t)i * m + c];
+      sc = beta * sc;
+      for (int i = k + 1; i < m; ++i) H[(int64_t)i * m + c] = H[(int64_t)i * m + c] - vec[i] * sc;
+    }
+    __syncthreads();
+    // right: all rows, columns k+1..m-1, of H and of Z (one thread per row)
+    for (int i = tid; i < m; i += NH_THREADS) {
+      c64 t(0.0, 0.0), tz(0.0, 0.0);
+      for (int c = k + 1; c < m; ++c) {
+        t = t + H[(int64_t)i * m + c] * vec[c];
+        tz = tz + Z[(int64_t)i * m + c] * vec[c];
+      }
+      t = beta * t;
+      tz = beta * tz;
+      for (int c = k + 1; c < m; ++c) {
+        H[(int64_t)i * m + c] = H[(int64_t)i * m + c] - t * conj(vec[c]);
+        Z[(int64_t)i * m + c] = Z[(int64_t)i * m + c] - tz * conj(vec[c]);
+      }
+    }
+    __syncthreads();
+    for (int i = k + 2 + tid; i < m; i += NH_THREADS) H[(int64_t)i * m + k] = c64(0.0, 0.0);
+    if (tid == 0) H[(int64_t)(k + 1) * m + k] = alpha;
+    __syncthreads();
+  }
+  // ---- 3. shifted QR (Wilkinson shifts, Givens rotations) to the Schur form T = Z^H C Z
+  int hi = m - 1, its = 0, total = 0;
+  while (hi >= 1) {
+    if (tid == 0) {
+      int l = hi;
+      for (; l >= 1; --l) {
+        const double sub = cabs(H[(int64_t)l * m + l - 1]);
+        const double dsum = cabs(H[(int64_t)l * m + l]) + cabs(H[(int64_t)(l - 1) * m + l - 1]);
+        if (sub <= eps * dsum || sub < 1e-300) break;
+      }
+      if (l >= 1) H[(int64_t)l * m + l - 1] = c64(0.0, 0.0);
+      s_ctl[0] = (l < 1) ? 0 : l;
+    }
+    __syncthreads();
+    const int lo = s_ctl[0];
+    __syncthreads();
+    if (lo == hi) {
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (++total > 40 * m) {
+      if (tid == 0) *flag = 2;
+      return;
+    }
+    ++its;
+    if (tid == 0) {
+      c64 mu;
+      const c64 a = H[(int64_t)(hi - 1) * m + hi - 1], b = H[(int64_t)(hi - 1) * m + hi];
+      const c64 c = H[(int64_t)hi * m + hi - 1], d = H[(int64_t)hi * m + hi];
+      if (its % 11 == 10) {
+        // exceptional shift after a run of slow iterations
+        mu = d + c64(0.75 * cabs(c), 0.0);
+      } else {
+        const c64 half(0.5 * (a.re - d.re), 0.5 * (a.im - d.im));
+        const c64 disc = csqrt(half * half + b * c);
+        const c64 m1 = c64(0.5 * (a.re + d.re), 0.5 * (a.im + d.im)) + disc;
+        const c64 m2 = c64(0.5 * (a.re + d.re), 0.5 * (a.im + d.im)) - disc;
+        mu = cabs(m1 - d) <= cabs(m2 - d) ? m1 : m2;
+      }
+      s_cs[0] = H[(int64_t)lo * m + lo] - mu;  // x
+      s_cs[1] = H[(int64_t)(lo + 1) * m + lo];  // y
+    }
+    __syncthreads();
+    for (int k = lo; k < hi; ++k) {
+      __shared__ double s_c;
+      __shared__ c64 s_s;
+      if (tid == 0) {
+        const c64 x = s_cs[0], y = s_cs[1];
+        const double ax = cabs(x), ay = cabs(y);
+        double cc;
+        c64 ss;
+        if (ay == 0.0) {
+          cc = 1.0;
+          ss = c64(0.0, 0.0);
+        } else if (ax == 0.0) {
+          cc = 0.0;
+          ss = c64(y.re / ay, -y.im / ay);
+        } else {
+          const double rr = hypot(ax, ay);
+          cc = ax / rr;
+          ss = c64(x.re / ax, x.im / ax) * c64(y.re / rr, -y.im / rr);
+        }
+        s_c = cc;
+        s_s = ss;
+      }
+      __syncthreads();
+      const double cc = s_c;
+      const c64 ss = s_s;
+      // rows k, k+1 from the left: G = [c s; -conj(s) c]
+      const int c0 = (k == lo) ? lo : k - 1;
+      for (int j = c0 + tid; j < m; j += NH_THREADS) {
+        const c64 a = H[(int64_t)k * m + j], b = H[(int64_t)(k + 1) * m + j];
+        H[(int64_t)k * m + j] = cc * a + ss * b;
+        H[(int64_t)(k + 1) * m + j] = cc * b - conj(ss) * a;
+      }
+      __syncthreads();
+      // columns k, k+1 from the right by G^H, rows 0..min(k+2, hi); and Z
+      const int rmax = (k + 2 < hi) ? k + 2 : hi;
+      for (int i = tid; i < m; i += NH_THREADS) {
+        if (i <= rmax) {
+          const c64 a = H[(int64_t)i * m + k], b = H[(int64_t)i * m + k + 1];
+          H[(int64_t)i * m + k] = cc * a + conj(ss) * b;
+          H[(int64_t)i * m + k + 1] = cc * b - ss * a;
+        }
+        const c64 za = Z[(int64_t)i * m + k], zb = Z[(int64_t)i * m + k + 1];
+        Z[(int64_t)i * m + k] = cc * za + conj(ss) * zb;
+        Z[(int64_t)i * m + k + 1] = cc * zb - ss * za;
+      }
+      __syncthreads();
+      if (tid == 0 && k + 1 < hi) {
+        s_cs[0] = H[(int64_t)(k + 1) * m + k];
+        s_cs[1] = H[(int64_t)(k + 2) * m + k];
+      }
+      __syncthreads();
+    }
+  }
+  // ---- 4. eigenvectors of the triangular T: right (V, upper) and left (U, lower)
+  double tnorm = 0.0;
+  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+    const int i = (int)(e / m), c = (int)(e % m);
+    if (c >= i) tnorm = fmax(tnorm, cabs(H[e]));
+  }
+  red_v[tid] = tnorm;
+  __syncthreads();
+  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) red_v[tid] = fmax(red_v[tid], red_v[tid + s]);
+    __syncthreads();
+  }
+  const double small = fmax(eps * red_v[0], 1e-300);
+  __syncthreads();
+  for (int i = tid; i < m; i += NH_THREADS) {
+    const c64 li = H[(int64_t)i * m + i];
+    lam[i] = li;
+    for (int k = m - 1; k > i; --k) V[(int64_t)k * m + i] = c64(0.0, 0.0);
+    V[(int64_t)i * m + i] = c64(1.0, 0.0);
+    for (int k = i - 1; k >= 0; --k) {
+      c64 sacc(0.0, 0.0);
+      for (int l = k + 1; l <= i; ++l) sacc = sacc + H[(int64_t)k * m + l] * V[(int64_t)l * m + i];
+      c64 d = H[(int64_t)k * m + k] - li;
+      if (cabs(d) < small) d = c64(small, 0.0);
+      const c64 q = cdiv(sacc, d);
+      V[(int64_t)k * m + i] = c64(-q.re, -q.im);
+    }
+    if (two) {
+      // u^H (T - li I) = 0: conj(u_i) = 1, conj(u_k) = -sum_{l<k} conj(u_l) T[l][k] / (T[k][k] - li)
+      for (int k = 0; k < i; ++k) U[(int64_t)k * m + i] = c64(0.0, 0.0);
+      U[(int64_t)i * m + i] = c64(1.0, 0.0);
+      for (int k = i + 1; k < m; ++k) {
+        c64 sacc(0.0, 0.0);
+        for (int l = i; l < k; ++l) sacc = sacc + conj(U[(int64_t)l * m + i]) * H[(int64_t)l * m + k];
+        c64 d = H[(int64_t)k * m + k] - li;
+        if (cabs(d) < small) d = c64(small, 0.0);
+        const c64 q = cdiv(sacc, d);
+        U[(int64_t)k * m + i] = conj(c64(-q.re, -q.im));
+      }
+    }
+  }
+  __syncthreads();
+  // ---- 5. W = Z V; left: UC = Z U into H (free), WL = Binv^H UC
+  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    c64 acc(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) acc = acc + Z[(int64_t)i * m + k] * V[(int64_t)k * m + j];
+    W[e] = acc;
+  }
+  __syncthreads();
+  if (two) {
+    for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+      const int i = (int)(e / m), j = (int)(e % m);
+      c64 acc(0.0, 0.0);
+      for (int k = j; k < m; ++k) acc = acc + Z[(int64_t)i * m + k] * U[(int64_t)k * m + j];
+      H[e] = acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+      const int i = (int)(e / m), j = (int)(e % m);
+      c64 acc(0.0, 0.0);
+      for (int k = 0; k < m; ++k) acc = acc + conj(G[(int64_t)k * m3 + 2 * m + i]) * H[(int64_t)k * m + j];
+      WL[e] = acc;
+    }
+    __syncthreads();
+  }
+  // ---- 6. normalization: unit right vectors; wl_j^H Bq w_j = 1
+  for (int j = tid; j < m; j += NH_THREADS) {
+    double nn = 0.0;
+    for (int i = 0; i < m; ++i) nn += norm2(W[(int64_t)i * m + j]);
+    const double f = nn > 0.0 ? 1.0 / sqrt(nn) : 1.0;
+    for (int i = 0; i < m; ++i) W[(int64_t)i * m + j] = f * W[(int64_t)i * m + j];
+    if (two) {
+      c64 d(0.0, 0.0);
+      for (int i = 0; i < m; ++i) {
+        c64 t(0.0, 0.0);
+        for (int k = 0; k < m; ++k) t = t + Bq[(int64_t)i * m + k] * W[(int64_t)k * m + j];
+        d = d + conj(WL[(int64_t)i * m + j]) * t;
+      }
+      const c64 g = cabs(d) > 0.0 ? cdiv(c64(1.0, 0.0), conj(d)) : c64(1.0, 0.0);
+      for (int i = 0; i < m; ++i) WL[(int64_t)i * m + j] = WL[(int64_t)i * m + j] * g;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Orthonormal basis of the range of the n x m block Q (row-major): equilibrated Gram
+// matrix, Cholesky with column drops, then one Newton-Schulz pass; returns the kept count
+// and the m x kept transform T (Q T orthonormal).  Host-synchronizing (reads the drops).
+struct Orth {
+  c64 *S, *S2, *Linv, *H1, *V, *TG, *Tr;
+  double* d;
+  int* keep;
+  int* flag;
+  int* idx;
+  double* part;
+  double* bn;
+};
+
+int orthonormalize(hipStream_t s, int64_t n, int m, const c64* Q, Orth& o, int* h_keep, int* h_idx, double* h_scal,
+                   int& kept) {
+  MF_TRY(rm_gemm<c64>(s, m, m, (int)n, Q, m, true, true, Q, m, o.S, m));
+  MF_HIP_CHECK(hipMemsetAsync(o.flag, 0, 16, s));
+  const int tok = prof_begin(s);
+  MF_TRY(gram_equilibrate<c64>(s, m, o.S, o.S2, o.d, o.flag));
+  const double tau = 32.0 * m * 2.220446049250313e-16;
+  MF_TRY(chol_drop<c64>(s, m, o.S, o.Linv, o.keep, tau, o.TG));
+  prof_end(tok, s, K_ORTH, 0.0, 0.0);
+  MF_HIP_CHECK(hipMemcpyAsync(h_keep, o.keep, m * sizeof(int), hipMemcpyDeviceToHost, s));
+  MF_HIP_CHECK(hipMemcpyAsync(h_scal, o.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  MF_HIP_CHECK(hipStreamSynchronize(s));
+  int k = 0;
+  for (int i = 0; i < m; ++i)
+    if (h_keep[i]) h_idx[k++] = i;
+  kept = k;
+  if (k == 0) return 0;
+  MF_HIP_CHECK(hipMemcpyAsync(o.idx, h_idx, k * sizeof(int), hipMemcpyHostToDevice, s));
+  MF_TRY(build_h1<c64>(s, m, k, o.Linv, o.d, o.idx, o.H1));
+  // second pass: S1 = (Q H1)^H (Q H1) = H1^H (Q^H Q) H1, from the Gram matrix of Q
+  MF_TRY(rm_gemm<c64>(s, m, m, (int)n, Q, m, true, true, Q, m, o.S, m));
+  MF_TRY(rm_gemm<c64>(s, m, k, m, o.S, m, false, false, o.H1, k, o.TG, k));
+  MF_TRY(rm_gemm<c64>(s, k, k, m, o.H1, k, true, true, o.TG, k, o.S2, k));
+  MF_TRY(hermitian_part<c64>(s, k, o.S2));
+  MF_TRY(ns_invsqrt<c64>(s, k, o.S2, o.V, 3, o.TG));
+  MF_TRY(hermitian_part<c64>(s, k, o.V));
+  MF_TRY(rm_gemm<c64>(s, m, k, k, o.H1, k, false, false, o.V, k, o.Tr, k));
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+template <typename C>
+static int nh_run(mfeast_ctx* h, int64_t n, const c64* A, int64_t lda, const c64* B, int64_t ldb, int32_t* fpm,
+                  double* epsout, int32_t* loop, std::complex<double> emid, double r, int32_t* m0p, double* E,
+                  c64* Xu, int64_t ldx, int32_t* Mout, double* res_out, const std::vector<std::complex<double>>& z,
+                  const std::vector<std::complex<double>>& w) {
+  auto f = [&](int i) { return fpm[i - 1]; };
+  hipStream_t s = h->stream;
+  const int ne = (int)z.size();
+  const int m0in = *m0p;
+  int m0 = m0in;
+  const bool two = f(15) == 0;
+  const bool hasB = B != nullptr;
+  const double alpha = std::abs(emid) + r;
+  const double eps = std::pow(10.0, -f(3));
+  const int64_t ld = lu_ld(n);
+  const size_t szC = sizeof(C);
+  const size_t blk = (size_t)n * m0 * sizeof(c64);
+  const size_t sq = (size_t)m0 * m0 * sizeof(c64);
+  Timer total_t, ph;
+  total_t.start();
+  double t_fact = 0, t_solve = 0, t_ax = 0, t_bx = 0, t_eig = 0;
+
+  // ---- workspace
+  C* LU = (C*)h->ws(S_LU, (size_t)ne * n * ld * szC);
+  C* Dinv = (C*)h->ws(S_DINV, (size_t)ne * ((n + LU_NB - 1) / LU_NB) * 2 * LU_NB * LU_NB * szC);
+  C* Pinv = (C*)h->ws(S_PANINV, (size_t)ne * panel_inverse_entries(n) * szC);
+  int* ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
+  int* perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);
+  int* pinv = (int*)h->ws(S_PINV, (size_t)ne * n * 4);
+  int* linfo = (int*)h->ws(S_INFO, (size_t)ne * 4 + 64);
+  c64* zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
+  C* Wf = two ? (C*)h->ws(S_WF, (size_t)ne * n * m0 * szC) : nullptr;
+  C* Wc = (C*)h->ws(S_WC, (size_t)ne * n * m0 * szC);
+  C* Wy = (C*)h->ws(S_WY, (size_t)ne * n * m0 * szC);
+  SolveSide<C> side{};
+  bool two_streams = false;
+  if (two && h->ensure_aux()) {
+    C* Wy2 = (C*)h->ws(S_WY2, (size_t)ne * n * m0 * szC);
+    if (!Wy2) return -2;
+    side = SolveSide<C>{h->aux, h->ev_fork, h->ev_join, Wy2};
+    two_streams = true;
+  }
+  c64* X = (c64*)h->ws(S_X, blk);
+  c64* XL = (c64*)h->ws(S_NH_XL, blk);
+  c64* Q = (c64*)h->ws(S_Q, blk);
+  c64* QL = (c64*)h->ws(S_NH_QL, blk);
+  c64* R = (c64*)h->ws(S_R, blk);
+  c64* RL = (c64*)h->ws(S_NH_RL, blk);
+  c64* AQ = (c64*)h->ws(S_AQ, blk);
+  c64* BQ = hasB ? (c64*)h->ws(S_BQ, blk) : nullptr;
+  c64* AhQ = two ? (c64*)h->ws(S_NH_AHQ, blk) : nullptr;
+  c64* BhQ = (two && hasB) ? (c64*)h->ws(S_NH_BHQ, blk) : nullptr;
+  c64* Qo = (c64*)h->ws(S_AX, blk);
+  c64* QLo = two ? (c64*)h->ws(S_NH_QLO, blk) : nullptr;
+  c64* AQo = (c64*)h->ws(S_BX, blk);
+  c64* BQo = hasB ? (c64*)h->ws(S_NH_BQO, blk) : nullptr;
+  c64* AhQo = two ? (c64*)h->ws(S_NH_AHQO, blk) : nullptr;
+  c64* BhQo = (two && hasB) ? (c64*)h->ws(S_NH_BHQO, blk) : nullptr;
+  c64* T3 = (c64*)h->ws(S_NH_T3, blk);  // A X, then A^H Y
+  c64* T4 = (c64*)h->ws(S_NH_T4, blk);  // B X, then B^H Y
+  c64* Aq = (c64*)h->ws(S_S, sq);
+  c64* Bq = (c64*)h->ws(S_T, sq);
+  c64* Wr = (c64*)h->ws(S_W, sq);
+  c64* Wl = (c64*)h->ws(S_NH_WL, sq);
+  c64* Gw = (c64*)h->ws(S_HW, 3 * sq);
+  c64* Hw = (c64*)h->ws(S_V, sq);
+  c64* Zw = (c64*)h->ws(S_G, sq);
+  c64* Vw = (c64*)h->ws(S_C, sq);
+  c64* Uw = (c64*)h->ws(S_Z2, sq);
+  Orth orr{}, orl{};
+  orr.S = (c64*)h->ws(S_NH_O1, sq);
+  orr.S2 = (c64*)h->ws(S_NH_O2, sq);
+  orr.Linv = (c64*)h->ws(S_NH_O3, sq);
+  orr.H1 = (c64*)h->ws(S_NH_O4, sq);
+  orr.V = (c64*)h->ws(S_NH_O5, sq);
+  orr.TG = (c64*)h->ws(S_TG, std::max(3 * sq, (size_t)m0 * 32 * sizeof(c64)));
+  orr.Tr = (c64*)h->ws(S_NH_TR, sq);
+  orl = orr;
+  orl.Tr = (c64*)h->ws(S_NH_TL, sq);
+  const size_t nsmall = (size_t)m0 * 24 + (size_t)ne * m0 * 8 + 256;
+  double* small = (double*)h->ws(S_SMALL, nsmall * sizeof(double));
+  const int nchunk = (int)((n + 255) / 256);
+  double* part = (double*)h->ws(S_PART, (size_t)nchunk * m0 * 2 * sizeof(double) + 64);
+  char* hp = h->host(nsmall * sizeof(double) + 4096);
+  if (!LU || !Dinv || !Pinv || !ipiv || !perm || !pinv || !linfo || !zdev || (two && !Wf) || !Wc || !Wy || !X ||
+      !XL || !Q || !QL || !R || !RL || !AQ || (hasB && !BQ) || (two && !AhQ) || (two && hasB && !BhQ) || !Qo ||
+      (two && !QLo) || !AQo || (hasB && !BQo) || (two && !AhQo) || (two && hasB && !BhQo) || !T3 || !T4 || !Aq ||
+      !Bq || !Wr || !Wl || !Gw || !Hw || !Zw || !Vw || !Uw || !orr.S || !orr.S2 || !orr.Linv || !orr.H1 ||
+      !orr.V || !orr.TG || !orr.Tr || !orl.Tr || !small || !part || !hp)
+    return -2;
+  // small device arrays and their pinned host mirrors (same offsets)
+  auto dsl = [&](size_t off) { return small + off; };
+  auto hsl = [&](size_t off) { return reinterpret_cast<double*>(hp) + off; };
+  const size_t o_cs = 0, o_csl = m0, o_us = 2 * m0, o_usl = 3 * m0, o_rn = 4 * m0, o_bn = 5 * m0, o_rnl = 6 * m0,
+               o_bnl = 7 * m0, o_lam = 8 * m0 /* 2 m0 */, o_rho = 10 * m0 /* 2 m0 */, o_keep = 12 * m0,
+               o_idx = 13 * m0, o_keepl = 14 * m0, o_idxl = 15 * m0, o_d = 16 * m0, o_dl = 17 * m0,
+               o_flag = 18 * m0, o_perm = 19 * m0, o_cR = 24 * (size_t)m0 /* 2 ne m0 */,
+               o_cL = 24 * (size_t)m0 + 2 * (size_t)ne * m0 /* 2 ne m0 */;
+  orr.d = dsl(o_d);
+  orl.d = dsl(o_dl);
+  orr.keep = (int*)dsl(o_keep);
+  orl.keep = (int*)dsl(o_keepl);
+  orr.idx = (int*)dsl(o_idx);
+  orl.idx = (int*)dsl(o_idxl);
+  orr.flag = orl.flag = (int*)dsl(o_flag);
+  orr.part = orl.part = part;
+  c64* d_lam = reinterpret_cast<c64*>(dsl(o_lam));
+  c64* h_lam = reinterpret_cast<c64*>(hsl(o_lam));
+  c64* d_rho = reinterpret_cast<c64*>(dsl(o_rho));
+  c64* h_rho = reinterpret_cast<c64*>(hsl(o_rho));
+  c64* d_cR = reinterpret_cast<c64*>(dsl(o_cR));
+  c64* h_cR = reinterpret_cast<c64*>(hsl(o_cR));
+  c64* d_cL = reinterpret_cast<c64*>(dsl(o_cL));
+  c64* h_cL = reinterpret_cast<c64*>(hsl(o_cL));
+  int* d_flag = (int*)dsl(o_flag);
+  int* h_flag = (int*)hsl(o_flag);
+
+  // ---- factorizations F_j = (z_j B - A)^H: the shift-form kernel reads a column-major
+  //      matrix as its conjugate transpose, so it is given the conjugate nodes
+  ph.start();
+  {
+    std::vector<c64> zc(ne);
+    for (int j = 0; j < ne; ++j) zc[j] = c64(z[j].real(), -z[j].imag());
+    MF_HIP_CHECK(hipMemcpyAsync(zdev, zc.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
+    int tok = prof_begin(s);
+    MF_TRY(shift_form<c64, C>(s, n, A, lda, B, ldb, zdev, ne, LU, perm));
+    prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((hasB ? 2.0 : 1.0) * sizeof(c64) + ne * szC));
+    MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
+    tok = prof_begin(s);
+    MF_TRY(panel_inverses<C>(s, n, ne, LU, Dinv, Pinv));
+    prof_end(tok, s, K_LU_ROWS, 0.0, 0.0);
+    std::vector<int> hi(ne);
+    MF_HIP_CHECK(hipMemcpyAsync(hi.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < ne; ++j)
+      if (hi[j] != 0) return -2;
+  }
+  t_fact += ph.stop();
+
+  // ---- starting blocks (row-major n x m0)
+  if (f(5) == 1) {
+    MF_TRY(copy_cm_to_rm<c64>(s, n, m0, Xu, ldx, X, m0));
+    if (two) MF_TRY(copy_cm_to_rm<c64>(s, n, m0, Xu + (int64_t)m0in * ldx, ldx, XL, m0));
+  } else {
+    MF_TRY(random_block<c64>(s, n, m0, (uint64_t)(uint32_t)f(51), X, m0));
+    if (two) MF_TRY(random_block<c64>(s, n, m0, (uint64_t)(uint32_t)(f(51) + 1), XL, m0));
+  }
+
+  auto prod = [&](const c64* Mat, int64_t ldm, bool herm, int m, const c64* Xi, c64* Yo) -> int {
+    // Yo = op(Mat) Xi with Mat column-major (element (i, k) at Mat[i + k ldm]): for op = N
+    // the rows of Mat are read M-contiguous; Mat^H Xi = conj(Mat^T conj(Xi)), with Mat^T the
+    // row-major view as stored (T3 holds conj(Xi))
+    if (!herm) return rm_gemm<c64>(s, (int)n, m, (int)n, Mat, ldm, true, false, Xi, m, Yo, m);
+    const int64_t cnt = n * (int64_t)m;
+    hipLaunchKernelGGL(k_conj, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, Xi, T3);
+    MF_TRY(rm_gemm<c64>(s, (int)n, m, (int)n, Mat, ldm, false, false, T3, m, Yo, m));
+    hipLaunchKernelGGL(k_conj, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, Yo, Yo);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  };
+
+  std::vector<std::complex<double>> lam;
+  std::vector<double> resR, resL;
+  std::vector<int> order;
+  double trace_prev_re = 0.0, trace_prev_im = 0.0;
+  int info = 0, M = 0, k = 0;
+  for (;;) {
+    const bool resid = k > 0;
+    // ---- right-hand sides: B Y, B^H Y~ (first contour) or the residuals R, R~
+    const c64* rhsR = R;
+    const c64* rhsL = RL;
+    if (!resid) {
+      ph.start();
+      if (hasB) {
+        MF_TRY(prod(B, ldb, false, m0, X, R));
+        if (two) MF_TRY(prod(B, ldb, true, m0, XL, RL));
+      } else {
+        rhsR = X;
+        rhsL = XL;
+      }
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      t_bx += ph.stop();
+    }
+    ph.start();
+    MF_TRY(col_absmax<c64>(s, n, m0, rhsR, m0, dsl(o_rn)));
+    if (two) MF_TRY(col_absmax<c64>(s, n, m0, rhsL, m0, dsl(o_rnl)));
+    MF_HIP_CHECK(hipMemcpyAsync(hsl(o_rn), dsl(o_rn), m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(hsl(o_rnl), dsl(o_rnl), m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < m0; ++c) {
+      const double a = hsl(o_rn)[c], b = two ? hsl(o_rnl)[c] : 1.0;
+      if (!std::isfinite(a) || !std::isfinite(b)) return -2;
+      hsl(o_cs)[c] = a > 0.0 ? 1.0 / a : 1.0;
+      hsl(o_us)[c] = a > 0.0 ? a : 1.0;
+      hsl(o_csl)[c] = b > 0.0 ? 1.0 / b : 1.0;
+      hsl(o_usl)[c] = b > 0.0 ? b : 1.0;
+      std::complex<double> rho(0.0, 0.0);
+      for (int j = 0; j < ne; ++j) {
+        std::complex<double> cr = w[j];
+        if (resid) cr = w[j] / (z[j] - lam[c]);
+        rho += cr;
+        const std::complex<double> cl = std::conj(cr);
+        h_cR[(size_t)j * m0 + c] = c64(cr.real(), cr.imag());
+        h_cL[(size_t)j * m0 + c] = c64(cl.real(), cl.imag());
+      }
+      h_rho[c] = c64(rho.real(), rho.imag());
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(dsl(o_cs), hsl(o_cs), 4 * (size_t)m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_rho, h_rho, m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_cR, h_cR, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_cL, h_cL, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    {
+      int tok = prof_begin(s);
+      dim3 grid((unsigned)((m0 + 255) / 256), (unsigned)n);
+      hipLaunchKernelGGL((k_rhs_two<C>), grid, dim3(256), 0, s, n, m0, rhsR, rhsL, dsl(o_cs), dsl(o_csl), ne, perm,
+                         two ? Wf : (C*)nullptr, Wc);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * m0 * (two ? 2.0 : 1.0) * (16.0 + ne * szC));
+      // right: conjugate-transpose sweeps of F_j (Wc); left: forward sweeps (Wf)
+      MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Pinv, two ? Wf : (C*)nullptr, Wc, Wy, two_streams ? &side : nullptr));
+      tok = prof_begin(s);
+      hipLaunchKernelGGL((k_accumulate_two<C>), grid, dim3(256), 0, s, n, m0, ne, two ? Wf : (C*)nullptr, Wc, pinv,
+                         d_cR, d_cL, d_rho, dsl(o_us), dsl(o_usl), X, XL, Q, QL, resid ? 1 : 0);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * m0 * (two ? 2.0 : 1.0) * (ne * szC + 32.0));
+    }
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_solve += ph.stop();
+
+    // ---- Rayleigh-Ritz: products with A, B (and A^H, B^H) on the raw blocks
+    ph.start();
+    MF_TRY(prod(A, lda, false, m0, Q, AQ));
+    if (two) MF_TRY(prod(A, lda, true, m0, QL, AhQ));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_ax += ph.stop();
+    if (hasB) {
+      ph.start();
+      MF_TRY(prod(B, ldb, false, m0, Q, BQ));
+      if (two) MF_TRY(prod(B, ldb, true, m0, QL, BhQ));
+      MF_HIP_CHECK(hipStreamSynchronize(s));
+      t_bx += ph.stop();
+    }
+    ph.start();
+    int kr = 0, kl = 0;
+    MF_TRY(orthonormalize(s, n, m0, Q, orr, (int*)hsl(o_keep), (int*)hsl(o_idx), hsl(o_flag), kr));
+    if (h_flag[0] != 0 || kr == 0) { info = -3; break; }
+    if (two) {
+      MF_TRY(orthonormalize(s, n, m0, QL, orl, (int*)hsl(o_keepl), (int*)hsl(o_idxl), hsl(o_flag), kl));
+      if (h_flag[0] != 0 || kl == 0) { info = -3; break; }
+    } else {
+      kl = kr;
+    }
+    const int kk = std::min(kr, kl);
+    // transforms restricted to the first kk kept columns (m0 x kk)
+    c64* Tr = orr.Tr;
+    c64* Tl = two ? orl.Tr : orr.Tr;
+    if (kk < kr) {
+      hipLaunchKernelGGL(k_take_cols, dim3((kk + 255) / 256, m0), dim3(256), 0, s, m0, kk, orr.Tr, kr, orr.S2);
+      Tr = orr.S2;
+    }
+    if (two && kk < kl) {
+      hipLaunchKernelGGL(k_take_cols, dim3((kk + 255) / 256, m0), dim3(256), 0, s, m0, kk, orl.Tr, kl, orl.H1);
+      Tl = orl.H1;
+    }
+    const int krs = (kk < kr) ? kk : kr, kls = (two && kk < kl) ? kk : kl;
+    (void)krs;
+    (void)kls;
+    // Qo = Q Tr, A Qo, B Qo; QLo = QL Tl, A^H QLo, B^H QLo  (n x kk, leading dimension kk)
+    MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, Q, m0, false, false, Tr, kk, Qo, kk));
+    MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, AQ, m0, false, false, Tr, kk, AQo, kk));
+    if (hasB) MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, BQ, m0, false, false, Tr, kk, BQo, kk));
+    const c64* QLx = Qo;
+    if (two) {
+      MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, QL, m0, false, false, Tl, kk, QLo, kk));
+      MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, AhQ, m0, false, false, Tl, kk, AhQo, kk));
+      if (hasB) MF_TRY(rm_gemm<c64>(s, (int)n, kk, m0, BhQ, m0, false, false, Tl, kk, BhQo, kk));
+      QLx = QLo;
+    }
+    // reduced pencil Aq = QLo^H A Qo, Bq = QLo^H B Qo
+    MF_TRY(rm_gemm<c64>(s, kk, kk, (int)n, QLx, kk, true, true, AQo, kk, Aq, kk));
+    MF_TRY(rm_gemm<c64>(s, kk, kk, (int)n, QLx, kk, true, true, hasB ? BQo : Qo, kk, Bq, kk));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    ph.start();
+    {
+      const int tok = prof_begin(s);
+      hipLaunchKernelGGL(k_nh_eig, dim3(1), dim3(NH_THREADS), 0, s, kk, Aq, Bq, two ? 1 : 0, Gw, Hw, Zw, Vw, Uw,
+                         d_lam, Wr, Wl, d_flag);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_EIG, 0.0, 0.0);
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(h_lam, d_lam, kk * sizeof(c64), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    if (h_flag[0] != 0) { info = -3; break; }
+    m0 = kk;
+    lam.resize(m0);
+    bool finite = true;
+    for (int c = 0; c < m0; ++c) {
+      lam[c] = std::complex<double>(h_lam[c].re, h_lam[c].im);
+      if (!std::isfinite(lam[c].real()) || !std::isfinite(lam[c].imag())) finite = false;
+    }
+    if (!finite) { info = -3; break; }
+    // ---- Ritz vectors and residuals
+    ph.start();
+    MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, Qo, m0, false, false, Wr, m0, X, m0));
+    MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, AQo, m0, false, false, Wr, m0, T3, m0));
+    const c64* BX = X;
+    if (hasB) {
+      MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, BQo, m0, false, false, Wr, m0, T4, m0));
+      BX = T4;
+    }
+    {
+      const int tok = prof_begin(s);
+      MF_TRY(nh_resid(s, n, m0, T3, BX, d_lam, false, R, dsl(o_rn), dsl(o_bn), part));
+      prof_end(tok, s, K_RESID, 0.0, (double)n * m0 * 48.0);
+    }
+    if (two) {
+      MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, QLo, m0, false, false, Wl, m0, XL, m0));
+      MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, AhQo, m0, false, false, Wl, m0, T3, m0));
+      const c64* BhY = XL;
+      if (hasB) {
+        MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, BhQo, m0, false, false, Wl, m0, T4, m0));
+        BhY = T4;
+      }
+      const int tok = prof_begin(s);
+      MF_TRY(nh_resid(s, n, m0, T3, BhY, d_lam, true, RL, dsl(o_rnl), dsl(o_bnl), part));
+      prof_end(tok, s, K_RESID, 0.0, (double)n * m0 * 48.0);
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(hsl(o_rn), dsl(o_rn), 4 * (size_t)m0in * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    resR.assign(m0, 0.0);
+    resL.assign(m0, 0.0);
+    bool fin = true;
+    for (int c = 0; c < m0; ++c) {
+      resR[c] = std::sqrt(hsl(o_rn)[c]) / (alpha * std::sqrt(hsl(o_bn)[c]));
+      if (two) resL[c] = std::sqrt(hsl(o_rnl)[c]) / (alpha * std::sqrt(hsl(o_bnl)[c]));
+      if (!std::isfinite(resR[c]) || !std::isfinite(resL[c])) fin = false;
+    }
+    if (!fin) { info = -2; break; }
+    // ---- count, order (inside first, each by real then imaginary part), trace, stop
+    std::vector<char> in(m0);
+    M = 0;
+    for (int c = 0; c < m0; ++c) {
+      in[c] = inside_ellipse(lam[c], emid, r, f(18), f(19)) ? 1 : 0;
+      M += in[c];
+    }
+    order.resize(m0);
+    for (int c = 0; c < m0; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (in[a] != in[b]) return in[a] > in[b];
+      if (lam[a].real() != lam[b].real()) return lam[a].real() < lam[b].real();
+      return lam[a].imag() < lam[b].imag();
+    });
+    double tr_re = 0.0, tr_im = 0.0, maxres = 0.0;
+    for (int q = 0; q < M; ++q) {
+      const int c = order[q];
+      tr_re += lam[c].real();
+      tr_im += lam[c].imag();
+      maxres = std::max(maxres, resR[c]);
+      if (two) maxres = std::max(maxres, resL[c]);
+    }
+    const double eo = (k == 0) ? 1.0 : std::hypot(tr_re - trace_prev_re, tr_im - trace_prev_im) / alpha;
+    trace_prev_re = tr_re;
+    trace_prev_im = tr_im;
+    *epsout = eo;
+    *loop = k;
+    *Mout = M;
+    if (f(1) != 0)
+      fprintf(stderr, "%3d %6d  %24.16E %24.16E  %24.16E  %24.16E  m0=%d\n", k, M, tr_re, tr_im, eo, maxres, m0);
+    if (M == 0) { info = 1; break; }
+    if (M >= m0) { info = 3; break; }
+    if ((f(6) == 1) ? (maxres < eps) : (eo < eps)) { info = 0; break; }
+    if (k >= f(4)) { info = 2; break; }
+    ++k;
+  }
+  if (info == 0 || info == 1 || info == 2 || info == 3) {
+    // eigenpairs to the caller's layout in the reported order: E complex (m0 values), X
+    // right vectors in columns 0..m0-1 and left vectors in columns m0in.., res right
+    // then left (at m0in)
+    std::vector<int> hperm(order.begin(), order.end());
+    int* d_perm = (int*)dsl(o_perm);
+    MF_HIP_CHECK(hipMemcpyAsync(d_perm, hperm.data(), m0 * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_TRY(copy_rm_to_cm<c64>(s, n, m0, X, m0, Xu, ldx, d_perm));
+    if (two) MF_TRY(copy_rm_to_cm<c64>(s, n, m0, XL, m0, Xu + (int64_t)m0in * ldx, ldx, d_perm));
+    std::vector<double> e_out(2 * (size_t)m0), r_out(two ? 2 * (size_t)m0in : (size_t)m0, 0.0);
+    for (int q = 0; q < m0; ++q) {
+      e_out[2 * q] = lam[order[q]].real();
+      e_out[2 * q + 1] = lam[order[q]].imag();
+      r_out[q] = resR[order[q]];
+      if (two) r_out[m0in + q] = resL[order[q]];
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(E, e_out.data(), e_out.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out.data(), r_out.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    *m0p = m0;
+  }
+  h->timing[0] = t_fact;
+  h->timing[1] = t_solve;
+  h->timing[2] = t_ax;
+  h->timing[3] = t_bx;
+  h->timing[5] = total_t.stop();
+  h->timing[4] = h->timing[5] - t_fact - t_solve - t_ax - t_bx;
+  h->timing[6] = (double)(*loop + 1);
+  h->timing[7] = t_eig;
+  return info;
+}
+
+static int check_general_fpm(const int32_t* fpm, bool expert) {
+  auto f = [&](int i) { return fpm[i - 1]; };
+  if (!expert) {
+    if (f(16) != 0 && f(16) != 1) return 116;
+    if (f(16) == 0 && !gauss_full_allowed(f(8))) return 108;
+    if (f(16) == 1 && f(8) < 2) return 108;
+    if (f(18) <= 0) return 118;
+    if (f(19) < -180 || f(19) > 180) return 119;
+  } else if (f(8) < 1) {
+    return 108;
+  }
+  if (f(3) < 0 || f(3) > 16) return 103;
+  if (f(4) < 0) return 104;
+  if (f(5) != 0 && f(5) != 1) return 105;
+  if (f(6) != 0 && f(6) != 1) return 106;
+  if (f(14) != 0) return 114;
+  if (f(15) != 0 && f(15) != 1) return 115;
+  if (f(42) != 0 && f(42) != 1) return 142;
+  if (f(53) != 0 && f(53) != 1) return 153;
+  return 0;
+}
+
+extern "C" {
+
+void mfeast_init_general(int32_t* fpm) {
+  if (fpm == nullptr) return;
+  mfeast_init(fpm);
+  fpm[14] = 0;    // fpm(15) two-sided: right and left eigenvectors
+  fpm[15] = 1;    // fpm(16) trapezoidal
+  fpm[17] = 100;  // fpm(18) circle
+}
+
+int mfeast_gcontour(double emid_re, double emid_im, double r, int32_t ne, int32_t rule, int32_t ratio_pct,
+                    int32_t angle_deg, double* zne, double* wne) {
+  if (!(r > 0.0)) return 200;
+  if (rule != 0 && rule != 1) return 116;
+  if ((rule == 0 && !gauss_full_allowed(ne)) || (rule == 1 && ne < 2)) return 108;
+  if (ratio_pct <= 0) return 118;
+  if (angle_deg < -180 || angle_deg > 180) return 119;
+  if (zne == nullptr) return -108;
+  if (wne == nullptr) return -109;
+  std::vector<std::complex<double>> z, w;
+  full_contour(std::complex<double>(emid_re, emid_im), r, ne, rule, ratio_pct, angle_deg, z, w);
+  for (int j = 0; j < ne; ++j) {
+    zne[2 * j] = z[j].real();
+    zne[2 * j + 1] = z[j].imag();
+    wne[2 * j] = w[j].real();
+    wne[2 * j + 1] = w[j].imag();
+  }
+  return 0;
+}
+
+int mfeast_zgegv(mfeast_handle h, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 int32_t* fpm, double* epsout, int32_t* loop, const double* emid, double r, int32_t* m0, double* E,
+                 double* X, int64_t ldx, int32_t* M, double* res, const double* zne, const double* wne) {
+  // argument positions: h 1, n 2, A 3, lda 4, B 5, ldb 6, fpm 7, epsout 8, loop 9, emid 10,
+  // r 11, m0 12, E 13, X 14, ldx 15, M 16, res 17, zne 18, wne 19
+  if (n < 1 || n > 16384) return 202;
+  if (m0 == nullptr) return -112;
+  if (*m0 < 1 || *m0 > n || *m0 > NH_MAX_M0) return 201;
+  if (emid == nullptr) return -110;
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(emid[0]) || !std::isfinite(emid[1])) return 200;
+  if (fpm == nullptr) return -107;
+  if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -118 : -119;
+  const int fi = check_general_fpm(fpm, zne != nullptr);
+  if (fi) return fi;
+  if (h == nullptr) return -101;
+  if (A == nullptr) return -103;
+  if (lda < n) return -104;
+  if (B != nullptr && ldb < n) return -106;
+  if (epsout == nullptr) return -108;
+  if (loop == nullptr) return -109;
+  if (E == nullptr) return -113;
+  if (X == nullptr) return -114;
+  if (ldx < n) return -115;
+  if (M == nullptr) return -116;
+  if (res == nullptr) return -117;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  GemmScratchScope scratch_scope(h);
+  const std::complex<double> em(emid[0], emid[1]);
+  std::vector<std::complex<double>> z, w;
+  const int ne = fpm[7];
+  if (zne != nullptr) {
+    z.resize(ne);
+    w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+      z[j] = std::complex<double>(zne[2 * j], zne[2 * j + 1]);
+      w[j] = std::complex<double>(wne[2 * j], wne[2 * j + 1]);
+    }
+  } else {
+    full_contour(em, r, ne, fpm[15], fpm[17], fpm[18], z, w);
+  }
+  set_gemm_3m(fpm[52] == 0);
+  prof_enable(fpm[51] == 1 || h->prof_all);
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
+  const c64* Ac = reinterpret_cast<const c64*>(A);
+  const c64* Bc = reinterpret_cast<const c64*>(B);
+  c64* Xc = reinterpret_cast<c64*>(X);
+  int info;
+  if (fpm[41] == 1)
+    info = nh_run<c32>(h, n, Ac, lda, Bc, ldb, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
+  else
+    info = nh_run<c64>(h, n, Ac, lda, Bc, ldb, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
+  if (prof_on()) {
+    (void)hipStreamSynchronize(h->stream);
+    prof_collect(h->prof);
+    prof_enable(false);
+  }
+  return info;
+}
+
+}  // extern "C"

@@ -271,7 +271,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
   // algorithmic work of one direction: 8 n^2 m flops per node (L and U sweeps)
   const double dir_flops = 8.0 * (double)n * n * m * ne;
   const double dir_bytes = (double)sizeof(C) * ne * ((double)n * n + 2.0 * n * m);
-  if (Wc != nullptr && side != nullptr) {
+  if (Wf != nullptr && Wc != nullptr && side != nullptr) {
     // both directions at once: they share only the factors, which they read; the
     // conjugate-transpose one runs on side->s2 with its own ping-pong buffer
     const int tok = prof_begin(s);
@@ -284,10 +284,13 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
     prof_end(tok, s, cls, 2.0 * dir_flops, 2.0 * dir_bytes);
     return 0;
   }
-  // forward direction: L (W -> Y) then U (Y -> W)
-  int tok = prof_begin(s);
-  if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
-  prof_end(tok, s, cls, dir_flops, dir_bytes);
+  // forward direction: L (W -> Y) then U (Y -> W); skipped when Wf is null
+  int tok;
+  if (Wf != nullptr) {
+    tok = prof_begin(s);
+    if (sweep(s, Wf, Y, false, false) || sweep(s, Y, Wf, true, false)) return -2;
+    prof_end(tok, s, cls, dir_flops, dir_bytes);
+  }
   if (Wc == nullptr) return 0;
   // conjugate-transpose direction: U^H (lower) then L^H (unit upper)
   tok = prof_begin(s);

@@ -195,3 +195,40 @@ def test_adjoint_argument_checks():
     assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 2, d, 4, None) == -112
     assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 0, None, 4, None) == -113
     assert f(h, 4, d, 4, 2, d, d, 4, None, None, 4, 0, d, 3, None) == -114
+
+
+@pytest.mark.parametrize("rule,ne,ratio,angle", [(1, 16, 100, 0), (1, 7, 60, -45), (0, 24, 100, 0), (0, 12, 40, 170)])
+def test_full_contour_matches_oracle(rule, ne, ratio, angle):
+    from oracle import nonhermitian as nh
+    info, z, w = mf.mfeast_gcontour(0.3 - 1.2j, 0.7, ne, rule, ratio, angle)
+    assert info == 0
+    zo, wo = nh.full_contour(0.3 - 1.2j, 0.7, ne, rule=rule, ratio_pct=ratio, angle_deg=angle)
+    np.testing.assert_allclose(z, zo, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(w, wo, rtol=0, atol=1e-14)
+
+
+def test_general_driver_argument_checks():
+    """mfeast_zgegv's host checks in Table tab_info order, with host dummies and a NULL
+    handle (no device pointer is dereferenced)."""
+    from oracle import nonhermitian as nh
+    dummy = np.zeros(8)
+
+    def call(n=10, m0=4, r=1.0, fpm=None, handle=None, lda=None, X=dummy, res=dummy, ldx=None):
+        f = nh.nfeastinit().astype(np.int32) if fpm is None else fpm
+        return mf.mfeast_zgegv(handle, n, dummy, lda or max(n, 1), None, max(n, 1), f, 0.0, r, m0, dummy, X,
+                               ldx or max(n, 1), res)["info"]
+    assert call(n=0) == 202
+    assert call(m0=0) == 201
+    assert call(m0=11) == 201
+    assert call(n=1000, m0=513) == 201
+    assert call(r=0.0) == 200
+    for idx, val, code in [(7, 1, 108), (15, 2, 116), (17, 0, 118), (18, 181, 119), (14, 2, 115), (13, 1, 114),
+                           (2, 17, 103), (3, -1, 104)]:
+        f = nh.nfeastinit().astype(np.int32)
+        f[idx] = val
+        assert call(fpm=f) == code, (idx, val)
+    assert call() == -101
+    assert call(handle=ctypes.c_void_p(1), lda=5) == -104
+    assert call(handle=ctypes.c_void_p(1), ldx=5) == -115
+    assert call(handle=ctypes.c_void_p(1), res=None) == -117
+    np.testing.assert_array_equal(mf.mfeast_init_general().astype(np.int64), nh.nfeastinit())
