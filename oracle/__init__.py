@@ -23,6 +23,7 @@ from .splitmix import splitmix64_uniform, initial_subspace
 from .ifeast import bicgstab_block, feast_csr, ifeastinit
 from . import adjoint
 from . import nonhermitian
+from . import polynomial
 from . import stochastic
 from .feast import (
     feastinit,
@@ -51,5 +52,6 @@ __all__ = [
     "ifeastinit",
     "adjoint",
     "nonhermitian",
+    "polynomial",
     "stochastic",
 ]

@@ -38,7 +38,12 @@ Readings where the guide is silent (listed with their reasons in the design note
               eigenvectors W, W~ of (Aq, Bq); one-sided (fpm(15)=1): Q~ = Q and only right
               vectors.  X = Q W with unit 2-norm columns; Y = Q~ W~ scaled so that
               y_i^H B x_i = 1.
-  R-inside    M = number of Ritz values inside the (closed) ellipse; no residual filter.
+  R-inside    M = number of found pairs: Ritz values inside the (closed) ellipse whose
+              relative residual (right, and left when two-sided) is below SPURIOUS_RES = 0.1;
+              spurious Ritz values of a projected non-normal problem can fall inside the
+              contour with residuals of order one (the Hermitian reading's first test).
+              info = 1 when no Ritz value lies inside, 3 when all do (whatever their
+              residuals); convergence needs at least one found pair.
   R-order     inside values first, then the others, each ascending by real part, then by
               imaginary part; X (and Y, res) follow E.
   R-conv      fpm(6)=1: max residual (right, and left when two-sided) over the inside
@@ -59,6 +64,7 @@ from .contour import gauss_legendre_rule
 from .splitmix import initial_subspace
 
 GAUSS_FULL_ALLOWED = tuple(range(2, 41)) + (48, 64, 80, 96, 112)
+SPURIOUS_RES = 1.0e-1
 
 
 def full_contour(emid, r, ne, rule=1, ratio_pct=100, angle_deg=0):
@@ -255,7 +261,12 @@ def feast_general(A, B, emid, r, m0, fpm=None, X0=None, zne=None, wne=None, form
             BhY = Bm.conj().T @ Yl
             Rl = A.conj().T @ Yl - BhY * np.conj(lam)[None, :]
             res_l = np.linalg.norm(Rl, axis=0) / (alpha * np.linalg.norm(BhY, axis=0))
-        inside = inside_ellipse(lam, emid, r, f(18), f(19))
+        ok = res < SPURIOUS_RES
+        if two:
+            ok = ok & (res_l < SPURIOUS_RES)
+        geo = inside_ellipse(lam, emid, r, f(18), f(19))
+        n_inside = int(np.sum(geo))
+        inside = geo & ok
         perm = _order(lam, inside)
         lam, X, res = lam[perm], X[:, perm], res[perm]
         if two:
@@ -273,13 +284,13 @@ def feast_general(A, B, emid, r, m0, fpm=None, X0=None, zne=None, wne=None, form
                                "E": lam[:M].copy()})
         out.update(E=lam, X=X, Y=Yl if two else None, M=M, res=res, res_left=res_l, epsout=epsout, loop=k,
                    m0=X.shape[1])
-        if M == 0:
+        if n_inside == 0:
             out["info"] = 1
             return out
-        if M >= X.shape[1]:
+        if n_inside >= X.shape[1]:
             out["info"] = 3
             return out
-        if (maxres < eps) if f(6) == 1 else (epsout < eps):
+        if M > 0 and ((maxres < eps) if f(6) == 1 else (epsout < eps)):
             out["info"] = 0
             return out
         if k >= f(4):

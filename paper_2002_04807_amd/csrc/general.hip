@@ -39,7 +39,7 @@ namespace {
 
 constexpr int NH_MAX_M0 = 512;  // the reduced eigensolver runs in one workgroup
 constexpr int NH_THREADS = 256;
-constexpr double NH_RANK_TOL = 1.0e-13;
+constexpr double NH_SPURIOUS_RES = 1.0e-1;
 
 // ---------------------------------------------------------------------------
 // full contour: z(theta) = emid + e^{i phi} (r cos theta + i e r sin theta), theta in
@@ -947,10 +947,16 @@ static int nh_run(mfeast_ctx* h, int64_t n, const c64* A, int64_t lda, const c64
     }
     if (!fin) { info = -2; break; }
     // ---- count, order (inside first, each by real then imaginary part), trace, stop
+    // found: inside the contour with residuals below NH_SPURIOUS_RES (spurious Ritz values
+    // of the projected non-normal problem may fall inside with residuals of order one)
     std::vector<char> in(m0);
     M = 0;
+    int n_inside = 0;
     for (int c = 0; c < m0; ++c) {
-      in[c] = inside_ellipse(lam[c], emid, r, f(18), f(19)) ? 1 : 0;
+      const bool geo = inside_ellipse(lam[c], emid, r, f(18), f(19));
+      const bool ok = resR[c] < NH_SPURIOUS_RES && (!two || resL[c] < NH_SPURIOUS_RES);
+      n_inside += geo ? 1 : 0;
+      in[c] = (geo && ok) ? 1 : 0;
       M += in[c];
     }
     order.resize(m0);
@@ -976,9 +982,9 @@ static int nh_run(mfeast_ctx* h, int64_t n, const c64* A, int64_t lda, const c64
     *Mout = M;
     if (f(1) != 0)
       fprintf(stderr, "%3d %6d  %24.16E %24.16E  %24.16E  %24.16E  m0=%d\n", k, M, tr_re, tr_im, eo, maxres, m0);
-    if (M == 0) { info = 1; break; }
-    if (M >= m0) { info = 3; break; }
-    if ((f(6) == 1) ? (maxres < eps) : (eo < eps)) { info = 0; break; }
+    if (n_inside == 0) { info = 1; break; }
+    if (n_inside >= m0) { info = 3; break; }
+    if (M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps))) { info = 0; break; }
     if (k >= f(4)) { info = 2; break; }
     ++k;
   }

@@ -178,3 +178,47 @@ def prescribed_nonnormal(n, seed, generalized=False, spread=2.0, coupling=0.3):
     Binv = np.eye(n) if B is None else np.linalg.inv(B)
     Y = (Vinv @ Binv).conj().T
     return A, B, lam, V, Y
+
+
+def prescribed_polynomial(n, p, seed, leading=False, spread=2.0, coupling=0.3):
+    """Matrix polynomial sum_k lambda^k A_k (k = 0..p) with known eigenpairs.
+
+    Draw order from default_rng(seed): for t = 1..p the spectrum D_t (real parts, then
+    imaginary parts, each U[-spread, spread]) and G_t for V_t = I + coupling G_t / sqrt(n);
+    then, with leading=True, C for L = I + 0.1 C C^H / n.  With S_t = V_t diag(D_t) V_t^-1,
+    P(lambda) = L (lambda I - S_p) ... (lambda I - S_1), expanded into the coefficients A_k
+    of lambda^k (L = I without leading).  Its eigenvalues are those of every S_t; for
+    lambda in eig(S_t) with eigenvector v of S_t, the right eigenvector is
+    x = (lambda I - S_1)^-1 ... (lambda I - S_(t-1))^-1 v.
+    Returns (As, lam (p n values, S_1's first), X (n x p n, unit columns))."""
+    rng = np.random.default_rng(seed)
+    S, D, Vs = [], [], []
+    for t in range(p):
+        d = rng.uniform(-spread, spread, n) + 1j * rng.uniform(-spread, spread, n)
+        G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+        V = np.eye(n) + coupling * G / np.sqrt(n)
+        S.append((V * d[None, :]) @ np.linalg.inv(V))
+        D.append(d)
+        Vs.append(V)
+    L = np.eye(n, dtype=np.complex128)
+    if leading:
+        C = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+        L = np.eye(n) + 0.1 * (C @ C.conj().T) / n
+    # coefficients of (lambda - S_p) ... (lambda - S_1), lowest degree first
+    coef = [np.eye(n, dtype=np.complex128)]
+    for t in range(p):
+        new = [np.zeros((n, n), dtype=np.complex128) for _ in range(len(coef) + 1)]
+        for k, Ck in enumerate(coef):
+            new[k + 1] += Ck
+            new[k] -= S[t] @ Ck
+        coef = new
+    As = [L @ Ck for Ck in coef]
+    lam, X = [], []
+    for t in range(p):
+        for i in range(n):
+            x = Vs[t][:, i].astype(np.complex128)
+            for u in range(t - 1, -1, -1):
+                x = np.linalg.solve(D[t][i] * np.eye(n) - S[u], x)
+            lam.append(D[t][i])
+            X.append(x / np.linalg.norm(x))
+    return As, np.array(lam), np.stack(X, axis=1)
