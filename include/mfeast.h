@@ -210,6 +210,39 @@ int mfeast_zgegv(mfeast_handle h, int64_t n, const double* A, int64_t lda, const
                  double* E, double* X, int64_t ldx, int32_t* M, double* res, const double* zne,
                  const double* wne);
 
+/* Defaults of the polynomial driver: mfeast_init_general, then fpm(15)=1 (right
+ * eigenvectors only, the one mode of Section 3.4's drivers). */
+void mfeast_init_polynomial(int32_t* fpm);
+
+/* Dense complex polynomial eigenvalue problem sum_{k=0..p} lambda^k A_k x = 0 (Section
+ * 3.4, zfeast_gepev / zfeast_sypev forms; real or symmetric coefficients are passed as
+ * general complex ones): the eigenvalues inside the full contour of Emid, r, fpm(18),
+ * fpm(19) with fpm(8) nodes (or the expert nodes zne, weights wne) and their right
+ * eigenvectors.  P(z_j) = sum_k z_j^k A_k is formed and factored once per node (RCI
+ * cases 10/11); the first iteration applies sum_j w_j P(z_j)^-1 to the starting block,
+ * later ones the residual form rho(lambda_i) x_i - sum_j w_j/(z_j - lambda_i)
+ * P(z_j)^-1 P(lambda_i) x_i.  Rayleigh-Ritz projects every A_k on an orthonormal,
+ * rank-truncated basis of the subspace and solves the companion linearization of the
+ * projected polynomial (size p m <= 512) on the device in one workgroup; of its p m
+ * eigenvalues the m nearest the contour's centre in the ellipse's own metric are kept.
+ * A pair is counted in M when its value lies inside the contour and its residual is
+ * below min(0.1, 10^(-fpm(3)/2)); info 3 when all m kept values lie inside (the p m values
+ * of the linearization crowd the subspace: about 1.5 times the count inside is enough
+ * for M0).  fpm(42)=1 factors and solves in complex FP32, fpm(42)=0 in FP64.
+ *  p       degree, 1 <= p <= 8
+ *  A       device, the p+1 complex column-major n x n matrices A_0..A_p, element (i, j)
+ *          of A_k at A[2*(i + j*lda + k*lda*n)] (re, im) (Table tab-spec3's A(LDA,N,p+1))
+ *  fpm     host, 64 int32 (fpm(15) must be 1)
+ *  m0      host, in: 1 <= M0 <= n with p*M0 <= 512; out: possibly reduced
+ *  E, X, M, epsout, loop, emid, r, zne, wne as for mfeast_zgegv (right eigenvectors only)
+ *  res     device, m0 doubles: ||P(lambda_i) x_i|| / sum_k |lambda_i|^k ||A_k x_i||
+ * Returns Table tab_info codes: 202 (n), 201 (M0), 200 (r or Emid), 115 (fpm(15) != 1),
+ * other 1xx (fpm(i)), -102 (p), -(100+i) for argument i, 1, 2, 3, -2, -3 (singular
+ * projected leading coefficient or the reduced eigensolver did not converge), -900. */
+int mfeast_zgepev(mfeast_handle h, int32_t p, int64_t n, const double* A, int64_t lda, int32_t* fpm,
+                  double* epsout, int32_t* loop, const double* emid, double r, int32_t* m0, double* E, double* X,
+                  int64_t ldx, int32_t* M, double* res, const double* zne, const double* wne);
+
 /* Many independent dense real symmetric problems in one call (the first of the three
  * levels of parallelism of Section 1.1, independent search intervals or problems): the
  * arguments of mfeast_dsygv as arrays over nprob problems.  n, lda, ldb, ldx, emin, emax,

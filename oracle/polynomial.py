@@ -31,11 +31,18 @@ A_k X (case 30).  Readings (listed with their reasons in the design notes):
               style relative residual; the linear case's ||alpha B x|| has no polynomial
               analogue).  Convergence: max res over the inside pairs below 10^-fpm(3)
               (fpm(6) = 1) or epsout = |trace_k - trace_{k-1}| / (|Emid| + r) below it.
-  R-pone      right eigenvectors only (fpm(15) = 1); M, ordering and info codes as in the
-              non-Hermitian oracle: a Ritz pair counts as found when its value lies inside
-              the contour and its residual is below 0.1 (the linearization of the projected
-              polynomial has p m eigenvalues, and some of those inside the contour belong to
-              no eigenpair of the full problem; their residuals stay of order one).
+  R-pone      right eigenvectors only (fpm(15) = 1); ordering and info codes as in the
+              non-Hermitian oracle (info 3 when every kept Ritz value lies inside the
+              contour: the p m values of the linearization then crowd the subspace, and M0
+              must grow; about 1.5 times the count inside suffices in practice).
+  R-pfound    a Ritz pair counts as found (in M, the trace and the residual criterion) when
+              its value lies inside the contour and its residual is below min(0.1,
+              10^(-fpm(3)/2)).  The linearization of the projected polynomial has p m
+              eigenvalues, and those inside the contour that belong to no eigenpair of the
+              full problem keep relative residuals of 1e-2 to 1e-1 (this relative residual
+              is small for any vector when the coefficients differ in scale); the square
+              root of the target tolerance separates them from converging pairs, which
+              pass it on their way to 10^-fpm(3).
 """
 
 import numpy as np
@@ -46,6 +53,12 @@ from .splitmix import initial_subspace
 
 RANK_TOL = 1.0e-13
 SPURIOUS_RES = 1.0e-1
+
+
+def found_tol(fpm):
+    """R-pfound: a Ritz pair inside the contour counts as found below this residual,
+    min(0.1, 10^(-fpm(3)/2))."""
+    return min(SPURIOUS_RES, 10.0 ** (-0.5 * int(fpm[2])))
 
 
 def pfeastinit():
@@ -112,6 +125,7 @@ def feast_polynomial(As, emid, r, m0, fpm=None, X0=None, zne=None, wne=None):
         z, w = np.asarray(zne, np.complex128), np.asarray(wne, np.complex128)
     alpha = abs(emid) + r
     eps = 10.0 ** (-f(3))
+    ftol = found_tol(fpm)
     X = np.asarray(X0, dtype=np.complex128)[:, :m0].copy() if f(5) == 1 else initial_subspace(n, m0, f(51), True)
     facts = [sla.lu_factor(poly_eval(As, zj)) for zj in z]
     lam = None
@@ -155,7 +169,7 @@ def feast_polynomial(As, emid, r, m0, fpm=None, X0=None, zne=None, wne=None):
         res = np.linalg.norm(R, axis=0) / den
         geo = inside_ellipse(lam, emid, r, f(18), f(19))
         n_inside = int(np.sum(geo))
-        inside = geo & (res < SPURIOUS_RES)
+        inside = geo & (res < ftol)
         idx_in = np.where(inside)[0]
         idx_out = np.where(~inside)[0]
         key = lambda idx: idx[np.lexsort((lam[idx].imag, lam[idx].real))]  # noqa: E731
@@ -166,7 +180,8 @@ def feast_polynomial(As, emid, r, m0, fpm=None, X0=None, zne=None, wne=None):
         epsout = 1.0 if trace_prev is None else abs(trace - trace_prev) / alpha
         trace_prev = trace
         maxres = float(np.max(res[:M])) if M else 0.0
-        out["history"].append({"it": k, "M": M, "epsout": epsout, "maxres": maxres, "E": lam[:M].copy()})
+        out["history"].append({"it": k, "M": M, "n_inside": n_inside, "epsout": epsout, "maxres": maxres,
+                               "E": lam[:M].copy()})
         out.update(E=lam, X=X, M=M, res=res, epsout=epsout, loop=k, m0=m)
         if n_inside == 0:
             out["info"] = 1

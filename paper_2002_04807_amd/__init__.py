@@ -26,6 +26,7 @@ EXPORTED = (
     "mfeast_init_stochastic", "mfeast_contour", "mfeast_zolotarev", "mfeast_dsygv", "mfeast_dsygv_noalloc",
     "mfeast_zhegv", "mfeast_dcsrgv", "mfeast_dsy_adjoint", "mfeast_dsygv_batched", "mfeast_get_timing",
     "mfeast_get_profile", "mfeast_set_profiling", "mfeast_init_general", "mfeast_gcontour", "mfeast_zgegv",
+    "mfeast_init_polynomial", "mfeast_zgepev",
 )
 
 
@@ -65,6 +66,11 @@ def _load():
     lib.mfeast_zgegv.argtypes = [c_vp, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.POINTER(ctypes.c_double), c_i32p,
                                  c_dp, ctypes.c_double, c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, c_dp, c_dp]
     lib.mfeast_zgegv.restype = c_int
+    lib.mfeast_init_polynomial.argtypes = [c_i32p]
+    lib.mfeast_init_polynomial.restype = None
+    lib.mfeast_zgepev.argtypes = [c_vp, ctypes.c_int32, i64, c_dp, i64, c_i32p, ctypes.POINTER(ctypes.c_double),
+                                  c_i32p, c_dp, ctypes.c_double, c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, c_dp, c_dp]
+    lib.mfeast_zgepev.restype = c_int
     dense = [c_vp, ctypes.c_char, i64, c_dp, i64, c_dp, i64, c_i32p, ctypes.c_double, ctypes.c_double,
              c_i32p, c_dp, c_dp, i64, c_i32p, c_dp, ctypes.POINTER(ctypes.c_double), c_i32p, c_dp, c_dp]
     for name in ("mfeast_dsygv", "mfeast_zhegv", "mfeast_dsygv_noalloc"):
@@ -161,6 +167,13 @@ def mfeast_init_general():
     """fpm defaults of the non-Hermitian driver (two-sided, trapezoidal, circle)."""
     fpm = np.zeros(64, dtype=np.int32)
     _load().mfeast_init_general(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return fpm
+
+
+def mfeast_init_polynomial():
+    """fpm defaults of the polynomial driver (right eigenvectors, trapezoidal, circle)."""
+    fpm = np.zeros(64, dtype=np.int32)
+    _load().mfeast_init_polynomial(fpm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return fpm
 
 
@@ -519,6 +532,64 @@ def mfeast_zgegv(h, n, A, lda, B, ldb, fpm, emid, r, m0, E, X, ldx, res, zne=Non
                             None if wb is None else wb.ctypes.data)
     return {"info": int(info), "m0": int(m0_c.value), "M": int(M_c.value), "epsout": float(eps_c.value),
             "loop": int(loop_c.value)}
+
+
+def mfeast_zgepev(h, p, n, A, lda, fpm, emid, r, m0, E, X, ldx, res, zne=None, wne=None):
+    """C mfeast_zgepev; A (the p + 1 coefficient matrices, complex128 column-major, A_k at
+    k lda n), E (complex128, m0), X (complex128 column-major), res (float64, m0) device
+    tensors or pointers."""
+    lib = _load()
+    fpm_a = _fpm_array(fpm)
+    m0_c = ctypes.c_int32(int(m0))
+    M_c = ctypes.c_int32(0)
+    eps_c = ctypes.c_double(0.0)
+    loop_c = ctypes.c_int32(0)
+    em = np.array([complex(emid).real, complex(emid).imag], dtype=np.float64)
+    zb = wb = None
+    if zne is not None:
+        zb = np.ascontiguousarray(np.asarray(zne, dtype=np.complex128)).view(np.float64)
+        wb = np.ascontiguousarray(np.asarray(wne, dtype=np.complex128)).view(np.float64)
+    hp = h.ptr if isinstance(h, Handle) else h
+    info = lib.mfeast_zgepev(hp, int(p), int(n), _ptr(A), int(lda),
+                             fpm_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(eps_c),
+                             ctypes.byref(loop_c), em.ctypes.data, float(r), ctypes.byref(m0_c), _ptr(E), _ptr(X),
+                             int(ldx), ctypes.byref(M_c), _ptr(res), None if zb is None else zb.ctypes.data,
+                             None if wb is None else wb.ctypes.data)
+    return {"info": int(info), "m0": int(m0_c.value), "M": int(M_c.value), "epsout": float(eps_c.value),
+            "loop": int(loop_c.value)}
+
+
+def feast_polynomial(As, emid, r, m0, fpm=None, X0=None, handle=None, zne=None, wne=None):
+    """Eigenvalues of sum_k lambda^k A_k x = 0 inside the full contour (Emid, r) and their
+    right eigenvectors.  As: list of the p + 1 coefficient matrices as GPU tensors (complex128
+    or real, n x n).  X0: starting vectors, n x m0.  Returns a dict with E (complex), X, res,
+    M, m0, loop, epsout, info."""
+    import torch
+    p = len(As) - 1
+    n = As[0].shape[0]
+    dev = As[0].device
+    fpm = mfeast_init_polynomial() if fpm is None else _fpm_array(fpm).copy()
+    # A(n, n, p + 1) column-major: element (i, j) of A_k at i + j n + k n n
+    A_ = torch.stack([a.to(torch.complex128).mT for a in As]).contiguous()
+    X = torch.zeros((m0, n), dtype=torch.complex128, device=dev).mT
+    if X0 is not None:
+        X[:, :X0.shape[1]].copy_(X0.to(torch.complex128))
+        fpm[4] = 1
+    E = torch.zeros(m0, dtype=torch.complex128, device=dev)
+    res = torch.zeros(m0, dtype=torch.float64, device=dev)
+    own = handle is None
+    h = Handle(dev.index or 0) if own else handle
+    try:
+        out = mfeast_zgepev(h, p, n, A_, n, fpm, emid, r, m0, E, X, n, res, zne, wne)
+        out["timing"] = h.timing()
+        if fpm[51] == 1:
+            out["profile"] = h.profile()
+    finally:
+        if own:
+            h.close()
+    m = out["m0"]
+    out.update(E=E[:m], X=X[:, :m], res=res[:m], fpm=fpm)
+    return out
 
 
 def feast_general(A, B, emid, r, m0, fpm=None, X0=None, handle=None, zne=None, wne=None):

@@ -22,6 +22,8 @@ enum Slot {
   // non-Hermitian driver: left blocks, products with A^H and B^H, bases, reduced factors
   S_NH_XL, S_NH_QL, S_NH_RL, S_NH_AHQ, S_NH_BHQ, S_NH_QLO, S_NH_BQO, S_NH_AHQO, S_NH_BHQO, S_NH_T3, S_NH_T4,
   S_NH_WL, S_NH_O1, S_NH_O2, S_NH_O3, S_NH_O4, S_NH_O5, S_NH_TR, S_NH_TL,
+  // polynomial driver: products with every coefficient, reduced coefficients, companion form
+  S_PL_AKQ, S_PL_AKQO, S_PL_AKX, S_PL_AQ, S_PL_L0, S_PL_L1, S_PL_WZ, S_PL_G, S_PL_H, S_PL_Z, S_PL_V,
   S_NSLOTS
 };
 

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "../../include/mfeast.h"
@@ -601,6 +602,102 @@ int orthonormalize(hipStream_t s, int64_t n, int m, const c64* Q, Orth& o, int* 
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Polynomial FEAST (Section 3.4): kernels of its driver
+//
+// F_j = P(z_j)^H = sum_k conj(z_j)^k A_k^H (Horner), row-major with row stride ld; the
+// coefficient matrices are column-major, A_k at As + k lda n, read as their conjugate
+// transposes (coalesced, as the shift-form kernel); zc holds the conjugate nodes
+template <typename C>
+__global__ void k_poly_form(int64_t n, int64_t ld, const c64* __restrict__ As, int64_t lda, int p,
+                            const c64* __restrict__ zc, int ne, C* __restrict__ LU, int* __restrict__ perm) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (c >= n) return;
+  const int64_t mstride = lda * n;
+  for (int j = 0; j < ne; ++j) {
+    c64 acc = conj(As[(int64_t)p * mstride + i * lda + c]);
+    for (int k = p - 1; k >= 0; --k) acc = acc * zc[j] + conj(As[(int64_t)k * mstride + i * lda + c]);
+    LU[(int64_t)j * n * ld + i * ld + c] = convert<C, c64>(acc);
+  }
+  if (i == 0)
+    for (int j = 0; j < ne; ++j) perm[(int64_t)j * n + c] = (int)c;
+}
+
+// companion linearization of sum_k lambda^k Aq_k (each m x m, row-major, Aq_k at Aq + k m m):
+// L0 = [[0, I, ...], ..., [-Aq_0, ..., -Aq_(p-1)]], L1 = diag(I, ..., I, Aq_p), size p m
+__global__ void k_companion(int m, int p, const c64* __restrict__ Aq, c64* __restrict__ L0, c64* __restrict__ L1) {
+  const int pm = p * m;
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (col >= pm) return;
+  const int bi = row / m, ri = row % m, bj = col / m, cj = col % m;
+  c64 l0(0.0, 0.0), l1(0.0, 0.0);
+  if (bi < p - 1) {
+    if (bj == bi + 1 && ri == cj) l0 = c64(1.0, 0.0);
+    if (bj == bi && ri == cj) l1 = c64(1.0, 0.0);
+  } else {
+    const c64 a = Aq[((int64_t)bj * m + ri) * m + cj];
+    l0 = c64(-a.re, -a.im);
+    if (bj == p - 1) l1 = Aq[((int64_t)p * m + ri) * m + cj];
+  }
+  L0[(int64_t)row * pm + col] = l0;
+  L1[(int64_t)row * pm + col] = l1;
+}
+
+// Wsel (m x m) = first block rows of the selected eigenvector columns, unit columns
+__global__ void k_first_block(int m, int pm, const c64* __restrict__ Wz, const int* __restrict__ sel,
+                              c64* __restrict__ Wsel) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int s = sel[j];
+  double nn = 0.0;
+  for (int i = 0; i < m; ++i) nn += norm2(Wz[(int64_t)i * pm + s]);
+  const double f = nn > 0.0 ? 1.0 / sqrt(nn) : 1.0;
+  for (int i = 0; i < m; ++i) Wsel[(int64_t)i * m + j] = f * Wz[(int64_t)i * pm + s];
+}
+
+// R = sum_k lam^k AkX_k (AkX_k at AkX + k n m), column sums of |R|^2 and of |AkX_k|^2 per k,
+// in 256-row chunks: part[(q nchunk + chunk) m + c], q = 0 for R, 1 + k for AkX_k
+__global__ void k_poly_resid_partial(int64_t n, int m, int p, const c64* __restrict__ AkX, const c64* __restrict__ lam,
+                                     c64* __restrict__ R, double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (c >= m) return;
+  const int64_t nchunk = gridDim.y;
+  const int64_t blk = n * (int64_t)m;
+  const c64 l = lam[c];
+  double sr = 0.0;
+  double sk[9];
+  for (int k = 0; k <= p; ++k) sk[k] = 0.0;
+  const int64_t r1 = ((chunk + 1) * NH_ROWS < n) ? (chunk + 1) * NH_ROWS : n;
+  for (int64_t r = chunk * NH_ROWS; r < r1; ++r) {
+    c64 acc(0.0, 0.0), pw(1.0, 0.0);
+    for (int k = 0; k <= p; ++k) {
+      const c64 a = AkX[k * blk + r * m + c];
+      sk[k] += norm2(a);
+      acc = acc + pw * a;
+      pw = pw * l;
+    }
+    R[r * m + c] = acc;
+    sr += norm2(acc);
+  }
+  part[chunk * m + c] = sr;
+  for (int k = 0; k <= p; ++k) part[((int64_t)(1 + k) * nchunk + chunk) * m + c] = sk[k];
+}
+
+__global__ void k_poly_resid_final(int m, int p, int nchunk, const double* __restrict__ part, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  for (int q = 0; q <= p + 1; ++q) {
+    double a = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) a += part[((int64_t)q * nchunk + ch) * m + c];
+    out[(int64_t)q * m + c] = a;
+  }
+}
+
+constexpr int POLY_MAX_P = 8;
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1020,6 +1117,330 @@ static int nh_run(mfeast_ctx* h, int64_t n, const c64* A, int64_t lda, const c64
   return info;
 }
 
+// ---------------------------------------------------------------------------
+// Polynomial FEAST driver (right eigenvectors; the readings of the polynomial oracle)
+template <typename C>
+static int poly_run(mfeast_ctx* h, int p, int64_t n, const c64* As, int64_t lda, int32_t* fpm, double* epsout,
+                    int32_t* loop, std::complex<double> emid, double r, int32_t* m0p, double* E, c64* Xu,
+                    int64_t ldx, int32_t* Mout, double* res_out, const std::vector<std::complex<double>>& z,
+                    const std::vector<std::complex<double>>& w) {
+  auto f = [&](int i) { return fpm[i - 1]; };
+  hipStream_t s = h->stream;
+  const int ne = (int)z.size();
+  const int m0in = *m0p;
+  int m0 = m0in;
+  const double alpha = std::abs(emid) + r;
+  const double eps = std::pow(10.0, -f(3));
+  const int64_t ld = lu_ld(n);
+  const size_t szC = sizeof(C);
+  const size_t blk = (size_t)n * m0 * sizeof(c64);
+  const size_t sq = (size_t)m0 * m0 * sizeof(c64);
+  const int pmax = p * m0;
+  const size_t psq = (size_t)pmax * pmax * sizeof(c64);
+  const int64_t mstride = lda * n;
+  Timer total_t, ph;
+  total_t.start();
+  double t_fact = 0, t_solve = 0, t_ax = 0, t_eig = 0;
+
+  C* LU = (C*)h->ws(S_LU, (size_t)ne * n * ld * szC);
+  C* Dinv = (C*)h->ws(S_DINV, (size_t)ne * ((n + LU_NB - 1) / LU_NB) * 2 * LU_NB * LU_NB * szC);
+  C* Pinv = (C*)h->ws(S_PANINV, (size_t)ne * panel_inverse_entries(n) * szC);
+  int* ipiv = (int*)h->ws(S_IPIV, (size_t)ne * n * 4);
+  int* perm = (int*)h->ws(S_PERM, (size_t)ne * n * 4);
+  int* pinv = (int*)h->ws(S_PINV, (size_t)ne * n * 4);
+  int* linfo = (int*)h->ws(S_INFO, (size_t)ne * 4 + 64);
+  c64* zdev = (c64*)h->ws(S_Z, (size_t)ne * sizeof(c64));
+  C* Wc = (C*)h->ws(S_WC, (size_t)ne * n * m0 * szC);
+  C* Wy = (C*)h->ws(S_WY, (size_t)ne * n * m0 * szC);
+  c64* X = (c64*)h->ws(S_X, blk);
+  c64* Q = (c64*)h->ws(S_Q, blk);
+  c64* R = (c64*)h->ws(S_R, blk);
+  c64* Qo = (c64*)h->ws(S_AX, blk);
+  c64* T3 = (c64*)h->ws(S_NH_T3, blk);
+  c64* AkQ = (c64*)h->ws(S_PL_AKQ, (size_t)(p + 1) * blk);
+  c64* AkQo = (c64*)h->ws(S_PL_AKQO, (size_t)(p + 1) * blk);
+  c64* AkX = (c64*)h->ws(S_PL_AKX, (size_t)(p + 1) * blk);
+  c64* Aq = (c64*)h->ws(S_PL_AQ, (size_t)(p + 1) * sq);
+  c64* L0 = (c64*)h->ws(S_PL_L0, psq);
+  c64* L1 = (c64*)h->ws(S_PL_L1, psq);
+  c64* Wz = (c64*)h->ws(S_PL_WZ, psq);
+  c64* Wsel = (c64*)h->ws(S_W, sq);
+  c64* Gw = (c64*)h->ws(S_PL_G, 3 * psq);
+  c64* Hw = (c64*)h->ws(S_PL_H, psq);
+  c64* Zw = (c64*)h->ws(S_PL_Z, psq);
+  c64* Vw = (c64*)h->ws(S_PL_V, psq);
+  Orth orr{};
+  orr.S = (c64*)h->ws(S_NH_O1, sq);
+  orr.S2 = (c64*)h->ws(S_NH_O2, sq);
+  orr.Linv = (c64*)h->ws(S_NH_O3, sq);
+  orr.H1 = (c64*)h->ws(S_NH_O4, sq);
+  orr.V = (c64*)h->ws(S_NH_O5, sq);
+  orr.TG = (c64*)h->ws(S_TG, std::max(3 * sq, (size_t)m0 * 32 * sizeof(c64)));
+  orr.Tr = (c64*)h->ws(S_NH_TR, sq);
+  const size_t nsmall = (size_t)m0 * 24 + (size_t)pmax * 4 + (size_t)(p + 2) * m0 + (size_t)ne * m0 * 4 + 256;
+  double* small = (double*)h->ws(S_SMALL, nsmall * sizeof(double));
+  const int nchunk = (int)((n + 255) / 256);
+  double* part = (double*)h->ws(S_PART, (size_t)nchunk * m0 * (p + 2) * sizeof(double) + 64);
+  char* hp = h->host(nsmall * sizeof(double) + 4096);
+  if (!LU || !Dinv || !Pinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wc || !Wy || !X || !Q || !R || !Qo ||
+      !T3 || !AkQ || !AkQo || !AkX || !Aq || !L0 || !L1 || !Wz || !Wsel || !Gw || !Hw || !Zw || !Vw || !orr.S ||
+      !orr.S2 || !orr.Linv || !orr.H1 || !orr.V || !orr.TG || !orr.Tr || !small || !part || !hp)
+    return -2;
+  auto dsl = [&](size_t off) { return small + off; };
+  auto hsl = [&](size_t off) { return reinterpret_cast<double*>(hp) + off; };
+  const size_t o_cs = 0, o_us = m0, o_keep = 2 * m0, o_idx = 3 * m0, o_d = 4 * m0, o_flag = 5 * m0,
+               o_perm = 6 * m0, o_sel = 7 * m0, o_rho = 8 * m0 /* 2 m0 */, o_lam = 10 * m0 /* 2 m0 */,
+               o_nrm = 24 * (size_t)m0 /* (p + 2) m0 */, o_mu = o_nrm + (size_t)(p + 2) * m0 /* 2 pmax */,
+               o_cR = o_mu + 2 * (size_t)pmax /* 2 ne m0 */;
+  orr.d = dsl(o_d);
+  orr.keep = (int*)dsl(o_keep);
+  orr.idx = (int*)dsl(o_idx);
+  orr.flag = (int*)dsl(o_flag);
+  orr.part = part;
+  int* d_flag = (int*)dsl(o_flag);
+  int* h_flag = (int*)hsl(o_flag);
+  c64* d_mu = reinterpret_cast<c64*>(dsl(o_mu));
+  c64* h_mu = reinterpret_cast<c64*>(hsl(o_mu));
+  c64* d_lam = reinterpret_cast<c64*>(dsl(o_lam));
+  c64* h_lam = reinterpret_cast<c64*>(hsl(o_lam));
+  c64* d_rho = reinterpret_cast<c64*>(dsl(o_rho));
+  c64* h_rho = reinterpret_cast<c64*>(hsl(o_rho));
+  c64* d_cR = reinterpret_cast<c64*>(dsl(o_cR));
+  c64* h_cR = reinterpret_cast<c64*>(hsl(o_cR));
+
+  // ---- F_j = P(z_j)^H for every node (right solves by its conjugate-transpose sweeps)
+  ph.start();
+  {
+    std::vector<c64> zc(ne);
+    for (int j = 0; j < ne; ++j) zc[j] = c64(z[j].real(), -z[j].imag());
+    MF_HIP_CHECK(hipMemcpyAsync(zdev, zc.data(), ne * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemsetAsync(linfo, 0, ne * 4, s));
+    int tok = prof_begin(s);
+    hipLaunchKernelGGL((k_poly_form<C>), dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, n, ld, As,
+                       lda, p, zdev, ne, LU, perm);
+    MF_HIP_CHECK(hipGetLastError());
+    prof_end(tok, s, K_OTHER, 0.0, (double)n * n * ((p + 1.0) * sizeof(c64) + ne * szC));
+    MF_TRY(lu_factor<C>(s, n, ne, LU, ipiv, perm, pinv, linfo, Dinv));
+    tok = prof_begin(s);
+    MF_TRY(panel_inverses<C>(s, n, ne, LU, Dinv, Pinv));
+    prof_end(tok, s, K_LU_ROWS, 0.0, 0.0);
+    std::vector<int> hi(ne);
+    MF_HIP_CHECK(hipMemcpyAsync(hi.data(), linfo, ne * 4, hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < ne; ++j)
+      if (hi[j] != 0) return -2;
+  }
+  t_fact += ph.stop();
+  if (f(5) == 1) MF_TRY(copy_cm_to_rm<c64>(s, n, m0, Xu, ldx, X, m0));
+  else MF_TRY(random_block<c64>(s, n, m0, (uint64_t)(uint32_t)f(51), X, m0));
+
+  std::vector<std::complex<double>> lam;
+  std::vector<double> res;
+  std::vector<int> order;
+  double tpr = 0.0, tpi = 0.0;
+  int info = 0, M = 0, k = 0;
+  for (;;) {
+    const bool resid = k > 0;
+    const c64* rhs = resid ? R : X;
+    ph.start();
+    MF_TRY(col_absmax<c64>(s, n, m0, rhs, m0, dsl(o_cs)));
+    MF_HIP_CHECK(hipMemcpyAsync(hsl(o_cs), dsl(o_cs), m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < m0; ++c) {
+      const double a = hsl(o_cs)[c];
+      if (!std::isfinite(a)) return -2;
+      hsl(o_cs)[c] = a > 0.0 ? 1.0 / a : 1.0;
+      hsl(o_us)[c] = a > 0.0 ? a : 1.0;
+      std::complex<double> rho(0.0, 0.0);
+      for (int j = 0; j < ne; ++j) {
+        std::complex<double> cr = w[j];
+        if (resid) {
+          const std::complex<double> q = w[j] / (z[j] - lam[c]);
+          rho += q;
+          cr = -q;
+        }
+        h_cR[(size_t)j * m0 + c] = c64(cr.real(), cr.imag());
+      }
+      h_rho[c] = c64(rho.real(), rho.imag());
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(dsl(o_cs), hsl(o_cs), 2 * (size_t)m0 * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_rho, h_rho, m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_cR, h_cR, (size_t)ne * m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    {
+      int tok = prof_begin(s);
+      dim3 grid((unsigned)((m0 + 255) / 256), (unsigned)n);
+      hipLaunchKernelGGL((k_rhs_two<C>), grid, dim3(256), 0, s, n, m0, rhs, (const c64*)nullptr, dsl(o_cs),
+                         dsl(o_cs), ne, perm, (C*)nullptr, Wc);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * m0 * (16.0 + ne * szC));
+      MF_TRY(lu_solve<C>(s, n, m0, ne, LU, Pinv, (C*)nullptr, Wc, Wy, nullptr));
+      tok = prof_begin(s);
+      hipLaunchKernelGGL((k_accumulate_two<C>), grid, dim3(256), 0, s, n, m0, ne, (const C*)nullptr, Wc, pinv, d_cR,
+                         d_cR, d_rho, dsl(o_us), dsl(o_us), X, X, Q, Q, resid ? 1 : 0);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_OTHER, 0.0, (double)n * m0 * (ne * szC + 32.0));
+    }
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_solve += ph.stop();
+
+    // ---- Rayleigh-Ritz: A_k Q, orthonormal basis, reduced coefficients, companion form
+    ph.start();
+    for (int kk = 0; kk <= p; ++kk)
+      MF_TRY(rm_gemm<c64>(s, (int)n, m0, (int)n, As + kk * mstride, lda, true, false, Q, m0, AkQ + (size_t)kk * n * m0,
+                          m0));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_ax += ph.stop();
+    ph.start();
+    int kr = 0;
+    MF_TRY(orthonormalize(s, n, m0, Q, orr, (int*)hsl(o_keep), (int*)hsl(o_idx), hsl(o_flag), kr));
+    if (h_flag[0] != 0 || kr == 0) { info = -3; break; }
+    if (p * kr > NH_MAX_M0) { info = -3; break; }
+    MF_TRY(rm_gemm<c64>(s, (int)n, kr, m0, Q, m0, false, false, orr.Tr, kr, Qo, kr));
+    for (int kk = 0; kk <= p; ++kk) {
+      MF_TRY(rm_gemm<c64>(s, (int)n, kr, m0, AkQ + (size_t)kk * n * m0, m0, false, false, orr.Tr, kr,
+                          AkQo + (size_t)kk * n * kr, kr));
+      MF_TRY(rm_gemm<c64>(s, kr, kr, (int)n, Qo, kr, true, true, AkQo + (size_t)kk * n * kr, kr,
+                          Aq + (size_t)kk * kr * kr, kr));
+    }
+    const int pm = p * kr;
+    hipLaunchKernelGGL(k_companion, dim3((pm + 255) / 256, pm), dim3(256), 0, s, kr, p, Aq, L0, L1);
+    MF_HIP_CHECK(hipGetLastError());
+    {
+      const int tok = prof_begin(s);
+      hipLaunchKernelGGL(k_nh_eig, dim3(1), dim3(NH_THREADS), 0, s, pm, L0, L1, 0, Gw, Hw, Zw, Vw, Vw, d_mu, Wz,
+                         Wz, d_flag);
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_EIG, 0.0, 0.0);
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(h_mu, d_mu, pm * sizeof(c64), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    if (h_flag[0] != 0) { info = -3; break; }
+    // the kr values of the companion pencil nearest the contour's centre (ellipse metric)
+    std::vector<int> sel(pm);
+    std::vector<double> metric(pm);
+    const std::complex<double> rot = std::polar(1.0, -f(19) * M_PI / 180.0);
+    for (int q = 0; q < pm; ++q) {
+      const std::complex<double> mu(h_mu[q].re, h_mu[q].im);
+      const std::complex<double> u = rot * (mu - emid);
+      const double e = f(18) / 100.0;
+      const double mt = (u.real() / r) * (u.real() / r) + (u.imag() / (e * r)) * (u.imag() / (e * r));
+      metric[q] = std::isfinite(mt) ? mt : std::numeric_limits<double>::infinity();
+      sel[q] = q;
+    }
+    std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return metric[a] < metric[b]; });
+    m0 = kr;
+    lam.resize(m0);
+    bool fin = true;
+    int* hsel = (int*)hsl(o_sel);
+    for (int q = 0; q < m0; ++q) {
+      hsel[q] = sel[q];
+      lam[q] = std::complex<double>(h_mu[sel[q]].re, h_mu[sel[q]].im);
+      h_lam[q] = h_mu[sel[q]];
+      if (!std::isfinite(metric[sel[q]])) fin = false;
+    }
+    if (!fin) { info = -3; break; }
+    ph.start();
+    MF_HIP_CHECK(hipMemcpyAsync(dsl(o_sel), hsel, m0 * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(d_lam, h_lam, m0 * sizeof(c64), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_first_block, dim3((m0 + 255) / 256), dim3(256), 0, s, m0, pm, Wz, (const int*)dsl(o_sel),
+                       Wsel);
+    MF_HIP_CHECK(hipGetLastError());
+    // Ritz vectors, A_k X, residuals
+    MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, Qo, m0, false, false, Wsel, m0, X, m0));
+    for (int kk = 0; kk <= p; ++kk)
+      MF_TRY(rm_gemm<c64>(s, (int)n, m0, m0, AkQo + (size_t)kk * n * m0, m0, false, false, Wsel, m0,
+                          AkX + (size_t)kk * n * m0, m0));
+    {
+      const int tok = prof_begin(s);
+      hipLaunchKernelGGL(k_poly_resid_partial, dim3((m0 + 255) / 256, nchunk), dim3(256), 0, s, n, m0, p, AkX, d_lam,
+                         R, part);
+      hipLaunchKernelGGL(k_poly_resid_final, dim3((m0 + 255) / 256), dim3(256), 0, s, m0, p, nchunk, part,
+                         dsl(o_nrm));
+      MF_HIP_CHECK(hipGetLastError());
+      prof_end(tok, s, K_RESID, 0.0, (double)n * m0 * (p + 2.0) * 16.0);
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(hsl(o_nrm), dsl(o_nrm), (size_t)(p + 2) * m0 * sizeof(double), hipMemcpyDeviceToHost,
+                                s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    t_eig += ph.stop();
+    res.assign(m0, 0.0);
+    for (int c = 0; c < m0; ++c) {
+      double den = 0.0, pw = 1.0;
+      for (int kk = 0; kk <= p; ++kk) {
+        den += pw * std::sqrt(hsl(o_nrm)[(size_t)(1 + kk) * m0 + c]);
+        pw *= std::abs(lam[c]);
+      }
+      res[c] = std::sqrt(hsl(o_nrm)[c]) / den;
+      if (!std::isfinite(res[c])) fin = false;
+    }
+    if (!fin) { info = -2; break; }
+    // found: inside the contour with a residual below min(0.1, 10^(-fpm(3)/2)); values of the
+    // linearization that belong to no eigenpair keep residuals of 1e-2 to 1e-1
+    const double ftol = std::min(NH_SPURIOUS_RES, std::pow(10.0, -0.5 * f(3)));
+    std::vector<char> in(m0);
+    M = 0;
+    int n_inside = 0;
+    for (int c = 0; c < m0; ++c) {
+      const bool geo = inside_ellipse(lam[c], emid, r, f(18), f(19));
+      n_inside += geo ? 1 : 0;
+      in[c] = (geo && res[c] < ftol) ? 1 : 0;
+      M += in[c];
+    }
+    order.resize(m0);
+    for (int c = 0; c < m0; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (in[a] != in[b]) return in[a] > in[b];
+      if (lam[a].real() != lam[b].real()) return lam[a].real() < lam[b].real();
+      return lam[a].imag() < lam[b].imag();
+    });
+    double tr_re = 0.0, tr_im = 0.0, maxres = 0.0;
+    for (int q = 0; q < M; ++q) {
+      tr_re += lam[order[q]].real();
+      tr_im += lam[order[q]].imag();
+      maxres = std::max(maxres, res[order[q]]);
+    }
+    const double eo = (k == 0) ? 1.0 : std::hypot(tr_re - tpr, tr_im - tpi) / alpha;
+    tpr = tr_re;
+    tpi = tr_im;
+    *epsout = eo;
+    *loop = k;
+    *Mout = M;
+    if (f(1) != 0) fprintf(stderr, "%3d %6d  %24.16E  %24.16E  m0=%d\n", k, M, eo, maxres, m0);
+    if (n_inside == 0) { info = 1; break; }
+    if (n_inside >= m0) { info = 3; break; }
+    if (M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps))) { info = 0; break; }
+    if (k >= f(4)) { info = 2; break; }
+    ++k;
+  }
+  if (info == 0 || info == 1 || info == 2 || info == 3) {
+    std::vector<int> hperm(order.begin(), order.end());
+    int* d_perm = (int*)dsl(o_perm);
+    MF_HIP_CHECK(hipMemcpyAsync(d_perm, hperm.data(), m0 * sizeof(int), hipMemcpyHostToDevice, s));
+    MF_TRY(copy_rm_to_cm<c64>(s, n, m0, X, m0, Xu, ldx, d_perm));
+    std::vector<double> e_out(2 * (size_t)m0), r_out((size_t)m0);
+    for (int q = 0; q < m0; ++q) {
+      e_out[2 * q] = lam[order[q]].real();
+      e_out[2 * q + 1] = lam[order[q]].imag();
+      r_out[q] = res[order[q]];
+    }
+    MF_HIP_CHECK(hipMemcpyAsync(E, e_out.data(), e_out.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipMemcpyAsync(res_out, r_out.data(), r_out.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    *m0p = m0;
+  }
+  h->timing[0] = t_fact;
+  h->timing[1] = t_solve;
+  h->timing[2] = t_ax;
+  h->timing[3] = 0.0;
+  h->timing[5] = total_t.stop();
+  h->timing[4] = h->timing[5] - t_fact - t_solve - t_ax;
+  h->timing[6] = (double)(*loop + 1);
+  h->timing[7] = t_eig;
+  return info;
+}
+
 static int check_general_fpm(const int32_t* fpm, bool expert) {
   auto f = [&](int i) { return fpm[i - 1]; };
   if (!expert) {
@@ -1123,6 +1544,71 @@ int mfeast_zgegv(mfeast_handle h, int64_t n, const double* A, int64_t lda, const
     info = nh_run<c32>(h, n, Ac, lda, Bc, ldb, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
   else
     info = nh_run<c64>(h, n, Ac, lda, Bc, ldb, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
+  if (prof_on()) {
+    (void)hipStreamSynchronize(h->stream);
+    prof_collect(h->prof);
+    prof_enable(false);
+  }
+  return info;
+}
+
+void mfeast_init_polynomial(int32_t* fpm) {
+  if (fpm == nullptr) return;
+  mfeast_init_general(fpm);
+  fpm[14] = 1;  // fpm(15) right eigenvectors
+}
+
+int mfeast_zgepev(mfeast_handle h, int32_t p, int64_t n, const double* A, int64_t lda, int32_t* fpm, double* epsout,
+                  int32_t* loop, const double* emid, double r, int32_t* m0, double* E, double* X, int64_t ldx,
+                  int32_t* M, double* res, const double* zne, const double* wne) {
+  // argument positions: h 1, p 2, n 3, A 4, lda 5, fpm 6, epsout 7, loop 8, emid 9, r 10,
+  // m0 11, E 12, X 13, ldx 14, M 15, res 16, zne 17, wne 18
+  if (p < 1 || p > POLY_MAX_P) return -102;
+  if (n < 1 || n > 16384) return 202;
+  if (m0 == nullptr) return -111;
+  if (*m0 < 1 || *m0 > n || (int64_t)p * *m0 > NH_MAX_M0) return 201;
+  if (emid == nullptr) return -109;
+  if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(emid[0]) || !std::isfinite(emid[1])) return 200;
+  if (fpm == nullptr) return -106;
+  if ((zne == nullptr) != (wne == nullptr)) return zne == nullptr ? -117 : -118;
+  const int fi = check_general_fpm(fpm, zne != nullptr);
+  if (fi) return fi;
+  if (fpm[14] != 1) return 115;
+  if (h == nullptr) return -101;
+  if (A == nullptr) return -104;
+  if (lda < n) return -105;
+  if (epsout == nullptr) return -107;
+  if (loop == nullptr) return -108;
+  if (E == nullptr) return -112;
+  if (X == nullptr) return -113;
+  if (ldx < n) return -114;
+  if (M == nullptr) return -115;
+  if (res == nullptr) return -116;
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  GemmScratchScope scratch_scope(h);
+  const std::complex<double> em(emid[0], emid[1]);
+  std::vector<std::complex<double>> z, w;
+  const int ne = fpm[7];
+  if (zne != nullptr) {
+    z.resize(ne);
+    w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+      z[j] = std::complex<double>(zne[2 * j], zne[2 * j + 1]);
+      w[j] = std::complex<double>(wne[2 * j], wne[2 * j + 1]);
+    }
+  } else {
+    full_contour(em, r, ne, fpm[15], fpm[17], fpm[18], z, w);
+  }
+  set_gemm_3m(fpm[52] == 0);
+  prof_enable(fpm[51] == 1 || h->prof_all);
+  for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
+  const c64* Ac = reinterpret_cast<const c64*>(A);
+  c64* Xc = reinterpret_cast<c64*>(X);
+  int info;
+  if (fpm[41] == 1)
+    info = poly_run<c32>(h, p, n, Ac, lda, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
+  else
+    info = poly_run<c64>(h, p, n, Ac, lda, fpm, epsout, loop, em, r, m0, E, Xc, ldx, M, res, z, w);
   if (prof_on()) {
     (void)hipStreamSynchronize(h->stream);
     prof_collect(h->prof);

@@ -232,3 +232,35 @@ def test_general_driver_argument_checks():
     assert call(handle=ctypes.c_void_p(1), ldx=5) == -115
     assert call(handle=ctypes.c_void_p(1), res=None) == -117
     np.testing.assert_array_equal(mf.mfeast_init_general().astype(np.int64), nh.nfeastinit())
+
+
+def test_polynomial_driver_argument_checks():
+    """mfeast_zgepev's host checks with host dummies and a NULL or dummy handle (every call
+    below stops at a check before any device access)."""
+    from oracle import polynomial as pl
+    dummy = np.zeros(8)
+
+    def call(p=2, n=10, m0=4, r=1.0, fpm=None, handle=None, lda=None, X=dummy, res=dummy, ldx=None):
+        f = pl.pfeastinit().astype(np.int32) if fpm is None else fpm
+        return mf.mfeast_zgepev(handle, p, n, dummy, lda or max(n, 1), f, 0.0, r, m0, dummy, X, ldx or max(n, 1),
+                                res)["info"]
+    assert call(p=0) == -102
+    assert call(p=9) == -102
+    assert call(n=0) == 202
+    assert call(m0=0) == 201
+    assert call(m0=11) == 201
+    assert call(p=3, n=1000, m0=171) == 201  # p M0 > 512
+    assert call(p=3, n=1000, m0=170, handle=ctypes.c_void_p(1), lda=5) == -105
+    assert call(r=-1.0) == 200
+    f = pl.pfeastinit().astype(np.int32)
+    f[14] = 0
+    assert call(fpm=f) == 115
+    for idx, val, code in [(7, 1, 108), (15, 2, 116), (17, 0, 118), (18, 181, 119), (2, 17, 103)]:
+        f = pl.pfeastinit().astype(np.int32)
+        f[idx] = val
+        assert call(fpm=f) == code, (idx, val)
+    assert call() == -101
+    assert call(handle=ctypes.c_void_p(1), ldx=5) == -114
+    assert call(handle=ctypes.c_void_p(1), res=None) == -116
+    assert call(handle=ctypes.c_void_p(1), X=None) == -113
+    np.testing.assert_array_equal(mf.mfeast_init_polynomial().astype(np.int64), pl.pfeastinit())

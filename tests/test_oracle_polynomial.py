@@ -81,3 +81,38 @@ def test_argument_checks():
     f[14] = 0
     assert po.feast_polynomial([A, A], 0.0, 1.0, 4, f)["info"] == 115
     assert po.feast_polynomial([A, A], 0.0, 0.0, 4)["info"] == 200
+
+
+@pytest.mark.parametrize("n,p,seed,leading,emid,r,extra", [
+    (333, 2, 5, True, -0.3 + 0.4j, 0.9, {}),
+    (120, 3, 7, False, 0.1 + 0.1j, 1.0, {17: 70, 18: 20}),
+])
+def test_found_pairs_are_eigenpairs_at_every_iteration(n, p, seed, leading, emid, r, extra):
+    """R-pfound: over the whole history, every pair counted in M is within 1e-5 alpha of a
+    constructed eigenvalue inside the contour (no spurious value of the linearization is
+    counted), and the run ends with all of them (M0 = 1.5 times the count)."""
+    As, lam, Xe = gen.prescribed_polynomial(n, p, seed, leading=leading)
+    fpm = po.pfeastinit()
+    for k, v in extra.items():
+        fpm[k] = v
+    inside = nh.inside_ellipse(lam, emid, r, int(fpm[17]), int(fpm[18]))
+    cnt = int(inside.sum())
+    out = po.feast_polynomial(As, emid, r, int(np.ceil(1.5 * cnt)), fpm)
+    assert out["info"] == 0 and out["M"] == cnt
+    alpha = abs(emid) + r
+    li = lam[inside]
+    for h in out["history"]:
+        assert h["M"] <= cnt
+        for e in h["E"]:
+            assert np.min(np.abs(li - e)) <= 1e-5 * alpha
+
+
+def test_subspace_crowded_by_the_linearization_gives_info_3():
+    """M0 a little above the count: the 2 M0 values of the quadratic's linearization put
+    at least M0 inside the contour at the first iteration, which reports info 3; M0 below
+    the count does too."""
+    As, lam, Xe = gen.prescribed_polynomial(333, 2, 5, leading=True)
+    emid, r = -0.3 + 0.4j, 0.9
+    cnt = int(nh.inside_ellipse(lam, emid, r).sum())
+    assert po.feast_polynomial(As, emid, r, cnt + 20)["info"] == 3
+    assert po.feast_polynomial(As, emid, r, cnt // 3)["info"] == 3
