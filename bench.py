@@ -57,11 +57,14 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="only run this many FP32 steps (for rocprofv3 runs); no JSON extras")
-    p.add_argument("--workload", default="pencil", choices=("pencil", "sparse", "batched", "adjoint", "count"),
+    p.add_argument("--workload", default="pencil",
+                   choices=("pencil", "sparse", "batched", "adjoint", "count", "general", "polynomial"),
                    help="pencil: the metric's n=4096 generalized complex Hermitian problem (default); "
                         "sparse: 64^3 Laplacian CSR with batched BiCGSTAB; batched: 128 independent "
                         "real problems; adjoint: forward and backward of the n=4096 tridiagonal workload; "
-                        "count: stochastic eigenvalue-count estimate on the n=4096 pencil")
+                        "count: stochastic eigenvalue-count estimate on the n=4096 pencil; general: "
+                        "two-sided non-Hermitian FEAST on an n=4096 complex pencil; polynomial: quadratic "
+                        "FEAST at n=4096")
     return p.parse_args()
 
 
@@ -518,6 +521,260 @@ def bench_count(args, mf, torch, np, gen):
     return result
 
 
+def _match_err(E, lam_in, scale):
+    """Largest distance from each computed eigenvalue to the nearest exact one, and whether
+    the matching is one to one."""
+    import numpy as np
+    if E.size == 0 or lam_in.size == 0:
+        return None, False
+    d = np.abs(E[:, None] - lam_in[None, :])
+    idx = np.argmin(d, axis=1)
+    return float(np.max(d[np.arange(E.size), idx]) / scale), bool(np.unique(idx).size == E.size)
+
+
+GN, GSEED, GEMID, GR = 4096, 0, 0.0 + 0.0j, 0.5
+
+
+def bench_general(args, mf, torch, np, gen):
+    """Non-hermitian FEAST (Section 3.3) on a complex general pencil: n = 4096,
+    A = B V diag(lambda) V^-1 with lambda uniform on [-2, 2] + i[-2, 2], V = I + 0.3 G / sqrt(n),
+    B = I + 0.1 C C^H / n (seed 0); the eigenvalues in the circle |z| <= 0.5 with right and left
+    eigenvectors (two-sided, fpm(15)=0), M0 = 1.5 times the count, 16 trapezoidal nodes,
+    FP32 solves with the FP64 residual form, res <= 1e-10.  One step = one mfeast_zgegv call."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    A, B, lam, _, _ = gen.prescribed_nonnormal(GN, GSEED, generalized=True)
+    lam_in = lam[np.abs(lam - GEMID) <= GR]
+    cnt = int(lam_in.size)
+    m0 = int(math.ceil(1.5 * cnt))
+    print("bench: general inputs built in %.1f s (%d eigenvalues inside, M0 %d)"
+          % (time.perf_counter() - t0, cnt, m0), file=sys.stderr, flush=True)
+    At = torch.from_numpy(np.asfortranarray(A)).to(dev)
+    Bt = torch.from_numpy(np.asfortranarray(B)).to(dev)
+    E = torch.zeros(m0, dtype=torch.complex128, device=dev)
+    res = torch.zeros(2 * m0, dtype=torch.float64, device=dev)
+    X = torch.zeros((2 * m0, GN), dtype=torch.complex128, device=dev).mT
+    h = mf.Handle(0)
+
+    def step(profile):
+        fpm = mf.mfeast_init_general()
+        fpm[41] = 1
+        fpm[2] = 10
+        fpm[51] = 1 if profile else 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = mf.mfeast_zgegv(h, GN, At, GN, Bt, GN, fpm, GEMID, GR, m0, E, X, GN, res)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t1
+
+    for _ in range(args.warmup):
+        step(False)
+    times = []
+    for _ in range(max(1, args.steps)):
+        out, t = step(False)
+        times.append(t)
+    out_p, _ = step(True)
+    prof = h.profile()
+    timing = h.timing()
+    h.close()
+    M, mk = out["M"], out["m0"]
+    r_all = res.cpu().numpy()
+    rr, rl = r_all[:mk][:M], r_all[m0:m0 + mk][:M]
+    err, one_to_one = _match_err(E.cpu().numpy()[:M], lam_in, abs(GEMID) + GR)
+    conv = int(np.sum((rr <= RES_BAR) & (rl <= RES_BAR)))
+    t = float(np.median(times))
+    print("bench: general steps %s s, M %d of %d, loop %d" % (["%.3f" % x for x in times], M, cnt, out["loop"]),
+          file=sys.stderr, flush=True)
+    result = {
+        "metric": "converged eigenpairs/s (right and left), non-Hermitian FEAST, FP32 solves + FP64 residual form",
+        "value": conv / t, "unit": "eigenpairs/s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 solves + c128 residual/RR", "data": "synthetic",
+        "config": {"workload": "complex general pencil n=4096 (seed 0), circle |z|<=0.5, two-sided, "
+                               "16 trapezoidal nodes, M0=1.5x count, res<=1e-10, FP32 solves",
+                   "n": GN, "m0": m0, "nodes": 16, "seed": GSEED},
+        "accuracy": {"M": M, "exact_count": cnt, "max_eig_err_over_alpha": err, "one_to_one": one_to_one,
+                     "max_res_right": float(rr.max()) if M else None, "max_res_left": float(rl.max()) if M else None,
+                     "loop": out["loop"], "info": out["info"], "m0_out": mk},
+        "timing_split_s": {"factor": timing[0], "solve": timing[1], "a_x": timing[2], "b_x": timing[3],
+                           "rest": timing[4], "total": timing[5], "reduced_eig": timing[7]},
+        "time_split": classes_summary(prof, t * 1e3),
+        "roofline": roofline_of(prof),
+        "roofline_next": roofline_of(prof, 1),
+    }
+    for r in (result["roofline"], result["roofline_next"]):
+        if r is not None:
+            r["unit_of_work"] = r["unit_of_work"].replace("all 8 nodes: the forward (L, U) and the conjugate-transpose "
+                                                          "(U^H, L^H) sweeps", "all 16 nodes: the right (conjugate-"
+                                                          "transpose) and left (forward) sweeps")
+            if r["kernel_class"] == "reduced_eig":
+                r["kernel"] = "k_nh_eig (one workgroup)"
+                r["unit_of_work"] = "one reduced non-Hermitian eigensolve (nominal 116 m^3 flops)"
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_general(A, B, m0, out["loop"], conv)
+    return result
+
+
+def cpu_baseline_general(A, B, m0, loop, conv):
+    """The oracle's steps for the non-Hermitian workload on a bounded sample: one node's
+    complex128 LU (scipy, as the oracle), its right and left solves with M0 right-hand sides,
+    and one two-sided Rayleigh-Ritz step (range bases by SVD, reduced products, scipy eig
+    with left and right vectors), scaled to 16 nodes and the GPU run's loop count."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle import nonhermitian as nh
+    z, w = nh.full_contour(GEMID, GR, 16)
+    rng = np.random.default_rng(1)
+    Y = rng.standard_normal((GN, m0)) + 1j * rng.standard_normal((GN, m0))
+    t0 = time.perf_counter()
+    fac = sla.lu_factor(z[0] * B - A)
+    t_lu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Q = sla.lu_solve(fac, B @ Y)
+    QL = sla.lu_solve(fac, B.conj().T @ Y, trans=2)
+    t_solve = time.perf_counter() - t0
+    del fac
+    t0 = time.perf_counter()
+    Qo = nh._range_basis(Q)
+    QLo = nh._range_basis(QL)
+    k = min(Qo.shape[1], QLo.shape[1])
+    Qo, QLo = Qo[:, :k], QLo[:, :k]
+    Aq = QLo.conj().T @ (A @ Qo)
+    Bq = QLo.conj().T @ (B @ Qo)
+    sla.eig(Aq, Bq, left=True, right=True)
+    A.conj().T @ QLo
+    B.conj().T @ QLo
+    t_rr = time.perf_counter() - t0
+    iters = loop + 1
+    t_est = 16 * (t_lu + iters * t_solve) + iters * t_rr
+    return {"value": conv / t_est, "unit": "eigenpairs/s", "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
+            "sample": "one node of 16: complex128 LU (n=4096), right and left solves of %d right-hand sides, and "
+                      "one two-sided Rayleigh-Ritz step, %.1f s; scaled to 16 nodes and %d loops: est. %.1f s per "
+                      "call (lu %.2f s, solves %.2f s, rr %.2f s)" % (m0, t_lu + t_solve + t_rr, iters, t_est,
+                                                                      t_lu, t_solve, t_rr)}
+
+
+PN, PDEG, PSEED, PEMID, PR = 4096, 2, 0, 0.0 + 0.0j, 0.3
+
+
+def bench_polynomial(args, mf, torch, np, gen):
+    """Polynomial FEAST (Section 3.4) on a quadratic problem: n = 4096, P(lambda) =
+    L (lambda - S_2)(lambda - S_1) with S_t = V_t diag(D_t) V_t^-1 (D_t uniform on
+    [-2, 2] + i[-2, 2], V_t = I + 0.3 G_t / sqrt(n)) and L = I + 0.1 C C^H / n (seed 0); the
+    eigenvalues in |z| <= 0.3, M0 = 1.5 times the count, 16 trapezoidal nodes, FP32 solves
+    with the FP64 residual form, res <= 1e-10.  One step = one mfeast_zgepev call."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    As, lam, _ = gen.prescribed_polynomial(PN, PDEG, PSEED, leading=True, vectors=False)
+    lam_in = lam[np.abs(lam - PEMID) <= PR]
+    cnt = int(lam_in.size)
+    m0 = int(math.ceil(1.5 * cnt))
+    print("bench: polynomial inputs built in %.1f s (%d eigenvalues inside, M0 %d)"
+          % (time.perf_counter() - t0, cnt, m0), file=sys.stderr, flush=True)
+    At = torch.stack([torch.from_numpy(a).mT for a in As]).contiguous().to(dev)
+    E = torch.zeros(m0, dtype=torch.complex128, device=dev)
+    res = torch.zeros(m0, dtype=torch.float64, device=dev)
+    X = torch.zeros((m0, PN), dtype=torch.complex128, device=dev).mT
+    h = mf.Handle(0)
+
+    def step(profile):
+        fpm = mf.mfeast_init_polynomial()
+        fpm[41] = 1
+        fpm[2] = 10
+        fpm[51] = 1 if profile else 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = mf.mfeast_zgepev(h, PDEG, PN, At, PN, fpm, PEMID, PR, m0, E, X, PN, res)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t1
+
+    for _ in range(args.warmup):
+        step(False)
+    times = []
+    for _ in range(max(1, args.steps)):
+        out, t = step(False)
+        times.append(t)
+    out_p, _ = step(True)
+    prof = h.profile()
+    timing = h.timing()
+    h.close()
+    M = out["M"]
+    rr = res.cpu().numpy()[:M]
+    err, one_to_one = _match_err(E.cpu().numpy()[:M], lam_in, abs(PEMID) + PR)
+    conv = int(np.sum(rr <= RES_BAR))
+    t = float(np.median(times))
+    print("bench: polynomial steps %s s, M %d of %d, loop %d" % (["%.3f" % x for x in times], M, cnt, out["loop"]),
+          file=sys.stderr, flush=True)
+    result = {
+        "metric": "converged eigenpairs/s, polynomial (quadratic) FEAST, FP32 solves + FP64 residual form",
+        "value": conv / t, "unit": "eigenpairs/s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 solves + c128 residual/RR", "data": "synthetic",
+        "config": {"workload": "quadratic matrix polynomial n=4096 (seed 0, leading coefficient), circle "
+                               "|z|<=0.3, 16 trapezoidal nodes, M0=1.5x count, res<=1e-10, FP32 solves",
+                   "n": PN, "degree": PDEG, "m0": m0, "nodes": 16, "seed": PSEED},
+        "accuracy": {"M": M, "exact_count": cnt, "max_eig_err_over_alpha": err, "one_to_one": one_to_one,
+                     "max_res": float(rr.max()) if M else None, "loop": out["loop"], "info": out["info"]},
+        "timing_split_s": {"factor": timing[0], "solve": timing[1], "a_x": timing[2], "rest": timing[4],
+                           "total": timing[5], "reduced_eig": timing[7]},
+        "time_split": classes_summary(prof, t * 1e3),
+        "roofline": roofline_of(prof),
+        "roofline_next": roofline_of(prof, 1),
+    }
+    for r in (result["roofline"], result["roofline_next"]):
+        if r is not None:
+            r["unit_of_work"] = r["unit_of_work"].replace("all 8 nodes: the forward (L, U) and the conjugate-transpose "
+                                                          "(U^H, L^H) sweeps, which run concurrently on two streams",
+                                                          "all 16 nodes: the conjugate-transpose sweeps of P(z_j)^H")
+            if r["kernel_class"] == "reduced_eig":
+                r["kernel"] = "k_nh_eig on the companion pencil (one workgroup)"
+                r["unit_of_work"] = "one companion eigensolve of order 2 m (nominal 116 (2m)^3 flops)"
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_polynomial(As, m0, out["loop"], conv)
+    return result
+
+
+def cpu_baseline_polynomial(As, m0, loop, conv):
+    """The oracle's steps for the polynomial workload on a bounded sample: forming P(z_j) and
+    its complex128 LU for one node, one solve with M0 right-hand sides, and one
+    Rayleigh-Ritz step (range basis, the p + 1 projected coefficients, scipy eig of the
+    companion pencil), scaled to 16 nodes and the GPU run's loop count."""
+    import numpy as np
+    import scipy.linalg as sla
+    from oracle import nonhermitian as nh
+    from oracle import polynomial as po
+    z, w = nh.full_contour(PEMID, PR, 16)
+    rng = np.random.default_rng(1)
+    Y = rng.standard_normal((PN, m0)) + 1j * rng.standard_normal((PN, m0))
+    t0 = time.perf_counter()
+    fac = sla.lu_factor(po.poly_eval(As, z[0]))
+    t_lu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Q = sla.lu_solve(fac, Y)
+    t_solve = time.perf_counter() - t0
+    del fac
+    t0 = time.perf_counter()
+    Qo = nh._range_basis(Q)
+    m = Qo.shape[1]
+    Aq = [Qo.conj().T @ (Ak @ Qo) for Ak in As]
+    L0 = np.zeros((2 * m, 2 * m), dtype=np.complex128)
+    L1 = np.zeros_like(L0)
+    L0[:m, m:] = np.eye(m)
+    L1[:m, :m] = np.eye(m)
+    L0[m:, :m] = -Aq[0]
+    L0[m:, m:] = -Aq[1]
+    L1[m:, m:] = Aq[2]
+    sla.eig(L0, L1)
+    t_rr = time.perf_counter() - t0
+    iters = loop + 1
+    t_est = 16 * (t_lu + iters * t_solve) + iters * t_rr
+    return {"value": conv / t_est, "unit": "eigenpairs/s", "cores": _cores(), "cpu": _cpu_model(), "kind": "oracle",
+            "sample": "one node of 16: P(z) and its complex128 LU (n=4096), one solve of %d right-hand sides, and "
+                      "one Rayleigh-Ritz step with the companion eigensolve, %.1f s; scaled to 16 nodes and %d "
+                      "loops: est. %.1f s per call (lu %.2f s, solves %.2f s, rr %.2f s)"
+                      % (m0, t_lu + t_solve + t_rr, iters, t_est, t_lu, t_solve, t_rr)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -535,7 +792,7 @@ def main():
         sys.exit(1)
     if args.workload != "pencil":
         fn = {"sparse": bench_sparse, "batched": bench_batched, "adjoint": bench_adjoint,
-              "count": bench_count}[args.workload]
+              "count": bench_count, "general": bench_general, "polynomial": bench_polynomial}[args.workload]
         print(json.dumps(fn(args, mf, torch, np, gen)))
         return
     dev = torch.device("cuda:0")

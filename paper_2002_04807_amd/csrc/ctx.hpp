@@ -39,7 +39,8 @@ template <typename T> inline int gemmT(hipStream_t s, bool am, bool cj, const Ge
 // row-major product C(MxN) = op(A) * B, helper for the internal blocks
 template <typename T>
 inline int rm_gemm(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, bool a_mcontig, bool conj_a,
-                   const T* B, int64_t ldb, T* C, int64_t ldc, double alpha = 1.0, double beta = 0.0) {
+                   const T* B, int64_t ldb, T* C, int64_t ldc, double alpha = 1.0, double beta = 0.0,
+                   int cls = K_RR_GEMM) {
   GemmArgs g{};
   g.M = M; g.N = N; g.K = K;
   g.A = A; g.lda = lda; g.a_bs = 0;
@@ -49,7 +50,7 @@ inline int rm_gemm(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, 
   const int tok = prof_begin(s);
   const int rc = gemmT<T>(s, a_mcontig, conj_a, g);
   const double fl = (is_cplx<T>::value ? 8.0 : 2.0) * (double)M * N * K;
-  prof_end(tok, s, K_RR_GEMM, fl, (double)sizeof(T) * ((double)M * K + (double)K * N + 2.0 * M * N));
+  prof_end(tok, s, cls, fl, (double)sizeof(T) * ((double)M * K + (double)K * N + 2.0 * M * N));
   return rc;
 }
 

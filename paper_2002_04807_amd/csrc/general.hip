@@ -16,10 +16,10 @@
 //   RR        equilibrated, rank-truncated orthonormal bases of Q and Q~ (Cholesky of the
 //             Gram matrix with column drops, then Newton-Schulz), the reduced pencil
 //             Aq = Q~^H A Q, Bq = Q~^H B Q (two-sided, fpm(15) = 0; Q~ = Q one-sided,
-//             fpm(15) = 1), its eigenvalues and right and left eigenvectors in one
-//             workgroup (k_nh_eig: Gauss-Jordan for Bq^-1 Aq, Householder Hessenberg form,
-//             shifted QR to the Schur form, triangular eigenvectors), X = Q W (unit
-//             columns), Y = Q~ W~ (y_i^H B x_i = 1)
+//             fpm(15) = 1), its eigenvalues and right and left eigenvectors on the device
+//             (nh_eigensolve: Newton-Schulz inverse of Bq and GEMMs, Householder Hessenberg
+//             form and windowed shifted QR in one workgroup, triangular eigenvectors one
+//             workgroup per eigenvalue), X = Q W (unit columns), Y = Q~ W~ (y_i^H B x_i = 1)
 //   stop      M = #lambda inside the ellipse; residuals ||A x - lambda B x|| / ||alpha B x||
 //             and ||A^H y - conj(lambda) B^H y|| / ||alpha B^H y||, alpha = |Emid| + r;
 //             epsout = |trace_k - trace_{k-1}| / alpha (Table tab-common2).
@@ -38,9 +38,13 @@ using namespace mf;
 
 namespace {
 
-constexpr int NH_MAX_M0 = 512;  // the reduced eigensolver runs in one workgroup
+constexpr int NH_MAX_M0 = 512;  // the Schur form of the reduced problem runs in one workgroup
 constexpr int NH_THREADS = 256;
 constexpr double NH_SPURIOUS_RES = 1.0e-1;
+// nominal work of the Schur form and the eigenvectors of the triangular factor of an
+// order-m matrix, in flops per m^3 (a complex nonsymmetric eigensolve with vectors: four
+// times the usual 25 m^3 real count); the GEMMs around it count their own flops
+constexpr double NH_SCHUR_FLOPS = 100.0;
 
 // ---------------------------------------------------------------------------
 // full contour: z(theta) = emid + e^{i phi} (r cos theta + i e r sin theta), theta in
@@ -220,7 +224,18 @@ __global__ void k_take_cols(int rows, int k, const c64* __restrict__ src, int ld
 }
 
 // ---------------------------------------------------------------------------
-// The reduced non-Hermitian pencil in one workgroup (m <= NH_MAX_M0).
+// The reduced non-Hermitian pencil (Aq, Bq), order m <= NH_MAX_M0, in four stages:
+//   1. Binv = Bq^-1 by the Newton-Schulz iteration X <- X (2I - Bq X) from
+//      X0 = Bq^H / (||Bq||_1 ||Bq||_inf) (FP64 GEMMs), then C = Binv Aq
+//   2. Householder reduction of C to Hessenberg form (Z accumulated; three launches per
+//      column: the reflector, the update from the left over column blocks, the update
+//      from the right over row blocks of H and Z), then, in one workgroup, shifted QR
+//      with Wilkinson shifts to the Schur form T = Z^H C Z: each sweep chases its bulge
+//      through windows of QW rotations held in LDS by one wavefront, and the rest of H
+//      and Z receives each window's rotations from all threads afterwards
+//   3. eigenvectors of the triangular T (one workgroup per eigenvalue): right V (upper),
+//      left U (lower, u^H T = lambda u^H)
+//   4. W = Z V (unit columns); left: WL = Binv^H Z U scaled so that wl^H Bq w = 1
 __device__ inline double cabs(c64 a) { return hypot(a.re, a.im); }
 
 __device__ inline c64 csqrt(c64 z) {
@@ -234,33 +249,12 @@ __device__ inline c64 csqrt(c64 z) {
   return c64(fabs(z.im) / (2.0 * t), copysign(t, z.im));
 }
 
-// block-wide max of v with its index (lowest index on ties); red arrays of NH_THREADS
-__device__ inline int block_argmax(double v, int idx, double* red_v, int* red_i) {
-  const int tid = threadIdx.x;
-  red_v[tid] = v;
-  red_i[tid] = idx;
-  __syncthreads();
-  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double o = red_v[tid + s];
-      const int oi = red_i[tid + s];
-      if (o > red_v[tid] || (o == red_v[tid] && oi >= 0 && (red_i[tid] < 0 || oi < red_i[tid]))) {
-        red_v[tid] = o;
-        red_i[tid] = oi;
-      }
-    }
-    __syncthreads();
-  }
-  const int r = red_i[0];
-  __syncthreads();
-  return r;
-}
-
+template <int NT>
 __device__ inline double block_sum(double v, double* red_v) {
   const int tid = threadIdx.x;
   red_v[tid] = v;
   __syncthreads();
-  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red_v[tid] += red_v[tid + s];
     __syncthreads();
   }
@@ -269,130 +263,191 @@ __device__ inline double block_sum(double v, double* red_v) {
   return r;
 }
 
-// Aq, Bq: m x m row-major.  Outputs lam[m], W (right eigenvectors of the pencil, columns,
-// unit 2-norm) and, with two != 0, WL (left eigenvectors, wl_j^H Bq w_j = 1).
-// Work: G (m x 3m), H, Z, V, U (m x m each).  flag: 1 Bq singular, 2 no convergence.
-__global__ __launch_bounds__(NH_THREADS) void k_nh_eig(int m, const c64* __restrict__ Aq,
-                                                       const c64* __restrict__ Bq, int two, c64* __restrict__ G,
-                                                       c64* __restrict__ H, c64* __restrict__ Z,
-                                                       c64* __restrict__ V, c64* __restrict__ U,
-                                                       c64* __restrict__ lam, c64* __restrict__ W,
-                                                       c64* __restrict__ WL, int* __restrict__ flag) {
-  __shared__ double red_v[NH_THREADS];
-  __shared__ int red_i[NH_THREADS];
-  __shared__ c64 vec[NH_MAX_M0];
-  __shared__ c64 s_cs[2];
-  __shared__ int s_ctl[4];
+template <int NT>
+__device__ inline int block_max_int(int v, int* red_i) {
   const int tid = threadIdx.x;
-  const int m3 = 3 * m;
+  red_i[tid] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red_i[tid] = max(red_i[tid], red_i[tid + s]);
+    __syncthreads();
+  }
+  const int r = red_i[0];
+  __syncthreads();
+  return r;
+}
+
+// ---- stage 1: Newton-Schulz inverse
+// X0 = Bq^H / (max column sum * max row sum of |Bq|) (one workgroup)
+__global__ __launch_bounds__(NH_THREADS) void k_ns_init(int m, const c64* __restrict__ B, c64* __restrict__ X) {
+  __shared__ double red_v[NH_THREADS];
+  __shared__ double s_alpha;
+  const int tid = threadIdx.x;
+  double cmax = 0.0, rmax = 0.0;
+  for (int j = tid; j < m; j += NH_THREADS) {
+    double cs = 0.0, rs = 0.0;
+    for (int i = 0; i < m; ++i) {
+      cs += cabs(B[(int64_t)i * m + j]);
+      rs += cabs(B[(int64_t)j * m + i]);
+    }
+    cmax = fmax(cmax, cs);
+    rmax = fmax(rmax, rs);
+  }
+  red_v[tid] = cmax;
+  __syncthreads();
+  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) red_v[tid] = fmax(red_v[tid], red_v[tid + s]);
+    __syncthreads();
+  }
+  const double c1 = red_v[0];
+  __syncthreads();
+  red_v[tid] = rmax;
+  __syncthreads();
+  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+    if (tid < s) red_v[tid] = fmax(red_v[tid], red_v[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) s_alpha = (c1 > 0.0 && red_v[0] > 0.0) ? 1.0 / (c1 * red_v[0]) : 0.0;
+  __syncthreads();
+  const double al = s_alpha;
+  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    X[e] = al * conj(B[(int64_t)j * m + i]);
+  }
+}
+
+// T <- 2I - T in place, and per-workgroup partial sums of ||I - T||_F^2 (T = Bq X on entry)
+constexpr int NS_BLOCKS = 64;
+__global__ void k_ns_step(int m, c64* __restrict__ T, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t mm = (int64_t)m * m;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < mm; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    const c64 t = T[e];
+    const c64 r = c64((i == j ? 1.0 : 0.0) - t.re, -t.im);
+    acc += norm2(r);
+    T[e] = c64((i == j ? 2.0 : 0.0) - t.re, -t.im);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---- stage 2: Hessenberg form and windowed shifted QR (one workgroup)
+constexpr int QW = 20;       // rotations per window
+constexpr int QR_THREADS = 512;
+constexpr int QS = QW + 3;   // window order: the bulge column, QW rotation pairs, one more row
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---- Householder reduction to upper Hessenberg form, column k
+// the reflector I - beta v v^H mapping H[k+1.., k] to alpha e_1: v (entries k+1..m-1) and beta
+// to vb (vb[m] holds beta in its real part); column k of H set to its final value
+__global__ __launch_bounds__(256) void k_hess_vec(int m, int k, c64* __restrict__ H, c64* __restrict__ vb) {
+  __shared__ double red_v[256];
+  const int tid = threadIdx.x;
+  const c64 x0 = H[(int64_t)(k + 1) * m + k];
+  double part = 0.0;
+  for (int i = k + 1 + tid; i < m; i += 256) part += norm2(H[(int64_t)i * m + k]);
+  const double xn2 = block_sum<256>(part, red_v);
+  if (xn2 == 0.0) {
+    for (int i = k + 1 + tid; i < m; i += 256) vb[i] = c64(0.0, 0.0);
+    if (tid == 0) vb[m] = c64(0.0, 0.0);
+    return;
+  }
+  const double ax0 = cabs(x0), xn = sqrt(xn2);
+  const c64 ph = ax0 > 0.0 ? c64(x0.re / ax0, x0.im / ax0) : c64(1.0, 0.0);
+  const c64 alpha = c64(-xn * ph.re, -xn * ph.im);
+  const double vn2 = xn2 - ax0 * ax0 + norm2(x0 - alpha);
+  for (int i = k + 1 + tid; i < m; i += 256) {
+    vb[i] = (i == k + 1) ? x0 - alpha : H[(int64_t)i * m + k];
+    H[(int64_t)i * m + k] = (i == k + 1) ? alpha : c64(0.0, 0.0);
+  }
+  if (tid == 0) vb[m] = c64(vn2 > 0.0 ? 2.0 / vn2 : 0.0, 0.0);
+}
+
+// from the left: columns k+1..m-1 (16 per workgroup), rows k+1..m-1
+__global__ __launch_bounds__(256) void k_hess_left(int m, int k, c64* __restrict__ H, const c64* __restrict__ vb) {
+  __shared__ c64 red[256];
+  const double beta = vb[m].re;
+  if (beta == 0.0) return;
+  const int tc = threadIdx.x % 16, tr = threadIdx.x / 16;
+  const int c = k + 1 + blockIdx.x * 16 + tc;
+  c64 acc(0.0, 0.0);
+  if (c < m)
+    for (int i = k + 1 + tr; i < m; i += 16) acc = acc + conj(vb[i]) * H[(int64_t)i * m + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st >= 16; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const c64 w = beta * red[tc];
+  if (c < m)
+    for (int i = k + 1 + tr; i < m; i += 16) H[(int64_t)i * m + c] = H[(int64_t)i * m + c] - vb[i] * w;
+}
+
+// from the right: rows of H (0..m-1) and of Z (m..2m-1), 16 per workgroup, columns k+1..m-1
+__global__ __launch_bounds__(256) void k_hess_right(int m, int k, c64* __restrict__ H, c64* __restrict__ Z,
+                                                    const c64* __restrict__ vb) {
+  const double beta = vb[m].re;
+  if (beta == 0.0) return;
+  const int tc = threadIdx.x % 16, tr = threadIdx.x / 16;
+  const int r = blockIdx.x * 16 + tr;
+  if (r >= 2 * m) return;
+  c64* row = (r < m ? H + (int64_t)r * m : Z + (int64_t)(r - m) * m);
+  c64 acc(0.0, 0.0);
+  for (int c = k + 1 + tc; c < m; c += 16) acc = acc + row[c] * vb[c];
+  for (int o = 8; o > 0; o >>= 1) {
+    acc.re += __shfl_xor(acc.re, o, 16);
+    acc.im += __shfl_xor(acc.im, o, 16);
+  }
+  const c64 t = beta * acc;
+  for (int c = k + 1 + tc; c < m; c += 16) row[c] = row[c] - t * conj(vb[c]);
+}
+
+__global__ void k_eye(int m, c64* __restrict__ Z) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  Z[e] = c64(e / m == e % m ? 1.0 : 0.0, 0.0);
+}
+
+// shifted QR: H (in: upper Hessenberg; out: the Schur form T, upper triangular), Z (in:
+// the Hessenberg transform; out: C = Z T Z^H), both m x m row-major; tnorm: max |T_ij| over
+// the upper triangle; flag 2 when the iteration does not converge within 40 m sweeps
+__global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H, c64* __restrict__ Z,
+                                                      double* __restrict__ tnorm, int* __restrict__ flag) {
+  __shared__ double red_v[QR_THREADS];
+  __shared__ int red_i[QR_THREADS];
+  __shared__ c64 sH[QS * QS];
+  __shared__ double s_rc[QW];
+  __shared__ c64 s_rs[QW];
+  __shared__ c64 s_mu;
+  const int tid = threadIdx.x;
   const double eps = 2.220446049250313e-16;
   if (tid == 0) *flag = 0;
-  // ---- 1. Gauss-Jordan with partial pivoting on [Bq | Aq | I]: G = [I | Bq^-1 Aq | Bq^-1]
-  for (int64_t e = tid; e < (int64_t)m * m3; e += NH_THREADS) {
-    const int i = (int)(e / m3), c = (int)(e % m3);
-    G[e] = c < m ? Bq[(int64_t)i * m + c] : (c < 2 * m ? Aq[(int64_t)i * m + c - m] : c64(c - 2 * m == i ? 1.0 : 0.0, 0.0));
-  }
-  __syncthreads();
-  double gmax = 0.0;
-  for (int k = 0; k < m; ++k) {
-    double best = -1.0;
-    int bi = -1;
-    for (int i = k + tid; i < m; i += NH_THREADS) {
-      const double a = cabs(G[(int64_t)i * m3 + k]);
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
-    }
-    const int p = block_argmax(best, bi, red_v, red_i);
-    const c64 pv = G[(int64_t)p * m3 + k];
-    const double pa = cabs(pv);
-    gmax = fmax(gmax, pa);
-    if (!(pa > 1e-300) || pa < 1e-15 * gmax) {
-      if (tid == 0) *flag = 1;
-      return;
-    }
-    if (p != k)
-      for (int c = tid; c < m3; c += NH_THREADS) {
-        const c64 t = G[(int64_t)k * m3 + c];
-        G[(int64_t)k * m3 + c] = G[(int64_t)p * m3 + c];
-        G[(int64_t)p * m3 + c] = t;
-      }
-    __syncthreads();
-    const c64 inv = cdiv(c64(1.0, 0.0), pv);
-    for (int c = tid; c < m3; c += NH_THREADS) G[(int64_t)k * m3 + c] = inv * G[(int64_t)k * m3 + c];
-    for (int i = tid; i < m; i += NH_THREADS) vec[i] = G[(int64_t)i * m3 + k];
-    __syncthreads();
-    for (int64_t e = tid; e < (int64_t)m * m3; e += NH_THREADS) {
-      const int i = (int)(e / m3), c = (int)(e % m3);
-      if (i != k) G[e] = G[e] - vec[i] * G[(int64_t)k * m3 + c];
-    }
-    __syncthreads();
-  }
-  // ---- 2. H = Bq^-1 Aq, Z = I; Householder reduction to upper Hessenberg form
-  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
-    const int i = (int)(e / m), c = (int)(e % m);
-    H[e] = G[(int64_t)i * m3 + m + c];
-    Z[e] = c64(i == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int k = 0; k + 2 < m; ++k) {
-    double part = 0.0;
-    for (int i = k + 1 + tid; i < m; i += NH_THREADS) part += norm2(H[(int64_t)i * m + k]);
-    const double xn2 = block_sum(part, red_v);
-    if (xn2 == 0.0) continue;
-    const c64 x0 = H[(int64_t)(k + 1) * m + k];
-    const double ax0 = cabs(x0), xn = sqrt(xn2);
-    const c64 ph = ax0 > 0.0 ? c64(x0.re / ax0, x0.im / ax0) : c64(1.0, 0.0);
-    const c64 alpha = c64(-xn * ph.re, -xn * ph.im);
-    for (int i = k + 1 + tid; i < m; i += NH_THREADS) vec[i] = (i == k + 1) ? x0 - alpha : H[(int64_t)i * m + k];
-    const double vn2 = xn2 - ax0 * ax0 + norm2(x0 - alpha);
-    const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-    __syncthreads();
-    // left: rows k+1.., columns k..m-1 (one thread per column)
-    for (int c = k + tid; c < m; c += NH_THREADS) {
-      c64 sc(0.0, 0.0);
-      for (int i = k + 1; i < m; ++i) sc = sc + conj(vec[i]) * H[(int64_t)i * m + c];
-      sc = beta * sc;
-      for (int i = k + 1; i < m; ++i) H[(int64_t)i * m + c] = H[(int64_t)i * m + c] - vec[i] * sc;
-    }
-    __syncthreads();
-    // right: all rows, columns k+1..m-1, of H and of Z (one thread per row)
-    for (int i = tid; i < m; i += NH_THREADS) {
-      c64 t(0.0, 0.0), tz(0.0, 0.0);
-      for (int c = k + 1; c < m; ++c) {
-        t = t + H[(int64_t)i * m + c] * vec[c];
-        tz = tz + Z[(int64_t)i * m + c] * vec[c];
-      }
-      t = beta * t;
-      tz = beta * tz;
-      for (int c = k + 1; c < m; ++c) {
-        H[(int64_t)i * m + c] = H[(int64_t)i * m + c] - t * conj(vec[c]);
-        Z[(int64_t)i * m + c] = Z[(int64_t)i * m + c] - tz * conj(vec[c]);
-      }
-    }
-    __syncthreads();
-    for (int i = k + 2 + tid; i < m; i += NH_THREADS) H[(int64_t)i * m + k] = c64(0.0, 0.0);
-    if (tid == 0) H[(int64_t)(k + 1) * m + k] = alpha;
-    __syncthreads();
-  }
-  // ---- 3. shifted QR (Wilkinson shifts, Givens rotations) to the Schur form T = Z^H C Z
+  // ---- shifted QR on the active block [lo, hi]
   int hi = m - 1, its = 0, total = 0;
   while (hi >= 1) {
-    if (tid == 0) {
-      int l = hi;
-      for (; l >= 1; --l) {
-        const double sub = cabs(H[(int64_t)l * m + l - 1]);
-        const double dsum = cabs(H[(int64_t)l * m + l]) + cabs(H[(int64_t)(l - 1) * m + l - 1]);
-        if (sub <= eps * dsum || sub < 1e-300) break;
-      }
-      if (l >= 1) H[(int64_t)l * m + l - 1] = c64(0.0, 0.0);
-      s_ctl[0] = (l < 1) ? 0 : l;
+    // lo: the largest l <= hi with a negligible subdiagonal entry H[l][l-1] (0 if none)
+    int cand = 0;
+    for (int l = 1 + tid; l <= hi; l += QR_THREADS) {
+      const double sub = cabs(H[(int64_t)l * m + l - 1]);
+      const double dsum = cabs(H[(int64_t)l * m + l]) + cabs(H[(int64_t)(l - 1) * m + l - 1]);
+      if (sub <= eps * dsum || sub < 1e-300) cand = l;
     }
-    __syncthreads();
-    const int lo = s_ctl[0];
-    __syncthreads();
+    const int lo = block_max_int<QR_THREADS>(cand, red_i);
+    if (lo >= 1 && tid == 0) H[(int64_t)lo * m + lo - 1] = c64(0.0, 0.0);
     if (lo == hi) {
+      __syncthreads();
       --hi;
       its = 0;
       continue;
@@ -416,146 +471,288 @@ __global__ __launch_bounds__(NH_THREADS) void k_nh_eig(int m, const c64* __restr
         const c64 m2 = c64(0.5 * (a.re + d.re), 0.5 * (a.im + d.im)) - disc;
         mu = cabs(m1 - d) <= cabs(m2 - d) ? m1 : m2;
       }
-      s_cs[0] = H[(int64_t)lo * m + lo] - mu;  // x
-      s_cs[1] = H[(int64_t)(lo + 1) * m + lo];  // y
+      s_mu = mu;
     }
     __syncthreads();
-    for (int k = lo; k < hi; ++k) {
-      __shared__ double s_c;
-      __shared__ c64 s_s;
-      if (tid == 0) {
-        const c64 x = s_cs[0], y = s_cs[1];
-        const double ax = cabs(x), ay = cabs(y);
-        double cc;
-        c64 ss;
-        if (ay == 0.0) {
-          cc = 1.0;
-          ss = c64(0.0, 0.0);
-        } else if (ax == 0.0) {
-          cc = 0.0;
-          ss = c64(y.re / ay, -y.im / ay);
+    const c64 mu = s_mu;
+    for (int k0 = lo; k0 < hi;) {
+      const int kend = min(k0 + QW, hi);
+      const int nrot = kend - k0;
+      const int a = (k0 == lo) ? lo : k0 - 1;
+      const int e = min(hi, k0 + QW + 1);
+      const int sz = e - a + 1;
+      for (int q = tid; q < QS * QS; q += QR_THREADS) {
+        const int i = q / QS, j = q % QS;
+        sH[q] = (i < sz && j < sz) ? H[(int64_t)(a + i) * m + a + j] : c64(0.0, 0.0);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        // the chase inside the window, one wavefront: per rotation one round of LDS reads
+        // (its operands and the 2 x 2 block where the row and the column update meet), the
+        // row update of columns j != kl, kl+1 (lane j - c0l), the column update of rows
+        // i <= k+2 (lane i; the block's rows from the row-rotated values), one round of writes
+        const int lane = tid;
+        for (int r = 0; r < nrot; ++r) {
+          const int k = k0 + r, kl = k - a;
+          const int c0l = (k == lo) ? kl : kl - 1;
+          const int j = c0l + lane;
+          const int rmax = min(k + 2, hi) - a;
+          const int i = lane;
+          const c64 x = (k == lo) ? sH[kl * QS + kl] - mu : sH[kl * QS + kl - 1];
+          const c64 y = (k == lo) ? sH[(kl + 1) * QS + kl] : sH[(kl + 1) * QS + kl - 1];
+          const c64 b00 = sH[kl * QS + kl], b01 = sH[kl * QS + kl + 1];
+          const c64 b10 = sH[(kl + 1) * QS + kl], b11 = sH[(kl + 1) * QS + kl + 1];
+          const int jc = min(j, QS - 1), ic = min(i, QS - 1);
+          const c64 pa = sH[kl * QS + jc], pb = sH[(kl + 1) * QS + jc];
+          c64 qa = sH[ic * QS + kl], qb = sH[ic * QS + kl + 1];
+          // G = [c s; -conj(s) c] with G [x; y] = [r; 0], c real
+          const double ax2 = norm2(x), ay2 = norm2(y);
+          double cc;
+          c64 ss;
+          if (ay2 == 0.0) {
+            cc = 1.0;
+            ss = c64(0.0, 0.0);
+          } else if (ax2 == 0.0) {
+            const double iy = 1.0 / sqrt(ay2);
+            cc = 0.0;
+            ss = c64(y.re * iy, -y.im * iy);
+          } else {
+            const double ax = sqrt(ax2);
+            const double ir = 1.0 / sqrt(ax2 + ay2);
+            const double f = ir / ax;
+            cc = ax * ir;
+            ss = c64(f * (x.re * y.re + x.im * y.im), f * (x.im * y.re - x.re * y.im));
+          }
+          if (lane == 0) {
+            s_rc[r] = cc;
+            s_rs[r] = ss;
+          }
+          if (i == kl) {
+            qa = cc * b00 + ss * b10;
+            qb = cc * b01 + ss * b11;
+          } else if (i == kl + 1) {
+            qa = cc * b10 - conj(ss) * b00;
+            qb = cc * b11 - conj(ss) * b01;
+          }
+          if (j < sz && j != kl && j != kl + 1) {
+            sH[kl * QS + j] = cc * pa + ss * pb;
+            sH[(kl + 1) * QS + j] = cc * pb - conj(ss) * pa;
+          }
+          if (i <= rmax) {
+            sH[i * QS + kl] = cc * qa + conj(ss) * qb;
+            sH[i * QS + kl + 1] = cc * qb - ss * qa;
+          }
+          wave_sync();
+        }
+      }
+      __syncthreads();
+      // the window back to H; the window's rotations applied to the rest (entries k0..kend
+      // of each segment): rows of the columns right of the window, the rows above it, and
+      // every row of Z
+      for (int q = tid; q < sz * sz; q += QR_THREADS) {
+        const int i = q / sz, j = q % sz;
+        H[(int64_t)(a + i) * m + a + j] = sH[i * QS + j];
+      }
+      const int ncol = m - 1 - e, nabove = a;
+      const int items = ncol + nabove + m;
+      for (int it = tid; it < items; it += QR_THREADS) {
+        c64 v[QW + 1];
+        c64* M = H;
+        int64_t base, stride;
+        bool cols;
+        if (it < ncol) {
+          base = (int64_t)k0 * m + e + 1 + it;
+          stride = m;
+          cols = false;
         } else {
-          const double rr = hypot(ax, ay);
-          cc = ax / rr;
-          ss = c64(x.re / ax, x.im / ax) * c64(y.re / rr, -y.im / rr);
+          const bool isz = it >= ncol + nabove;
+          const int i = isz ? it - ncol - nabove : it - ncol;
+          if (isz) M = Z;
+          base = (int64_t)i * m + k0;
+          stride = 1;
+          cols = true;
         }
-        s_c = cc;
-        s_s = ss;
-      }
-      __syncthreads();
-      const double cc = s_c;
-      const c64 ss = s_s;
-      // rows k, k+1 from the left: G = [c s; -conj(s) c]
-      const int c0 = (k == lo) ? lo : k - 1;
-      for (int j = c0 + tid; j < m; j += NH_THREADS) {
-        const c64 a = H[(int64_t)k * m + j], b = H[(int64_t)(k + 1) * m + j];
-        H[(int64_t)k * m + j] = cc * a + ss * b;
-        H[(int64_t)(k + 1) * m + j] = cc * b - conj(ss) * a;
-      }
-      __syncthreads();
-      // columns k, k+1 from the right by G^H, rows 0..min(k+2, hi); and Z
-      const int rmax = (k + 2 < hi) ? k + 2 : hi;
-      for (int i = tid; i < m; i += NH_THREADS) {
-        if (i <= rmax) {
-          const c64 a = H[(int64_t)i * m + k], b = H[(int64_t)i * m + k + 1];
-          H[(int64_t)i * m + k] = cc * a + conj(ss) * b;
-          H[(int64_t)i * m + k + 1] = cc * b - ss * a;
+        // unconditional loads of entries k0..k0+QW (clamped to kend), issued together
+#pragma unroll
+        for (int q = 0; q <= QW; ++q) v[q] = M[base + (int64_t)min(q, nrot) * stride];
+        // row rotations act as [c s; -conj(s) c] on (v_r, v_r+1); column rotations (by G^H)
+        // as the same with s replaced by conj(s)
+#pragma unroll
+        for (int r = 0; r < QW; ++r) {
+          if (r < nrot) {
+            const double cc = s_rc[r];
+            const c64 ss = cols ? conj(s_rs[r]) : s_rs[r];
+            const c64 xa = v[r], yb = v[r + 1];
+            v[r] = cc * xa + ss * yb;
+            v[r + 1] = cc * yb - conj(ss) * xa;
+          }
         }
-        const c64 za = Z[(int64_t)i * m + k], zb = Z[(int64_t)i * m + k + 1];
-        Z[(int64_t)i * m + k] = cc * za + conj(ss) * zb;
-        Z[(int64_t)i * m + k + 1] = cc * zb - ss * za;
+#pragma unroll
+        for (int q = 0; q <= QW; ++q)
+          if (q <= nrot) M[base + (int64_t)q * stride] = v[q];
       }
       __syncthreads();
-      if (tid == 0 && k + 1 < hi) {
-        s_cs[0] = H[(int64_t)(k + 1) * m + k];
-        s_cs[1] = H[(int64_t)(k + 2) * m + k];
-      }
-      __syncthreads();
+      k0 = kend;
     }
   }
-  // ---- 4. eigenvectors of the triangular T: right (V, upper) and left (U, lower)
-  double tnorm = 0.0;
-  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
+  double tn = 0.0;
+  for (int64_t e = tid; e < (int64_t)m * m; e += QR_THREADS) {
     const int i = (int)(e / m), c = (int)(e % m);
-    if (c >= i) tnorm = fmax(tnorm, cabs(H[e]));
+    if (c >= i) tn = fmax(tn, cabs(H[e]));
   }
-  red_v[tid] = tnorm;
+  red_v[tid] = tn;
   __syncthreads();
-  for (int s = NH_THREADS / 2; s > 0; s >>= 1) {
+  for (int s = QR_THREADS / 2; s > 0; s >>= 1) {
     if (tid < s) red_v[tid] = fmax(red_v[tid], red_v[tid + s]);
     __syncthreads();
   }
-  const double small = fmax(eps * red_v[0], 1e-300);
+  if (tid == 0) *tnorm = red_v[0];
+}
+
+// ---- stage 3: eigenvectors of the triangular T, one workgroup (one wavefront) per eigenvalue i:
+// right V[:, i] (V[k][i] = 0 for k > i, V[i][i] = 1, back substitution upwards) and, with
+// two, left U[:, i] (u^H (T - lambda_i I) = 0: u_k = 0 for k < i, u_i = 1, forward)
+__global__ __launch_bounds__(64) void k_nh_trivec(int m, const c64* __restrict__ T, const double* __restrict__ tnorm,
+                                                  int two, c64* __restrict__ lam, c64* __restrict__ V,
+                                                  c64* __restrict__ U) {
+  __shared__ c64 col[NH_MAX_M0];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double small = fmax(2.220446049250313e-16 * (*tnorm), 1e-300);
+  const c64 li = T[(int64_t)i * m + i];
+  if (lane == 0) lam[i] = li;
+  for (int k = lane; k < m; k += 64) col[k] = c64(k == i ? 1.0 : 0.0, 0.0);
   __syncthreads();
-  for (int i = tid; i < m; i += NH_THREADS) {
-    const c64 li = H[(int64_t)i * m + i];
-    lam[i] = li;
-    for (int k = m - 1; k > i; --k) V[(int64_t)k * m + i] = c64(0.0, 0.0);
-    V[(int64_t)i * m + i] = c64(1.0, 0.0);
-    for (int k = i - 1; k >= 0; --k) {
-      c64 sacc(0.0, 0.0);
-      for (int l = k + 1; l <= i; ++l) sacc = sacc + H[(int64_t)k * m + l] * V[(int64_t)l * m + i];
-      c64 d = H[(int64_t)k * m + k] - li;
-      if (cabs(d) < small) d = c64(small, 0.0);
-      const c64 q = cdiv(sacc, d);
-      V[(int64_t)k * m + i] = c64(-q.re, -q.im);
-    }
-    if (two) {
-      // u^H (T - li I) = 0: conj(u_i) = 1, conj(u_k) = -sum_{l<k} conj(u_l) T[l][k] / (T[k][k] - li)
-      for (int k = 0; k < i; ++k) U[(int64_t)k * m + i] = c64(0.0, 0.0);
-      U[(int64_t)i * m + i] = c64(1.0, 0.0);
-      for (int k = i + 1; k < m; ++k) {
-        c64 sacc(0.0, 0.0);
-        for (int l = i; l < k; ++l) sacc = sacc + conj(U[(int64_t)l * m + i]) * H[(int64_t)l * m + k];
-        c64 d = H[(int64_t)k * m + k] - li;
-        if (cabs(d) < small) d = c64(small, 0.0);
-        const c64 q = cdiv(sacc, d);
-        U[(int64_t)k * m + i] = conj(c64(-q.re, -q.im));
-      }
-    }
-  }
-  __syncthreads();
-  // ---- 5. W = Z V; left: UC = Z U into H (free), WL = Binv^H UC
-  for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
-    const int i = (int)(e / m), j = (int)(e % m);
+  for (int k = i - 1; k >= 0; --k) {
     c64 acc(0.0, 0.0);
-    for (int k = 0; k <= j; ++k) acc = acc + Z[(int64_t)i * m + k] * V[(int64_t)k * m + j];
-    W[e] = acc;
+    for (int l = k + 1 + lane; l <= i; l += 64) acc = acc + T[(int64_t)k * m + l] * col[l];
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.re += __shfl_xor(acc.re, o);
+      acc.im += __shfl_xor(acc.im, o);
+    }
+    c64 d = T[(int64_t)k * m + k] - li;
+    if (cabs(d) < small) d = c64(small, 0.0);
+    const c64 q = cdiv(acc, d);
+    if (lane == 0) col[k] = c64(-q.re, -q.im);
+    __syncthreads();
   }
+  for (int k = lane; k < m; k += 64) V[(int64_t)k * m + i] = col[k];
+  if (!two) return;
   __syncthreads();
+  for (int k = lane; k < m; k += 64) col[k] = c64(k == i ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  // conj(u_k) = -sum_{l=i..k-1} conj(u_l) T[l][k] / (T[k][k] - lambda_i)
+  for (int k = i + 1; k < m; ++k) {
+    c64 acc(0.0, 0.0);
+    for (int l = i + lane; l < k; l += 64) acc = acc + conj(col[l]) * T[(int64_t)l * m + k];
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.re += __shfl_xor(acc.re, o);
+      acc.im += __shfl_xor(acc.im, o);
+    }
+    c64 d = T[(int64_t)k * m + k] - li;
+    if (cabs(d) < small) d = c64(small, 0.0);
+    const c64 q = cdiv(acc, d);
+    if (lane == 0) col[k] = conj(c64(-q.re, -q.im));
+    __syncthreads();
+  }
+  for (int k = lane; k < m; k += 64) U[(int64_t)k * m + i] = col[k];
+}
+
+// ---- stage 4: unit columns of W; with two, WL[:, j] scaled so that wl_j^H (Bq w_j) = 1
+// (BW = Bq W before the scaling of W)
+__global__ void k_nh_normalize(int m, c64* __restrict__ W, const c64* __restrict__ BW, c64* __restrict__ WL, int two) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double nn = 0.0;
+  for (int i = 0; i < m; ++i) nn += norm2(W[(int64_t)i * m + j]);
+  const double f = nn > 0.0 ? 1.0 / sqrt(nn) : 1.0;
+  for (int i = 0; i < m; ++i) W[(int64_t)i * m + j] = f * W[(int64_t)i * m + j];
+  if (!two) return;
+  c64 d(0.0, 0.0);
+  for (int i = 0; i < m; ++i) d = d + conj(WL[(int64_t)i * m + j]) * BW[(int64_t)i * m + j];
+  d = f * d;
+  const c64 g = cabs(d) > 0.0 ? cdiv(c64(1.0, 0.0), conj(d)) : c64(1.0, 0.0);
+  for (int i = 0; i < m; ++i) WL[(int64_t)i * m + j] = WL[(int64_t)i * m + j] * g;
+}
+
+// Reduced eigensolver workspace: Binv, X2, T (m x m each; T also holds U Z products), H,
+// Z, V, U (m x m), part (>= NS_BLOCKS + 2 doubles, device), flag (device int).
+struct NhEig {
+  c64 *binv, *x2, *t, *h, *z, *v, *u;
+  double* part;
+  int* flag;
+};
+
+// eigenvalues lam (device, m), right eigenvectors W (unit columns) and, with two, left
+// eigenvectors WL (wl_j^H Bq w_j = 1) of the pencil (Aq, Bq), all m x m row-major on the
+// device; h_flag (host): 0, 1 (Bq numerically singular), 2 (QR did not converge).
+// Host-synchronizing (the Newton-Schulz stop test).
+int nh_eigensolve(hipStream_t s, int m, const c64* Aq, const c64* Bq, bool two, NhEig& w, c64* lam, c64* W,
+                         c64* WL, int* h_flag) {
+  *h_flag = 0;
+  // ---- Bq^-1 by Newton-Schulz: stop when ||I - Bq X||_F has reached rounding level
+  int tok0 = prof_begin(s);
+  hipLaunchKernelGGL(k_ns_init, dim3(1), dim3(NH_THREADS), 0, s, m, Bq, w.binv);
+  MF_HIP_CHECK(hipGetLastError());
+  prof_end(tok0, s, K_EIG, 0.0, 0.0);
+  const int nb = std::min(NS_BLOCKS, (int)(((int64_t)m * m + 255) / 256));
+  std::vector<double> hp(nb);
+  double prev = std::numeric_limits<double>::infinity();
+  bool ok = false;
+  for (int it = 0; it < 100; ++it) {
+    MF_TRY(rm_gemm<c64>(s, m, m, m, Bq, m, false, false, w.binv, m, w.t, m, 1.0, 0.0, K_EIG));
+    const int tk = prof_begin(s);
+    hipLaunchKernelGGL(k_ns_step, dim3(nb), dim3(256), 0, s, m, w.t, w.part);
+    MF_HIP_CHECK(hipGetLastError());
+    prof_end(tk, s, K_EIG, 0.0, 0.0);
+    MF_TRY(rm_gemm<c64>(s, m, m, m, w.binv, m, false, false, w.t, m, w.x2, m, 1.0, 0.0, K_EIG));
+    std::swap(w.binv, w.x2);
+    MF_HIP_CHECK(hipMemcpyAsync(hp.data(), w.part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP_CHECK(hipStreamSynchronize(s));
+    double r2 = 0.0;
+    for (int b = 0; b < nb; ++b) r2 += hp[b];
+    const double r = std::sqrt(r2);
+    if (!std::isfinite(r)) break;
+    // the residual of the previous iterate; the new one is at least as good once it is small
+    if (r < 64.0 * m * 2.220446049250313e-16 || (r < 1e-6 && r > 0.25 * prev)) {
+      ok = true;
+      break;
+    }
+    prev = r;
+  }
+  if (!ok) {
+    *h_flag = 1;
+    return 0;
+  }
+  // ---- C = Binv Aq, then the Schur form
+  MF_TRY(rm_gemm<c64>(s, m, m, m, w.binv, m, false, false, Aq, m, w.h, m, 1.0, 0.0, K_EIG));
+  int tok = prof_begin(s);
+  hipLaunchKernelGGL(k_eye, dim3((unsigned)(((int64_t)m * m + 255) / 256)), dim3(256), 0, s, m, w.z);
+  for (int k = 0; k + 2 < m; ++k) {
+    hipLaunchKernelGGL(k_hess_vec, dim3(1), dim3(256), 0, s, m, k, w.h, w.x2);
+    hipLaunchKernelGGL(k_hess_left, dim3((m - k - 1 + 15) / 16), dim3(256), 0, s, m, k, w.h, (const c64*)w.x2);
+    hipLaunchKernelGGL(k_hess_right, dim3((2 * m + 15) / 16), dim3(256), 0, s, m, k, w.h, w.z, (const c64*)w.x2);
+  }
+  MF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_nh_qr, dim3(1), dim3(QR_THREADS), 0, s, m, w.h, w.z, w.part, w.flag);
+  MF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_nh_trivec, dim3(m), dim3(64), 0, s, m, w.h, w.part, two ? 1 : 0, lam, w.v, w.u);
+  MF_HIP_CHECK(hipGetLastError());
+  prof_end(tok, s, K_EIG, NH_SCHUR_FLOPS * (double)m * m * m, 0.0);
+  // ---- W = Z V; left: WL = Binv^H (Z U); BW = Bq W
+  MF_TRY(rm_gemm<c64>(s, m, m, m, w.z, m, false, false, w.v, m, W, m, 1.0, 0.0, K_EIG));
   if (two) {
-    for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
-      const int i = (int)(e / m), j = (int)(e % m);
-      c64 acc(0.0, 0.0);
-      for (int k = j; k < m; ++k) acc = acc + Z[(int64_t)i * m + k] * U[(int64_t)k * m + j];
-      H[e] = acc;
-    }
-    __syncthreads();
-    for (int64_t e = tid; e < (int64_t)m * m; e += NH_THREADS) {
-      const int i = (int)(e / m), j = (int)(e % m);
-      c64 acc(0.0, 0.0);
-      for (int k = 0; k < m; ++k) acc = acc + conj(G[(int64_t)k * m3 + 2 * m + i]) * H[(int64_t)k * m + j];
-      WL[e] = acc;
-    }
-    __syncthreads();
+    MF_TRY(rm_gemm<c64>(s, m, m, m, w.z, m, false, false, w.u, m, w.t, m, 1.0, 0.0, K_EIG));
+    MF_TRY(rm_gemm<c64>(s, m, m, m, w.binv, m, true, true, w.t, m, WL, m, 1.0, 0.0, K_EIG));
+    MF_TRY(rm_gemm<c64>(s, m, m, m, Bq, m, false, false, W, m, w.t, m, 1.0, 0.0, K_EIG));
   }
-  // ---- 6. normalization: unit right vectors; wl_j^H Bq w_j = 1
-  for (int j = tid; j < m; j += NH_THREADS) {
-    double nn = 0.0;
-    for (int i = 0; i < m; ++i) nn += norm2(W[(int64_t)i * m + j]);
-    const double f = nn > 0.0 ? 1.0 / sqrt(nn) : 1.0;
-    for (int i = 0; i < m; ++i) W[(int64_t)i * m + j] = f * W[(int64_t)i * m + j];
-    if (two) {
-      c64 d(0.0, 0.0);
-      for (int i = 0; i < m; ++i) {
-        c64 t(0.0, 0.0);
-        for (int k = 0; k < m; ++k) t = t + Bq[(int64_t)i * m + k] * W[(int64_t)k * m + j];
-        d = d + conj(WL[(int64_t)i * m + j]) * t;
-      }
-      const c64 g = cabs(d) > 0.0 ? cdiv(c64(1.0, 0.0), conj(d)) : c64(1.0, 0.0);
-      for (int i = 0; i < m; ++i) WL[(int64_t)i * m + j] = WL[(int64_t)i * m + j] * g;
-    }
-  }
+  tok = prof_begin(s);
+  hipLaunchKernelGGL(k_nh_normalize, dim3((m + 63) / 64), dim3(64), 0, s, m, W, w.t, WL, two ? 1 : 0);
+  MF_HIP_CHECK(hipGetLastError());
+  prof_end(tok, s, K_EIG, 0.0, 0.0);
+  MF_HIP_CHECK(hipMemcpyAsync(h_flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  MF_HIP_CHECK(hipStreamSynchronize(s));
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -986,14 +1183,10 @@ static int nh_run(mfeast_ctx* h, int64_t n, const c64* A, int64_t lda, const c64
     t_eig += ph.stop();
     ph.start();
     {
-      const int tok = prof_begin(s);
-      hipLaunchKernelGGL(k_nh_eig, dim3(1), dim3(NH_THREADS), 0, s, kk, Aq, Bq, two ? 1 : 0, Gw, Hw, Zw, Vw, Uw,
-                         d_lam, Wr, Wl, d_flag);
-      MF_HIP_CHECK(hipGetLastError());
-      prof_end(tok, s, K_EIG, 0.0, 0.0);
+      NhEig ew{Gw, Gw + (size_t)kk * kk, Gw + 2 * (size_t)kk * kk, Hw, Zw, Vw, Uw, part, d_flag};
+      MF_TRY(nh_eigensolve(s, kk, Aq, Bq, two, ew, d_lam, Wr, Wl, h_flag));
     }
     MF_HIP_CHECK(hipMemcpyAsync(h_lam, d_lam, kk * sizeof(c64), hipMemcpyDeviceToHost, s));
-    MF_HIP_CHECK(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_eig += ph.stop();
     if (h_flag[0] != 0) { info = -3; break; }
@@ -1306,14 +1499,10 @@ static int poly_run(mfeast_ctx* h, int p, int64_t n, const c64* As, int64_t lda,
     hipLaunchKernelGGL(k_companion, dim3((pm + 255) / 256, pm), dim3(256), 0, s, kr, p, Aq, L0, L1);
     MF_HIP_CHECK(hipGetLastError());
     {
-      const int tok = prof_begin(s);
-      hipLaunchKernelGGL(k_nh_eig, dim3(1), dim3(NH_THREADS), 0, s, pm, L0, L1, 0, Gw, Hw, Zw, Vw, Vw, d_mu, Wz,
-                         Wz, d_flag);
-      MF_HIP_CHECK(hipGetLastError());
-      prof_end(tok, s, K_EIG, 0.0, 0.0);
+      NhEig ew{Gw, Gw + (size_t)pm * pm, Gw + 2 * (size_t)pm * pm, Hw, Zw, Vw, Vw, part, d_flag};
+      MF_TRY(nh_eigensolve(s, pm, L0, L1, false, ew, d_mu, Wz, Wz, h_flag));
     }
     MF_HIP_CHECK(hipMemcpyAsync(h_mu, d_mu, pm * sizeof(c64), hipMemcpyDeviceToHost, s));
-    MF_HIP_CHECK(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     MF_HIP_CHECK(hipStreamSynchronize(s));
     t_eig += ph.stop();
     if (h_flag[0] != 0) { info = -3; break; }

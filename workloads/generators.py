@@ -180,7 +180,7 @@ def prescribed_nonnormal(n, seed, generalized=False, spread=2.0, coupling=0.3):
     return A, B, lam, V, Y
 
 
-def prescribed_polynomial(n, p, seed, leading=False, spread=2.0, coupling=0.3):
+def prescribed_polynomial(n, p, seed, leading=False, spread=2.0, coupling=0.3, vectors=True):
     """Matrix polynomial sum_k lambda^k A_k (k = 0..p) with known eigenpairs.
 
     Draw order from default_rng(seed): for t = 1..p the spectrum D_t (real parts, then
@@ -190,7 +190,8 @@ def prescribed_polynomial(n, p, seed, leading=False, spread=2.0, coupling=0.3):
     of lambda^k (L = I without leading).  Its eigenvalues are those of every S_t; for
     lambda in eig(S_t) with eigenvector v of S_t, the right eigenvector is
     x = (lambda I - S_1)^-1 ... (lambda I - S_(t-1))^-1 v.
-    Returns (As, lam (p n values, S_1's first), X (n x p n, unit columns))."""
+    Returns (As, lam (p n values, S_1's first), X (n x p n, unit columns; None with
+    vectors=False, which skips the n (p - 1) solves of large problems))."""
     rng = np.random.default_rng(seed)
     S, D, Vs = [], [], []
     for t in range(p):
@@ -213,6 +214,8 @@ def prescribed_polynomial(n, p, seed, leading=False, spread=2.0, coupling=0.3):
             new[k] -= S[t] @ Ck
         coef = new
     As = [L @ Ck for Ck in coef]
+    if not vectors:
+        return As, np.concatenate(D), None
     lam, X = [], []
     for t in range(p):
         for i in range(n):
