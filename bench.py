@@ -127,6 +127,8 @@ KERNELS = {
     "rr_gemm": ("k_gemm (FP64 Rayleigh-Ritz)", "mfma", "fp64_mfma", "one FP64 product"),
     "reduced_eig": ("k_bj_sub + k_bj_upd (block Jacobi)", "alu", "fp64_vector",
                     "one reduced eigensolve (48 m^3 flops per Jacobi sweep)"),
+    "batched_factor": ("factorization graph: k_bt_shift_form + blocked LU + panel inverses of every size class",
+                       "mfma", "fp32_mfma", "one replay: all problems and nodes (flops of the unpadded matrices)"),
 }
 
 
@@ -363,11 +365,15 @@ def bench_batched(args, mf, torch, np, gen):
         "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 solves + f64 residual/RR", "data": "synthetic",
         "config": {"workload": "128 real symmetric problems, n~U{256..2048} (seed 0), 24-48 eigenvalues each, "
-                               "M0=ceil(1.5 count), 8 Gauss nodes, 8 concurrent streams", "sum_n3": sum_n3},
+                               "M0=ceil(1.5 count), 8 Gauss nodes; all factorizations in one replayed graph "
+                               "(padded size classes), iterations on 8 concurrent streams", "sum_n3": sum_n3},
         "accuracy": {"problems_exact": exact_ok, "problems": len(probs), "max_abs_eig_err": max_err,
                      "loops": np.bincount([o["loop"] for o in outs]).tolist(), "ret": ret},
         "lu_tflops": 8.0 * (8.0 / 3.0) * sum_n3 / t / 1e12,
         "lu_tflops_kind": "algorithmic LU flops of all problems and nodes over the whole call's wall time",
+        "factor_graph_ms": prof.get("batched_factor", {}).get("ms"),
+        "factor_graph_tflops": (prof["batched_factor"]["flops"] / prof["batched_factor"]["ms"] / 1e9
+                                if prof.get("batched_factor", {}).get("ms") else None),
         "roofline": roofline,
         "roofline_next": roofline_of(prof, 1),
         "classes_ms_summed_over_problems": {c: round(v["ms"], 3) for c, v in prof.items() if v["ms"] > 0},

@@ -353,10 +353,11 @@ int mfeast_get_timing(mfeast_handle h, double* out);
  * BiCGSTAB, 7 BiCGSTAB vector updates and reductions, 8 B-orthonormalization
  * (equilibration, Cholesky with column drops, Newton-Schulz), 9 LU row interchanges,
  * U12 substitution and the inverses of the diagonal blocks and panels, 10 residual
- * norms and the B^-1 products of the found-pair test.  For the
- * batched entry point the classes are summed over all problems (their streams run
- * concurrently, so the times may add up to more than the call's wall time).
- * out: host, `count` doubles (44 cover all classes). */
+ * norms and the B^-1 products of the found-pair test, 11 the factorization graph of the
+ * batched entry point (every problem and node, one replay; flops of the unpadded
+ * matrices).  For the batched entry point the other classes are summed over all
+ * problems (their streams run concurrently, so the times may add up to more than the
+ * call's wall time).  out: host, `count` doubles (48 cover all classes). */
 int mfeast_get_profile(mfeast_handle h, double* out, int32_t count);
 
 /* Per-class timing (see mfeast_get_profile) for every later call on the handle:

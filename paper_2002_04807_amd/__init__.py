@@ -225,7 +225,7 @@ class Handle:
         return list(out)
 
     PROFILE_CLASSES = ("lu_trailing_gemm", "lu_panel", "contour_solve", "rr_gemm", "reduced_eig", "other",
-                       "bicgstab_spmv", "bicgstab_vector", "orth", "lu_rows", "resid")
+                       "bicgstab_spmv", "bicgstab_vector", "orth", "lu_rows", "resid", "batched_factor")
 
     def set_profiling(self, on=True):
         """Per-class device timing of every later call on this handle (mfeast_set_profiling)."""
@@ -462,11 +462,13 @@ def feast_eigh(A, emin, emax, m0, fpm=None, precision=1, handle=None):
     return _FEAST_EIGH.apply(A, emin, emax, m0, fpm, precision, handle)
 
 
-def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None):
-    """Many independent real symmetric problems (B = I) in one mfeast_dsygv_batched call.
+def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None, Bs=None):
+    """Many independent real symmetric problems in one mfeast_dsygv_batched call.
 
-    As: list of float64 GPU tensors (n_p x n_p, symmetric).  Returns a list of dicts
-    (info, M, m0, loop, epsout, E, X, res) and the batch wall time (handle timing)."""
+    As: list of float64 GPU tensors (n_p x n_p, symmetric); Bs: None (B = I) or a list of
+    symmetric positive definite float64 GPU tensors of the same sizes.  Returns the most
+    significant info, a list of dicts (info, M, m0, loop, epsout, E, X, res) and the batch
+    wall time (handle timing)."""
     import torch
     lib = _load()
     P = len(As)
@@ -481,6 +483,9 @@ def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None):
     R = [torch.zeros(int(m), dtype=torch.float64, device=dev) for m in m0]
     ptrs = lambda ts: (ctypes.c_void_p * P)(*[t.data_ptr() for t in ts])  # noqa: E731
     Ap = (ctypes.c_void_p * P)(*[a.data_ptr() for a, _ in Ac])
+    Bc = None if Bs is None else [colmajor(B.to(torch.float64)) for B in Bs]
+    Bp = None if Bc is None else (ctypes.c_void_p * P)(*[b.data_ptr() for b, _ in Bc])
+    ldb = None if Bc is None else np.array([ld for _, ld in Bc], dtype=np.int64)
     emin = np.ascontiguousarray(np.asarray(emins, dtype=np.float64))
     emax = np.ascontiguousarray(np.asarray(emaxs, dtype=np.float64))
     M = np.zeros(P, dtype=np.int32)
@@ -494,7 +499,8 @@ def feast_batched(As, emins, emaxs, m0s, fpm=None, handle=None):
     dp = ctypes.POINTER(ctypes.c_double)
     try:
         ret = lib.mfeast_dsygv_batched(
-            h.ptr, P, n.ctypes.data_as(i64p), Ap, lda.ctypes.data_as(i64p), None, None,
+            h.ptr, P, n.ctypes.data_as(i64p), Ap, lda.ctypes.data_as(i64p), Bp,
+            None if ldb is None else ldb.ctypes.data_as(i64p),
             fpm.ctypes.data_as(i32p), emin.ctypes.data_as(dp), emax.ctypes.data_as(dp), m0.ctypes.data_as(i32p),
             ptrs(E), ptrs(X), n.ctypes.data_as(i64p), M.ctypes.data_as(i32p), ptrs(R), eps.ctypes.data_as(dp),
             loop.ctypes.data_as(i32p), info.ctypes.data_as(i32p))

@@ -24,6 +24,8 @@ enum Slot {
   S_NH_WL, S_NH_O1, S_NH_O2, S_NH_O3, S_NH_O4, S_NH_O5, S_NH_TR, S_NH_TL,
   // polynomial driver: products with every coefficient, reduced coefficients, companion form
   S_PL_AKQ, S_PL_AKQO, S_PL_AKX, S_PL_AQ, S_PL_L0, S_PL_L1, S_PL_WZ, S_PL_G, S_PL_H, S_PL_Z, S_PL_V,
+  // batched problems: factors of every (problem, node) item, grouped in padded size classes
+  S_BT_LU, S_BT_DINV, S_BT_PANINV, S_BT_IPIV, S_BT_PERM, S_BT_PINV, S_BT_INFO, S_BT_ITEMS,
   S_NSLOTS
 };
 
@@ -86,6 +88,12 @@ struct mfeast_ctx {
   double prof[mf::K_NCLASS * 4] = {};
   bool prof_all = false;  // per-class timing of every later call (mfeast_set_profiling)
   double prof_sum[mf::K_NCLASS * 4] = {};  // batched workers: classes summed over their calls
+  // batched problems: the captured factorization of all size classes (a HIP graph), the
+  // key it was captured for (sizes, counts, buffers), one stream and event per class
+  hipGraphExec_t bt_exec = nullptr;
+  std::vector<int64_t> bt_key;
+  std::vector<hipStream_t> bt_streams;
+  std::vector<hipEvent_t> bt_events;
   // Allocation-free mode (mfeast_dsygv_noalloc): every workspace slot is carved from a
   // caller-supplied device region (a static device array), host staging uses ordinary
   // host memory, and nothing is ever freed.  A request that does not fit sets

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -304,16 +305,34 @@ struct DenseOp : Operator<T> {
   // fpm(50): extra refinement steps of the FP32 solves (FP64 solutions and residuals)
   int ir_steps = 0;
   c64 *irXf = nullptr, *irYc = nullptr, *irT = nullptr, *irAX = nullptr, *irBX = nullptr;
+  // factors supplied by the caller (LU, Pinv, perm, pinv set before prepare): those of the
+  // nf matrices padded to order nw >= n with an identity block; the solves run at order nw
+  // on right-hand sides whose rows beyond n are zero
+  bool ext = false;
+  int64_t nw = 0;
 
   DenseOp(mfeast_ctx* h_, char uplo_, int64_t n_, const T* A_, int64_t lda_, const T* B_, int64_t ldb_,
           const std::vector<c64>& z_, int m0_)
       : h(h_), uplo(uplo_), n(n_), A(A_), B(B_), lda(lda_), ldb(ldb_), z(z_), ne((int)z_.size()), m0max(m0_) {
     this->hasB = B_ != nullptr;
     nf = ne + (B_ != nullptr ? 1 : 0);
+    nw = n_;
   }
 
   int prepare(hipStream_t s) override {
     constexpr bool CPLX = is_cplx<T>::value;
+    if (ext) {
+      const size_t szC = sizeof(C);
+      Wf = (C*)h->ws(S_WF, (size_t)ne * nw * m0max * szC);
+      Wc = CPLX ? (C*)h->ws(S_WC, (size_t)ne * nw * m0max * szC) : nullptr;
+      Wy = (C*)h->ws(S_WY, (size_t)ne * nw * m0max * szC);
+      if (!Wf || (CPLX && !Wc) || !Wy || !LU || !Pinv || !perm || !pinv || ir_steps != 0 || uplo != 'F') return -2;
+      Af = A;
+      ldaf = lda;
+      Bf = B;
+      ldbf = ldb;
+      return 0;
+    }
     const int64_t nblk = (n + LU_NB - 1) / LU_NB;
     const size_t szT = sizeof(T), szC = sizeof(C);
     LU = (C*)h->ws(S_LU, (size_t)nf * n * lu_ld(n) * szC);
@@ -394,11 +413,11 @@ struct DenseOp : Operator<T> {
   // B^-1 R diag(cs) with the stored factors of B (matrix ne), then the column dots
   int binv_dots(hipStream_t s, int m, const T* R, const double* cs, double* out, double* partial) override {
     if (nf == ne) return -2;
-    const int64_t ld = lu_ld(n);
+    const int64_t ld = lu_ld(nw);
     int tok = prof_begin(s);
-    MF_TRY(rhs_prepare<T, C>(s, n, m, R, m, cs, 1, perm + (int64_t)ne * n, Wf, nullptr));
+    MF_TRY(rhs_prepare<T, C>(s, nw, m, R, m, cs, 1, perm + (int64_t)ne * nw, Wf, nullptr, n));
     prof_end(tok, s, K_RESID, 0.0, (double)n * m * (sizeof(T) + sizeof(C)));
-    MF_TRY(lu_solve<C>(s, n, m, 1, LU + (int64_t)ne * n * ld, Pinv + (size_t)ne * panel_inverse_entries(n), Wf,
+    MF_TRY(lu_solve<C>(s, nw, m, 1, LU + (int64_t)ne * nw * ld, Pinv + (size_t)ne * panel_inverse_entries(nw), Wf,
                        nullptr, Wy, nullptr, K_RESID));
     tok = prof_begin(s);
     MF_TRY(col_dots_mixed<T, C>(s, n, m, R, Wf, cs, out, partial));
@@ -418,9 +437,9 @@ struct DenseOp : Operator<T> {
     const double nb = (double)n * m;
     const int dirs = CPLX ? 2 : 1;
     int tok = prof_begin(s);
-    MF_TRY(rhs_prepare<T, C>(s, n, m, rhs, m, k.cs, ne, perm, Wf, Wc));
+    MF_TRY(rhs_prepare<T, C>(s, nw, m, rhs, m, k.cs, ne, perm, Wf, Wc, n));
     prof_end(tok, s, K_OTHER, 0.0, nb * (sizeof(T) + (double)dirs * ne * sizeof(C)));
-    MF_TRY(lu_solve<C>(s, n, m, ne, LU, Pinv, Wf, Wc, Wy, two_streams ? &side : nullptr));
+    MF_TRY(lu_solve<C>(s, nw, m, ne, LU, Pinv, Wf, Wc, Wy, two_streams ? &side : nullptr));
     if (sizeof(C) == sizeof(c32) && irXf != nullptr) {
       if constexpr (sizeof(C) == sizeof(c32)) MF_TRY(refine(s, m, rhs, k));
       tok = prof_begin(s);
@@ -429,7 +448,7 @@ struct DenseOp : Operator<T> {
       return 0;
     }
     tok = prof_begin(s);
-    MF_TRY(accumulate<T, C>(s, n, m, ne, Wf, Wc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0));
+    MF_TRY(accumulate<T, C>(s, nw, m, ne, Wf, Wc, pinv, k.cf, k.cc, k.rho, k.us, X, Q, resid ? 1 : 0, n));
     prof_end(tok, s, K_OTHER, 0.0, nb * ((double)dirs * ne * sizeof(C) + (resid ? 2.0 : 1.0) * sizeof(T)));
     return 0;
   }
@@ -1200,12 +1219,12 @@ static int run_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, dou
   return info;
 }
 
-template <typename T>
-static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
-                       int64_t ldb, int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X,
-                       int64_t ldx, int32_t* M, double* res, double* epsout, int32_t* loop, const double* zne,
-                       const double* wne) {
-  // Table tab_info order: N, M0, interval, fpm, then argument positions
+// argument checks of the dense drivers, in Table tab_info order: N, M0, interval, fpm,
+// then argument positions
+static int dense_check(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, const int32_t* fpm, double emin, double emax, const int32_t* m0, const double* E,
+                       const double* X, int64_t ldx, const int32_t* M, const double* res, const double* epsout,
+                       const int32_t* loop, const double* zne, const double* wne) {
   if (n < 1 || n > MAX_DENSE_N) return 202;
   if (m0 == nullptr) return -111;
   if (*m0 < 1 || *m0 > n || *m0 > MAX_M0) return 201;
@@ -1226,6 +1245,17 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   if (res == nullptr) return -116;
   if (epsout == nullptr) return -117;
   if (loop == nullptr) return -118;
+  return 0;
+}
+
+template <typename T>
+static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda, const double* B,
+                       int64_t ldb, int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X,
+                       int64_t ldx, int32_t* M, double* res, double* epsout, int32_t* loop, const double* zne,
+                       const double* wne) {
+  const int chk = dense_check(h, uplo, n, A, lda, B, ldb, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop,
+                              zne, wne);
+  if (chk) return chk;
   if (hipSetDevice(h->device) != hipSuccess) return -900;
   GemmScratchScope scratch_scope(h);
   const T* At = reinterpret_cast<const T*>(A);
@@ -1242,6 +1272,271 @@ static int dense_entry(mfeast_handle h, char uplo, int64_t n, const double* A, i
   }
   DenseOp<T, c64> op(h, uplo, n, At, lda, Bt, ldb, z, *m0);
   return run_loop<T>(h, op, n, fpm, emin, emax, m0, E, Xt, ldx, M, res, epsout, loop, z, w, c_inf);
+}
+
+// ---------------------------------------------------------------------------
+// Batched problems (the first level of parallelism of Section 1.1, independent problems):
+// the factorizations of every (problem, node) item as one captured launch sequence.  The
+// items are grouped into size classes (order rounded up to a multiple of 256); each matrix
+// is padded to its class order with an identity block, so that the factors of the padded
+// matrix are those of the problem's matrix in the leading block, and every class is a
+// uniform batch for the blocked LU.  The classes run as parallel branches of one HIP graph,
+// captured once per set of sizes and buffers (after an ordinary run of the same launches
+// with the GEMM tile autotuner on) and replayed by later calls.  The subspace iterations
+// of each problem then solve with its stored factors at the class order.
+struct BtItem {
+  const double* A;
+  const double* B;
+  int64_t lda, ldb, n;
+  double zre, zim;
+  int kind;  // 0: z B - A (B = I when null), 1: B itself
+  int pad_;
+};
+
+template <typename C>
+__global__ void k_bt_shift_form(int64_t nw, int64_t ld, const BtItem* __restrict__ items, C* __restrict__ LU,
+                                int* __restrict__ perm, int* __restrict__ info) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  const int q = blockIdx.z;
+  if (c >= nw) return;
+  const BtItem it = items[q];
+  c64 v(i == c ? 1.0 : 0.0, 0.0);
+  if (i < it.n && c < it.n) {
+    // real symmetric, column-major: element (i, c) read as A[i lda + c] (coalesced)
+    const double a = it.A[i * it.lda + c];
+    const double b = it.B != nullptr ? it.B[i * it.ldb + c] : (i == c ? 1.0 : 0.0);
+    v = it.kind ? c64(b, 0.0) : c64(it.zre * b - a, it.zim * b);
+  }
+  LU[(int64_t)q * nw * ld + i * ld + c] = convert<C, c64>(v);
+  if (i == 0) {
+    perm[(int64_t)q * nw + c] = (int)c;
+    if (c == 0) info[q] = 0;
+  }
+}
+
+constexpr int64_t BT_CLASS = 256;
+
+template <typename C>
+struct BtFactors {
+  int64_t nw = 0;
+  C* LU = nullptr;
+  C* Pinv = nullptr;
+  int* perm = nullptr;
+  int* pinv = nullptr;
+};
+
+struct BtClass {
+  int64_t nw;
+  int items, item0;
+  size_t lu, dinv, pinv, ints;
+};
+
+template <typename C>
+static int bt_class_launches(hipStream_t s, const BtClass& k, C* LU, C* Dinv, C* Pinv, int* ipiv, int* perm,
+                             int* pinv, int* info, const BtItem* items) {
+  const int64_t ld = lu_ld(k.nw);
+  hipLaunchKernelGGL((k_bt_shift_form<C>), dim3((unsigned)((k.nw + 255) / 256), (unsigned)k.nw, (unsigned)k.items),
+                     dim3(256), 0, s, k.nw, ld, items + k.item0, LU + k.lu, perm + k.ints, info + k.item0);
+  MF_HIP_CHECK(hipGetLastError());
+  MF_TRY(lu_factor<C>(s, k.nw, k.items, LU + k.lu, ipiv + k.ints, perm + k.ints, pinv + k.ints, info + k.item0,
+                      Dinv + k.dinv));
+  MF_TRY(panel_inverses<C>(s, k.nw, k.items, LU + k.lu, Dinv + k.dinv, Pinv + k.pinv));
+  return 0;
+}
+
+// state[p]: 0 = not factored here (the problem runs the ordinary path), 1 = factored
+// (fac[p] holds its factors), 2 = finished with info[p] (a singular shifted matrix or B)
+template <typename C>
+static int bt_factor(mfeast_handle h, int32_t nprob, const int64_t* n, const double* const* A, const int64_t* lda,
+                     const double* const* B, const int64_t* ldb, const int32_t* fpm, const double* emin,
+                     const double* emax, int32_t* m0, double* const* E, double* const* X, const int64_t* ldx,
+                     int32_t* M, double* const* res, double* epsout, int32_t* loop, int32_t* info,
+                     std::vector<int>& state, std::vector<BtFactors<C>>& fac, double& t_fact) {
+  state.assign(nprob, 0);
+  fac.assign(nprob, BtFactors<C>());
+  t_fact = 0.0;
+  if (fpm[49] != 0) return 0;  // fpm(50) refinement re-forms the shifted matrices per problem
+  const int ne = fpm[1];
+  std::vector<int> nf(nprob, 0);
+  std::map<int64_t, std::vector<int>> byclass;
+  for (int p = 0; p < nprob; ++p) {
+    const double* Bp = B ? B[p] : nullptr;
+    const int64_t ldbp = B ? ldb[p] : n[p];
+    if (dense_check(h, 'F', n[p], A[p], lda[p], Bp, ldbp, fpm, emin[p], emax[p], &m0[p], E[p], X[p], ldx[p], &M[p],
+                    res[p], &epsout[p], &loop[p], nullptr, nullptr) != 0)
+      continue;
+    nf[p] = ne + (Bp != nullptr ? 1 : 0);
+    byclass[(n[p] + BT_CLASS - 1) / BT_CLASS * BT_CLASS].push_back(p);
+  }
+  if (byclass.empty()) return 0;
+  // classes, largest first; item tables and buffer offsets
+  std::vector<BtClass> cls;
+  std::vector<BtItem> items;
+  std::vector<int> first(nprob, -1);
+  size_t lu = 0, dinv = 0, pinvs = 0, ints = 0;
+  for (auto it = byclass.rbegin(); it != byclass.rend(); ++it) {
+    BtClass k{it->first, 0, (int)items.size(), lu, dinv, pinvs, ints};
+    for (int p : it->second) {
+      std::vector<c64> z, w;
+      double c_inf = 0.0;
+      nodes_for(fpm, emin[p], emax[p], nullptr, nullptr, z, w, c_inf);
+      first[p] = (int)items.size();
+      const double* Bp = B ? B[p] : nullptr;
+      const int64_t ldbp = B ? ldb[p] : n[p];
+      for (int j = 0; j < ne; ++j) items.push_back(BtItem{A[p], Bp, lda[p], ldbp, n[p], z[j].re, z[j].im, 0, 0});
+      if (Bp != nullptr) items.push_back(BtItem{A[p], Bp, lda[p], ldbp, n[p], 0.0, 0.0, 1, 0});
+      k.items += nf[p];
+    }
+    const int64_t nblk = (k.nw + LU_NB - 1) / LU_NB;
+    lu += (size_t)k.items * k.nw * lu_ld(k.nw);
+    dinv += (size_t)k.items * nblk * 2 * LU_NB * LU_NB;
+    pinvs += (size_t)k.items * panel_inverse_entries(k.nw);
+    ints += (size_t)k.items * k.nw;
+    cls.push_back(k);
+  }
+  const int nitems = (int)items.size();
+  C* LU = (C*)h->ws(S_BT_LU, lu * sizeof(C));
+  C* Dinv = (C*)h->ws(S_BT_DINV, dinv * sizeof(C));
+  C* Pinv = (C*)h->ws(S_BT_PANINV, pinvs * sizeof(C));
+  int* ipiv = (int*)h->ws(S_BT_IPIV, ints * 4);
+  int* perm = (int*)h->ws(S_BT_PERM, ints * 4);
+  int* pinv = (int*)h->ws(S_BT_PINV, ints * 4);
+  int* dinfo = (int*)h->ws(S_BT_INFO, (size_t)nitems * 4);
+  BtItem* ditems = (BtItem*)h->ws(S_BT_ITEMS, (size_t)nitems * sizeof(BtItem));
+  if (!LU || !Dinv || !Pinv || !ipiv || !perm || !pinv || !dinfo || !ditems) return -2;
+  hipStream_t s = h->stream;
+  MF_HIP_CHECK(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(BtItem), hipMemcpyHostToDevice, s));
+  // the graph depends on the sizes, the counts, the buffers and the product scheme
+  std::vector<int64_t> key = {(int64_t)sizeof(C), (int64_t)gemm_3m(), (int64_t)(intptr_t)LU, (int64_t)(intptr_t)Dinv,
+                              (int64_t)(intptr_t)Pinv, (int64_t)(intptr_t)ipiv, (int64_t)(intptr_t)perm,
+                              (int64_t)(intptr_t)pinv, (int64_t)(intptr_t)dinfo, (int64_t)(intptr_t)ditems};
+  for (const BtClass& k : cls) {
+    key.push_back(k.nw);
+    key.push_back(k.items);
+  }
+  GemmScratchScope scratch_scope(h);
+  const bool prof_was = prof_on();
+  prof_enable(false);
+  // streams: [0] the origin of the graph (owned, so that capture never touches the
+  // caller's stream), [1..] one per class; events: [0] fork, [1..] class joins, then the
+  // hand-over from the caller's stream and back
+  const size_t nc = cls.size();
+  int rc = 0;
+  while (rc == 0 && h->bt_streams.size() < nc + 1) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      rc = -2;
+      break;
+    }
+    h->bt_streams.push_back(st);
+  }
+  while (rc == 0 && h->bt_events.size() < nc + 3) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      rc = -2;
+      break;
+    }
+    h->bt_events.push_back(e);
+  }
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (rc == 0 && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)) rc = -2;
+  hipStream_t o = rc == 0 ? h->bt_streams[0] : nullptr;
+  hipEvent_t ev_in = rc == 0 ? h->bt_events[nc + 1] : nullptr, ev_out = rc == 0 ? h->bt_events[nc + 2] : nullptr;
+  if (rc == 0 && (hipEventRecord(ev_in, s) != hipSuccess || hipStreamWaitEvent(o, ev_in, 0) != hipSuccess ||
+                  hipEventRecord(t0, o) != hipSuccess))
+    rc = -2;
+  if (rc == 0 && h->bt_exec != nullptr && h->bt_key == key) {
+    if (hipGraphLaunch(h->bt_exec, o) != hipSuccess) rc = -2;
+    if (rc == 0 && hipEventRecord(t1, o) != hipSuccess) rc = -2;
+  } else if (rc == 0) {
+    if (h->bt_exec != nullptr) (void)hipGraphExecDestroy(h->bt_exec);
+    h->bt_exec = nullptr;
+    h->bt_key.clear();
+    // this call's factorization, with the tile autotuner on (it synchronizes per new class)
+    set_gemm_tuning(true);
+    for (const BtClass& k : cls)
+      if (rc == 0) rc = bt_class_launches<C>(o, k, LU, Dinv, Pinv, ipiv, perm, pinv, dinfo, ditems);
+    set_gemm_tuning(false);
+    if (rc == 0 && hipEventRecord(t1, o) != hipSuccess) rc = -2;
+    // the same launches captured for later calls: one branch per class
+    if (rc == 0 && hipStreamBeginCapture(o, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      int crc = hipEventRecord(h->bt_events[0], o) == hipSuccess ? 0 : -2;
+      for (size_t c = 0; c < nc && crc == 0; ++c) {
+        hipStream_t st = h->bt_streams[c + 1];
+        if (hipStreamWaitEvent(st, h->bt_events[0], 0) != hipSuccess) crc = -2;
+        if (crc == 0) crc = bt_class_launches<C>(st, cls[c], LU, Dinv, Pinv, ipiv, perm, pinv, dinfo, ditems);
+        if (crc == 0 && hipEventRecord(h->bt_events[c + 1], st) != hipSuccess) crc = -2;
+        if (crc == 0 && hipStreamWaitEvent(o, h->bt_events[c + 1], 0) != hipSuccess) crc = -2;
+      }
+      hipGraph_t graph = nullptr;
+      const bool ended = hipStreamEndCapture(o, &graph) == hipSuccess;
+      if (crc == 0 && ended && graph != nullptr &&
+          hipGraphInstantiate(&h->bt_exec, graph, nullptr, nullptr, 0) == hipSuccess)
+        h->bt_key = key;
+      else
+        h->bt_exec = nullptr;
+      if (graph != nullptr) (void)hipGraphDestroy(graph);
+    }
+  }
+  if (o != nullptr && (hipEventRecord(ev_out, o) != hipSuccess || hipStreamWaitEvent(s, ev_out, 0) != hipSuccess))
+    rc = -2;
+  std::vector<int> hinfo(nitems);
+  if (rc == 0 && hipMemcpyAsync(hinfo.data(), dinfo, (size_t)nitems * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    rc = -2;
+  if (hipStreamSynchronize(s) != hipSuccess) rc = -2;
+  float ms = 0.0f;
+  if (rc == 0) (void)hipEventElapsedTime(&ms, t0, t1);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  prof_enable(prof_was);
+  t_fact = ms * 1e-3;
+  if (rc != 0) return rc;
+  for (const BtClass& k : cls) {
+    const int64_t ld = lu_ld(k.nw);
+    int q = 0;
+    for (int p : byclass[k.nw]) {
+      bool shift_ok = true, b_ok = true;
+      for (int j = 0; j < nf[p]; ++j) {
+        if (hinfo[first[p] + j] != 0) (j < ne ? shift_ok : b_ok) = false;
+      }
+      if (!shift_ok || !b_ok) {
+        info[p] = !shift_ok ? -2 : -3;
+        state[p] = 2;
+      } else {
+        state[p] = 1;
+        BtFactors<C>& f = fac[p];
+        f.nw = k.nw;
+        f.LU = LU + k.lu + (size_t)q * k.nw * ld;
+        f.Pinv = Pinv + k.pinv + (size_t)q * panel_inverse_entries(k.nw);
+        f.perm = perm + k.ints + (size_t)q * k.nw;
+        f.pinv = pinv + k.ints + (size_t)q * k.nw;
+      }
+      q += nf[p];
+    }
+  }
+  return 0;
+}
+
+// one batched problem with its stored factors
+template <typename C>
+static int dense_entry_ext(mfeast_handle h, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+                           int32_t* fpm, double emin, double emax, int32_t* m0, double* E, double* X, int64_t ldx,
+                           int32_t* M, double* res, double* epsout, int32_t* loop, const BtFactors<C>& f) {
+  if (hipSetDevice(h->device) != hipSuccess) return -900;
+  GemmScratchScope scratch_scope(h);
+  std::vector<c64> z, w;
+  double c_inf = 0.0;
+  nodes_for(fpm, emin, emax, nullptr, nullptr, z, w, c_inf);
+  set_gemm_3m(fpm[52] == 0);
+  DenseOp<double, C> op(h, 'F', n, A, lda, B, ldb, z, *m0);
+  op.ext = true;
+  op.nw = f.nw;
+  op.LU = f.LU;
+  op.Pinv = f.Pinv;
+  op.perm = f.perm;
+  op.pinv = f.pinv;
+  return run_loop<double>(h, op, n, fpm, emin, emax, m0, E, X, ldx, M, res, epsout, loop, z, w, c_inf);
 }
 
 static int csr_entry(mfeast_handle h, char uplo, int64_t n, const double* a, const int32_t* ia, const int32_t* ja,
@@ -1344,6 +1639,9 @@ int mfeast_destroy(mfeast_handle h) {
     (void)mfeast_destroy(w);
   }
   h->workers.clear();
+  if (h->bt_exec) (void)hipGraphExecDestroy(h->bt_exec);
+  for (hipEvent_t e : h->bt_events) (void)hipEventDestroy(e);
+  for (hipStream_t st : h->bt_streams) (void)hipStreamDestroy(st);
   for (int i = 0; i < S_NSLOTS; ++i)
     if (h->buf[i]) (void)hipFree(h->buf[i]);
   h->csrA.release();
@@ -1522,6 +1820,24 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
     w->owns_stream = true;
     h->workers.push_back(w);
   }
+  // the factorizations of every problem and node first, in padded size classes (one graph)
+  int32_t fb[64];
+  for (int i = 0; i < 64; ++i) fb[i] = fpm[i];
+  const bool fp32 = fpm[41] == 1;
+  const bool prof_req = fpm[51] == 1 || h->prof_all;
+  std::vector<int> state;
+  std::vector<BtFactors<c32>> fac32;
+  std::vector<BtFactors<c64>> fac64;
+  double t_fact = 0.0;
+  set_gemm_3m(fpm[52] == 0);
+  const int brc = fp32 ? bt_factor<c32>(h, nprob, n, A, lda, B, ldb, fb, emin, emax, m0, E, X, ldx, M, res, epsout,
+                                        loop, info, state, fac32, t_fact)
+                       : bt_factor<c64>(h, nprob, n, A, lda, B, ldb, fb, emin, emax, m0, E, X, ldx, M, res, epsout,
+                                        loop, info, state, fac64, t_fact);
+  if (brc != 0) state.assign(nprob, 0);
+  double fact_flops = 0.0;
+  for (int p = 0; p < nprob; ++p)
+    if (state[p] != 0) fact_flops += (fpm[1] + (B && B[p] ? 1 : 0)) * (8.0 / 3.0) * (double)n[p] * n[p] * n[p];
   // largest problems first
   std::vector<int> order(nprob);
   for (int p = 0; p < nprob; ++p) order[p] = p;
@@ -1541,8 +1857,15 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
       f[51] = (fpm[51] == 1 || h->prof_all) ? 1 : 0;
       const double* Bp = B ? B[p] : nullptr;
       const int64_t ldbp = B ? ldb[p] : n[p];
-      info[p] = dense_entry<double>(w, 'F', n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p], X[p],
-                                    ldx[p], &M[p], res[p], &epsout[p], &loop[p], nullptr, nullptr);
+      if (state[p] == 2) continue;
+      if (state[p] == 1)
+        info[p] = fp32 ? dense_entry_ext<c32>(w, n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p],
+                                              X[p], ldx[p], &M[p], res[p], &epsout[p], &loop[p], fac32[p])
+                       : dense_entry_ext<c64>(w, n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p],
+                                              X[p], ldx[p], &M[p], res[p], &epsout[p], &loop[p], fac64[p]);
+      else
+        info[p] = dense_entry<double>(w, 'F', n[p], A[p], lda[p], Bp, ldbp, f, emin[p], emax[p], &m0[p], E[p], X[p],
+                                      ldx[p], &M[p], res[p], &epsout[p], &loop[p], nullptr, nullptr);
       for (int i = 0; i < K_NCLASS * 4; ++i) w->prof_sum[i] += w->prof[i];
     }
     (void)hipStreamSynchronize(w->stream);
@@ -1557,12 +1880,18 @@ int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const
   for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
   for (int wi = 0; wi < nw; ++wi)
     for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] += h->workers[wi]->prof_sum[i];
+  if (prof_req && fact_flops > 0.0) {
+    h->prof[K_BT_FACT * 4 + 0] = 1.0;
+    h->prof[K_BT_FACT * 4 + 1] = t_fact * 1e3;
+    h->prof[K_BT_FACT * 4 + 2] = fact_flops;
+  }
   int worst = 0;
   for (int p = 0; p < nprob; ++p)
     if (info[p] < 0 && (worst >= 0 || info[p] < worst)) worst = info[p];
   if (worst == 0)
     for (int p = 0; p < nprob; ++p) worst = std::max(worst, (int)info[p]);
   for (int i = 0; i < 8; ++i) h->timing[i] = 0.0;
+  h->timing[0] = t_fact;
   h->timing[5] = total.stop();
   h->timing[6] = (double)nprob;
   return worst;

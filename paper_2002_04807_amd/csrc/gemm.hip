@@ -16,6 +16,8 @@
 // n x M0) split K over several workgroups per tile: each writes its partial tile to a
 // scratch buffer and a second kernel adds the partials in split order (deterministic).
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -383,6 +385,90 @@ static thread_local bool g_3m = true;
 void set_gemm_3m(bool on) { g_3m = on; }
 bool gemm_3m() { return g_3m; }
 
+// ---------------------------------------------------------------------------
+// tile autotuner (see kernels.hpp)
+namespace {
+std::mutex g_tune_mu;
+std::map<uint64_t, int> g_tune;  // size class -> tile index
+thread_local bool g_tune_on = false;
+
+int bucket(int64_t v) {
+  int b = 0;
+  while (b < 31 && (int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+uint64_t tune_key(int rbytes, bool cplx, bool g3m, const GemmArgs& g, int batch) {
+  return (uint64_t)rbytes | ((uint64_t)cplx << 4) | ((uint64_t)g3m << 5) | ((uint64_t)bucket(g.M) << 8) |
+         ((uint64_t)bucket(g.N) << 16) | ((uint64_t)bucket(g.K) << 24) | ((uint64_t)bucket(batch) << 32);
+}
+}  // namespace
+
+void set_gemm_tuning(bool on) { g_tune_on = on; }
+int gemm_tuned_classes() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB, int TBK, bool G3M>
+static void launch_tile_choice(int tile, const GemmArgs& g, int batch, hipStream_t s) {
+  switch (tile) {
+    case 1: launch_tile<R, CPLX, AM, CJ, BK_, CJB, 32, 64, TBK, G3M>(g, batch, s); return;
+    case 2: launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 32, TBK, G3M>(g, batch, s); return;
+    case 3: launch_tile<R, CPLX, AM, CJ, BK_, CJB, 32, 32, TBK, G3M>(g, batch, s); return;
+    default: launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, G3M>(g, batch, s); return;
+  }
+}
+
+// tile for an LU trailing update: the cached choice of its class; on a miss with tuning on,
+// each candidate runs twice on a scratch output (at most 8 batch entries) and the second
+// run is timed
+template <typename R, bool CPLX, bool TBK_, int TBK, bool G3M>
+static int tuned_tile(const GemmArgs& g, int batch, hipStream_t s) {
+  const uint64_t key = tune_key((int)sizeof(R), CPLX, G3M, g, batch);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  if (!g_tune_on) return 0;
+  constexpr int ES = CPLX ? 2 : 1;
+  const int bt = std::min(batch, 8);
+  R* out = static_cast<R*>(splitk_scratch((size_t)bt * g.M * g.N * ES * sizeof(R)));
+  if (out == nullptr) return 0;
+  GemmArgs t = g;
+  t.C = out;
+  t.ldc = g.N;
+  t.c_bs = (int64_t)g.M * g.N;
+  t.beta = 0.0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 0;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int tile = 0; tile < 4; ++tile) {
+    launch_tile_choice<R, CPLX, false, false, false, false, TBK, G3M>(tile, t, bt, s);
+    (void)hipEventRecord(e0, s);
+    launch_tile_choice<R, CPLX, false, false, false, false, TBK, G3M>(tile, t, bt, s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (tile == 0 || ms < best_ms) {
+      best = tile;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
 template <typename R, bool CPLX, bool AM, bool CJ, bool BK_, bool CJB>
 static void launch(const GemmArgs& g, int batch, hipStream_t s) {
   constexpr int BK = 16;
@@ -412,6 +498,21 @@ static void launch(const GemmArgs& g, int batch, hipStream_t s) {
   }
   // 8-deep K slabs for FP32 (measured 3-7% faster there), 16-deep for FP64
   constexpr int TBK = sizeof(R) == 4 ? 8 : 16;
+  // LU trailing updates: the autotuned tile of their size class
+  if constexpr (CPLX && !AM && !CJ && !BK_ && !CJB) {
+    if (g.tag == 1) {
+      if constexpr (sizeof(R) == 4) {
+        if (g_3m) {
+          const int tile = tuned_tile<R, CPLX, false, TBK, true>(g, batch, s);
+          launch_tile_choice<R, CPLX, AM, CJ, BK_, CJB, TBK, true>(tile, g, batch, s);
+          return;
+        }
+      }
+      const int tile = tuned_tile<R, CPLX, false, TBK, false>(g, batch, s);
+      launch_tile_choice<R, CPLX, AM, CJ, BK_, CJB, TBK, false>(tile, g, batch, s);
+      return;
+    }
+  }
   if constexpr (CPLX && sizeof(R) == 4) {
     if (g_3m) {
       launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, true>(g, batch, s);

@@ -43,6 +43,15 @@ void set_gemm_scratch(ScratchFn fn, void* owner);
 // (default on; fpm(53) = 1 selects the four-product scheme for a call)
 void set_gemm_3m(bool on);
 bool gemm_3m();
+// Tile autotuner for the LU trailing updates (products with tag 1): while tuning is on
+// for the calling host thread, the first product of each size class (element type,
+// scheme, log2 buckets of M, N, K and batch) times the 64x64, 32x64, 64x32 and 32x32
+// tiles on a scratch output (synchronizing the stream) and keeps the fastest for the
+// process; later products of the class use it, tuning on or off.  The tile does not
+// change the order of the K sums, so every choice gives the same results.
+void set_gemm_tuning(bool on);
+// number of size classes tuned so far, and the tile index chosen for the last one tuned
+int gemm_tuned_classes();
 
 // ------------------------------------------------------------------ LU
 constexpr int LU_NB = 64;  // outer panel width of the blocked LU and of the blocked solves
@@ -82,9 +91,11 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
 // Build per-node right-hand sides W_j (row-major n x m, type C) from an FP64 block RHS
 // (row-major, ld), each column multiplied by colscale[c]; forward blocks are gathered
 // with perm_j (W_j[i] = RHS[perm_j[i]]), conjugate-transpose blocks are not permuted.
+// With nreal < n the factors are those of a matrix padded with an identity block: RHS
+// has nreal rows and the rows beyond are zero.
 template <typename T, typename C>
 int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const double* colscale,
-                int ne, const int* perm, C* Wf, C* Wc);
+                int ne, const int* perm, C* Wf, C* Wc, int64_t nreal = -1);
 
 // Inverses of the diagonal blocks of L and U over panels of 4 LU_NB rows, formed once
 // per factorization from LU and Dinv; panel_inverse_entries(n) entries of C per node.
@@ -127,10 +138,11 @@ int col_dots_mixed(hipStream_t s, int64_t n, int m, const T* R, const C* X, cons
                    double* partial);
 
 // Q = (resid ? X*diag(rho) : 0) + diag-scaled sum over nodes (see accumulate in solve.hip).
+// With nreal < n (padded factors, see rhs_prepare) only the first nreal rows of Q are formed.
 template <typename T, typename C>
 int accumulate(hipStream_t s, int64_t n, int m, int ne, const C* Wf, const C* Wc, const int* perm_inv,
                const c64* coef_f, const c64* coef_c, const double* rho, const double* unscale,
-               const T* X, T* Q, int resid);
+               const T* X, T* Q, int resid, int64_t nreal = -1);
 
 // ------------------------------------------------------------------ Rayleigh-Ritz helpers
 template <typename T>

@@ -22,7 +22,8 @@ enum KClass {
   K_ORTH = 8,      // B-orthonormalization: equilibration, Cholesky with drops, Newton-Schulz
   K_LU_ROWS = 9,   // LU row interchanges, U12 substitution, diagonal-block and panel inverses
   K_RESID = 10,    // residual norms and the B^-1 products of the found-pair test
-  K_NCLASS = 11
+  K_BT_FACT = 11,  // batched problems: the factorization graph of every (problem, node) item
+  K_NCLASS = 12
 };
 
 bool prof_on();

@@ -14,29 +14,30 @@ namespace mf {
 template <typename T, typename C>
 __global__ void k_rhs_prepare(int64_t n, int m, const T* __restrict__ rhs, int64_t ld,
                               const double* __restrict__ cs, int ne, const int* __restrict__ perm,
-                              C* __restrict__ Wf, C* __restrict__ Wc) {
+                              C* __restrict__ Wf, C* __restrict__ Wc, int64_t nreal) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = blockIdx.y;
   if (c >= m) return;
   const double sc = cs[c];
   const int64_t blk = n * (int64_t)m;
   if (Wc != nullptr) {
-    const T v = rhs[i * ld + c];
-    const C cv = convert<C, c64>(convert<c64, T>(v) * c64(sc, 0.0));
+    const c64 v = i < nreal ? convert<c64, T>(rhs[i * ld + c]) : c64(0.0, 0.0);
+    const C cv = convert<C, c64>(v * c64(sc, 0.0));
     for (int j = 0; j < ne; ++j) Wc[j * blk + i * m + c] = cv;
   }
   for (int j = 0; j < ne; ++j) {
     const int64_t src = perm[(int64_t)j * n + i];
-    const T v = rhs[src * ld + c];
-    Wf[j * blk + i * m + c] = convert<C, c64>(convert<c64, T>(v) * c64(sc, 0.0));
+    const c64 v = src < nreal ? convert<c64, T>(rhs[src * ld + c]) : c64(0.0, 0.0);
+    Wf[j * blk + i * m + c] = convert<C, c64>(v * c64(sc, 0.0));
   }
 }
 
 template <typename T, typename C>
 int rhs_prepare(hipStream_t s, int64_t n, int m, const T* rhs, int64_t ld, const double* colscale,
-                int ne, const int* perm, C* Wf, C* Wc) {
+                int ne, const int* perm, C* Wf, C* Wc, int64_t nreal) {
   dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
-  hipLaunchKernelGGL((k_rhs_prepare<T, C>), grid, dim3(256), 0, s, n, m, rhs, ld, colscale, ne, perm, Wf, Wc);
+  hipLaunchKernelGGL((k_rhs_prepare<T, C>), grid, dim3(256), 0, s, n, m, rhs, ld, colscale, ne, perm, Wf, Wc,
+                     nreal < 0 ? n : nreal);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -344,8 +345,8 @@ __global__ void k_accumulate(int64_t n, int m, int ne, const C* __restrict__ Wf,
 template <typename T, typename C>
 int accumulate(hipStream_t s, int64_t n, int m, int ne, const C* Wf, const C* Wc, const int* perm_inv,
                const c64* coef_f, const c64* coef_c, const double* rho, const double* unscale,
-               const T* X, T* Q, int resid) {
-  dim3 grid((unsigned)((m + 255) / 256), (unsigned)n);
+               const T* X, T* Q, int resid, int64_t nreal) {
+  dim3 grid((unsigned)((m + 255) / 256), (unsigned)(nreal < 0 ? n : nreal));
   hipLaunchKernelGGL((k_accumulate<T, C>), grid, dim3(256), 0, s, n, m, ne, Wf, Wc, perm_inv, coef_f,
                      coef_c, rho, unscale, X, Q, resid);
   return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -423,20 +424,20 @@ template int ir_residual<double, c32>(hipStream_t, int64_t, int, int, const doub
 template int ir_residual<c64, c32>(hipStream_t, int64_t, int, int, const c64*, int64_t, const double*, const c64*,
                                    bool, const int*, const c64*, const c64*, c32*);
 
-template int rhs_prepare<double, c32>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c32*, c32*);
-template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c64*, c64*);
-template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*);
-template int rhs_prepare<c64, c64>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c64*, c64*);
+template int rhs_prepare<double, c32>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c32*, c32*, int64_t);
+template int rhs_prepare<double, c64>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, c64*, c64*, int64_t);
+template int rhs_prepare<c64, c32>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c32*, c32*, int64_t);
+template int rhs_prepare<c64, c64>(hipStream_t, int64_t, int, const c64*, int64_t, const double*, int, const int*, c64*, c64*, int64_t);
 template int lu_solve<c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, c32*, c32*, c32*,
                           const SolveSide<c32>*, int);
 template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, c64*, c64*, c64*,
                           const SolveSide<c64>*, int);
 template int panel_inverses<c32>(hipStream_t, int64_t, int, const c32*, const c32*, c32*);
 template int panel_inverses<c64>(hipStream_t, int64_t, int, const c64*, const c64*, c64*);
-template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
-template int accumulate<double, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int);
-template int accumulate<c64, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int);
-template int accumulate<c64, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int);
+template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int, int64_t);
+template int accumulate<double, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int, int64_t);
+template int accumulate<c64, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int, int64_t);
+template int accumulate<c64, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int, int64_t);
 
 template int col_dots_mixed<double, c32>(hipStream_t, int64_t, int, const double*, const c32*, const double*,
                                          double*, double*);
