@@ -248,11 +248,20 @@ int mfeast_zgepev(mfeast_handle h, int32_t p, int64_t n, const double* A, int64_
  * arguments of mfeast_dsygv as arrays over nprob problems.  n, lda, ldb, ldx, emin, emax,
  * m0 (in/out), M, epsout, loop, info are host arrays of nprob entries; A, B, E, X, res are
  * host arrays of nprob device pointers (B may be NULL for B = I everywhere, or hold NULL
- * entries); fpm (64 entries) is shared.  Problems are spread, largest first, over
- * concurrent streams of the handle's device (one host worker thread each, 8 by default,
- * MFEAST_BATCH_STREAMS in the environment overrides); cooperative kernels are not used in
- * this mode.  info[p] is problem p's code; the return value is the most negative code,
- * else the largest positive one, else 0, or -(100+i) for an invalid argument i. */
+ * entries); fpm (64 entries) is shared.  First the shifted matrices of every problem and
+ * node (and B) are formed and factored together: grouped in size classes (the order
+ * rounded up to a multiple of 256, padded with an identity block), each class one batched
+ * blocked LU, all classes as parallel branches of one HIP graph that the handle captures at
+ * the first call with a given set of sizes and keeps for later calls with the same sizes
+ * (the first call also tunes the GEMM tiles of the LU updates; the handle's device memory
+ * holds all factors at once).  Then the problems iterate, largest first, on concurrent
+ * streams of the handle's device (one host worker thread each, 8 by default,
+ * MFEAST_BATCH_STREAMS in the environment overrides), solving with the stored factors;
+ * cooperative kernels are not used in this mode.  With fpm(50) > 0 every problem factors
+ * its own matrices instead.  info[p] is problem p's code; the return value is the most
+ * negative code, else the largest positive one, else 0, or -(100+i) for an invalid
+ * argument i.  mfeast_get_timing: [0] the factorization of all problems, [5] the call,
+ * [6] nprob. */
 int mfeast_dsygv_batched(mfeast_handle h, int32_t nprob, const int64_t* n, const double* const* A,
                          const int64_t* lda, const double* const* B, const int64_t* ldb,
                          const int32_t* fpm, const double* emin, const double* emax, int32_t* m0,
