@@ -30,7 +30,7 @@ METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res
 TRAFFIC = {
     "contour_solve": {"bytes": 14.05e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "c3fcf19cca226602"},
+                      "sha256_16": "95d87b85e37b624c"},
     "reduced_eig": {"bytes": 3.73e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip"],
                     "sha256_16": "6da79370437ec863"},
