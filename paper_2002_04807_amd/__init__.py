@@ -211,8 +211,10 @@ class Handle:
 
     def __del__(self):
         # no HIP call while the interpreter shuts down: the runtime (and a profiler's tool
-        # library) may already be finalized; the process exit releases the device memory
-        if sys.is_finalizing():
+        # library) may already be finalized; the process exit releases the device memory.
+        # A closed handle has nothing to release (and at shutdown the module globals,
+        # sys included, may already be gone).
+        if getattr(self, "ptr", None) is None or sys is None or sys.is_finalizing():
             return
         try:
             self.close()
