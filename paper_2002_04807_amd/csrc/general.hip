@@ -420,6 +420,26 @@ __global__ void k_eye(int m, c64* __restrict__ Z) {
   Z[e] = c64(e / m == e % m ? 1.0 : 0.0, 0.0);
 }
 
+// A window's rotations applied to one segment v[0..nrot] (loaded by the caller): rotation r
+// acts as [c s; -conj(s) c] on (v_r, v_r+1), with s replaced by conj(s) for a column segment
+// (rotations applied from the right)
+__device__ inline void qr_rotate_segment(c64 (&v)[QW + 1], int nrot, bool cols, const double* __restrict__ rc,
+                                         const c64* __restrict__ rs) {
+#pragma unroll
+  for (int r = 0; r < QW; ++r) {
+    // the rotations' LDS reads are issued four at a time (hoisting all of them would hold
+    // 6 QW registers and spill)
+    if ((r & 3) == 0) __asm__ volatile("" ::: "memory");
+    if (r < nrot) {
+      const double cc = rc[r];
+      const c64 ss = cols ? conj(rs[r]) : rs[r];
+      const c64 xa = v[r], yb = v[r + 1];
+      v[r] = cc * xa + ss * yb;
+      v[r + 1] = cc * yb - conj(ss) * xa;
+    }
+  }
+}
+
 // shifted QR: H (in: upper Hessenberg; out: the Schur form T, upper triangular), Z (in:
 // the Hessenberg transform; out: C = Z T Z^H), both m x m row-major; tnorm: max |T_ij| over
 // the upper triangle; flag 2 when the iteration does not converge within 40 m sweeps
@@ -427,9 +447,9 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
                                                       double* __restrict__ tnorm, int* __restrict__ flag) {
   __shared__ double red_v[QR_THREADS];
   __shared__ int red_i[QR_THREADS];
-  __shared__ c64 sH[QS * QS];
-  __shared__ double s_rc[QW];
-  __shared__ c64 s_rs[QW];
+  __shared__ c64 sH[2][QS * QS];
+  __shared__ double s_rc[2][QW];
+  __shared__ c64 s_rs[2][QW];
   __shared__ c64 s_mu;
   const int tid = threadIdx.x;
   const double eps = 2.220446049250313e-16;
@@ -475,124 +495,186 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
     }
     __syncthreads();
     const c64 mu = s_mu;
-    for (int k0 = lo; k0 < hi;) {
-      const int kend = min(k0 + QW, hi);
-      const int nrot = kend - k0;
-      const int a = (k0 == lo) ? lo : k0 - 1;
-      const int e = min(hi, k0 + QW + 1);
-      const int sz = e - a + 1;
-      for (int q = tid; q < QS * QS; q += QR_THREADS) {
-        const int i = q / QS, j = q % QS;
-        sH[q] = (i < sz && j < sz) ? H[(int64_t)(a + i) * m + a + j] : c64(0.0, 0.0);
-      }
-      __syncthreads();
+    // The sweep in windows of QW rotations.  Phase p: wavefront 0 chases window p inside
+    // its LDS block while the other wavefronts apply window p - 1's rotations to the rest of
+    // H and Z; one barrier per phase.  Window p's block needs window p - 1's row rotations
+    // on the columns it adds to the right (rows k0_{p-1}..k0_p of columns e_{p-1}+1..e_p):
+    // wavefront 0 applies those itself first, and the other wavefronts leave them out.
+    const int nwin = (hi - lo + QW - 1) / QW;
+    for (int p = 0; p <= nwin; ++p) {
+      const int buf = p & 1;
       if (tid < 64) {
-        // the chase inside the window, one wavefront: per rotation one round of LDS reads
-        // (its operands and the 2 x 2 block where the row and the column update meet), the
-        // row update of columns j != kl, kl+1 (lane j - c0l), the column update of rows
-        // i <= k+2 (lane i; the block's rows from the row-rotated values), one round of writes
-        const int lane = tid;
-        for (int r = 0; r < nrot; ++r) {
-          const int k = k0 + r, kl = k - a;
-          const int c0l = (k == lo) ? kl : kl - 1;
-          const int j = c0l + lane;
-          const int rmax = min(k + 2, hi) - a;
-          const int i = lane;
-          const c64 x = (k == lo) ? sH[kl * QS + kl] - mu : sH[kl * QS + kl - 1];
-          const c64 y = (k == lo) ? sH[(kl + 1) * QS + kl] : sH[(kl + 1) * QS + kl - 1];
-          const c64 b00 = sH[kl * QS + kl], b01 = sH[kl * QS + kl + 1];
-          const c64 b10 = sH[(kl + 1) * QS + kl], b11 = sH[(kl + 1) * QS + kl + 1];
-          const int jc = min(j, QS - 1), ic = min(i, QS - 1);
-          const c64 pa = sH[kl * QS + jc], pb = sH[(kl + 1) * QS + jc];
-          c64 qa = sH[ic * QS + kl], qb = sH[ic * QS + kl + 1];
-          // G = [c s; -conj(s) c] with G [x; y] = [r; 0], c real
-          const double ax2 = norm2(x), ay2 = norm2(y);
-          double cc;
-          c64 ss;
-          if (ay2 == 0.0) {
-            cc = 1.0;
-            ss = c64(0.0, 0.0);
-          } else if (ax2 == 0.0) {
-            const double iy = 1.0 / sqrt(ay2);
-            cc = 0.0;
-            ss = c64(y.re * iy, -y.im * iy);
+        if (p < nwin) {
+          const int lane = tid;
+          const int k0 = lo + p * QW;
+          const int kend = min(k0 + QW, hi);
+          const int nrot = kend - k0;
+          const int a = (p == 0) ? lo : k0 - 1;
+          const int e = min(hi, k0 + QW + 1);
+          const int sz = e - a + 1;
+          c64* __restrict__ S = sH[buf];
+          constexpr int NQ = (QS * QS + 63) / 64;  // block entries per lane
+          c64 g[NQ];
+          if (p == 0) {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+              const int q = lane + 64 * t;
+              const int i = q / QS, j = q % QS;
+              g[t] = (q < QS * QS && i < sz && j < sz) ? H[(int64_t)(a + i) * m + a + j] : c64(0.0, 0.0);
+            }
+#pragma unroll
+            for (int t = 0; t < NQ; ++t)
+              if (lane + 64 * t < QS * QS) S[lane + 64 * t] = g[t];
           } else {
-            const double ax = sqrt(ax2);
-            const double ir = 1.0 / sqrt(ax2 + ay2);
-            const double f = ir / ax;
-            cc = ax * ir;
-            ss = c64(f * (x.re * y.re + x.im * y.im), f * (x.im * y.re - x.re * y.im));
-          }
-          if (lane == 0) {
-            s_rc[r] = cc;
-            s_rs[r] = ss;
-          }
-          if (i == kl) {
-            qa = cc * b00 + ss * b10;
-            qb = cc * b01 + ss * b11;
-          } else if (i == kl + 1) {
-            qa = cc * b10 - conj(ss) * b00;
-            qb = cc * b11 - conj(ss) * b01;
-          }
-          if (j < sz && j != kl && j != kl + 1) {
-            sH[kl * QS + j] = cc * pa + ss * pb;
-            sH[(kl + 1) * QS + j] = cc * pb - conj(ss) * pa;
-          }
-          if (i <= rmax) {
-            sH[i * QS + kl] = cc * qa + conj(ss) * qb;
-            sH[i * QS + kl + 1] = cc * qb - ss * qa;
+            // the previous window is a full one: rows pk0..k0 rotated, block [pa, pe].  The new
+            // block takes its top-left 3 x 3 from the previous block, rows k0-1 and k0 of the
+            // columns right of pe from the catch-up (those columns' rows pk0..k0 receive the
+            // previous window's row rotations here: the other wavefronts leave them out), and
+            // the rest from H (those loads issued together, before the catch-up's own).
+            const int pk0 = k0 - QW, pe = k0 + 1;
+            const int pa = (p == 1) ? lo : pk0 - 1;
+            const c64* __restrict__ P = sH[buf ^ 1];
+            const int ncu = e - pe;  // catch-up columns pe+1..e (at most QW), one per lane
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+              const int q = lane + 64 * t;
+              const int i = q / QS, j = q % QS;
+              const int gi = a + i, gj = a + j;
+              const bool fresh = q < QS * QS && i < sz && j < sz && !(gi <= pe && gj <= pe) && !(gj > pe && gi <= k0);
+              g[t] = fresh ? H[(int64_t)gi * m + gj] : c64(0.0, 0.0);
+            }
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+              const int q = lane + 64 * t;
+              const int i = q / QS, j = q % QS;
+              const int gi = a + i, gj = a + j;
+              if (q < QS * QS) {
+                if (!(i < sz && j < sz)) S[q] = c64(0.0, 0.0);
+                else if (gi <= pe && gj <= pe) S[q] = P[(gi - pa) * QS + (gj - pa)];
+                else if (!(gj > pe && gi <= k0)) S[q] = g[t];
+              }
+            }
+            const int col = pe + 1 + lane;
+            c64 v[QW + 1];
+            if (lane < ncu) {
+#pragma unroll
+              for (int q = 0; q <= QW; ++q) v[q] = H[(int64_t)(pk0 + q) * m + col];
+            }
+            if (lane < ncu) {
+              qr_rotate_segment(v, QW, false, s_rc[buf ^ 1], s_rs[buf ^ 1]);
+              // rows pk0..k0-2 are done for this window; rows a = k0-1 and k0 go into the
+              // block (written back with it)
+#pragma unroll
+              for (int q = 0; q < QW - 1; ++q) H[(int64_t)(pk0 + q) * m + col] = v[q];
+              S[col - a] = v[QW - 1];
+              S[QS + col - a] = v[QW];
+            }
           }
           wave_sync();
-        }
-      }
-      __syncthreads();
-      // the window back to H; the window's rotations applied to the rest (entries k0..kend
-      // of each segment): rows of the columns right of the window, the rows above it, and
-      // every row of Z
-      for (int q = tid; q < sz * sz; q += QR_THREADS) {
-        const int i = q / sz, j = q % sz;
-        H[(int64_t)(a + i) * m + a + j] = sH[i * QS + j];
-      }
-      const int ncol = m - 1 - e, nabove = a;
-      const int items = ncol + nabove + m;
-      for (int it = tid; it < items; it += QR_THREADS) {
-        c64 v[QW + 1];
-        c64* M = H;
-        int64_t base, stride;
-        bool cols;
-        if (it < ncol) {
-          base = (int64_t)k0 * m + e + 1 + it;
-          stride = m;
-          cols = false;
-        } else {
-          const bool isz = it >= ncol + nabove;
-          const int i = isz ? it - ncol - nabove : it - ncol;
-          if (isz) M = Z;
-          base = (int64_t)i * m + k0;
-          stride = 1;
-          cols = true;
-        }
-        // unconditional loads of entries k0..k0+QW (clamped to kend), issued together
-#pragma unroll
-        for (int q = 0; q <= QW; ++q) v[q] = M[base + (int64_t)min(q, nrot) * stride];
-        // row rotations act as [c s; -conj(s) c] on (v_r, v_r+1); column rotations (by G^H)
-        // as the same with s replaced by conj(s)
-#pragma unroll
-        for (int r = 0; r < QW; ++r) {
-          if (r < nrot) {
-            const double cc = s_rc[r];
-            const c64 ss = cols ? conj(s_rs[r]) : s_rs[r];
-            const c64 xa = v[r], yb = v[r + 1];
-            v[r] = cc * xa + ss * yb;
-            v[r + 1] = cc * yb - conj(ss) * xa;
+          // the chase inside the window: per rotation one round of LDS reads (its operands
+          // and the 2 x 2 block where the row and the column update meet), the row update of
+          // columns j != kl, kl+1 (lane j - c0l), the column update of rows i <= k+2 (lane i;
+          // the block's rows from the row-rotated values), one round of writes
+          for (int r = 0; r < nrot; ++r) {
+            const int k = k0 + r, kl = k - a;
+            const int c0l = (k == lo) ? kl : kl - 1;
+            const int j = c0l + lane;
+            const int rmax = min(k + 2, hi) - a;
+            const int i = lane;
+            const c64 x = (k == lo) ? S[kl * QS + kl] - mu : S[kl * QS + kl - 1];
+            const c64 y = (k == lo) ? S[(kl + 1) * QS + kl] : S[(kl + 1) * QS + kl - 1];
+            const c64 b00 = S[kl * QS + kl], b01 = S[kl * QS + kl + 1];
+            const c64 b10 = S[(kl + 1) * QS + kl], b11 = S[(kl + 1) * QS + kl + 1];
+            const int jc = min(j, QS - 1), ic = min(i, QS - 1);
+            const c64 pa_ = S[kl * QS + jc], pb_ = S[(kl + 1) * QS + jc];
+            c64 qa = S[ic * QS + kl], qb = S[ic * QS + kl + 1];
+            // G = [c s; -conj(s) c] with G [x; y] = [r; 0], c real
+            const double ax2 = norm2(x), ay2 = norm2(y);
+            double cc;
+            c64 ss;
+            if (ay2 == 0.0) {
+              cc = 1.0;
+              ss = c64(0.0, 0.0);
+            } else if (ax2 == 0.0) {
+              const double iy = 1.0 / sqrt(ay2);
+              cc = 0.0;
+              ss = c64(y.re * iy, -y.im * iy);
+            } else {
+              // c = |x| / r, s = x conj(y) / (|x| r), r = sqrt(|x|^2 + |y|^2): the two square
+              // roots side by side, then one division
+              const double ax = sqrt(ax2);
+              const double r = sqrt(ax2 + ay2);
+              const double f = 1.0 / (ax * r);
+              cc = ax2 * f;
+              ss = c64(f * (x.re * y.re + x.im * y.im), f * (x.im * y.re - x.re * y.im));
+            }
+            if (lane == 0) {
+              s_rc[buf][r] = cc;
+              s_rs[buf][r] = ss;
+            }
+            if (i == kl) {
+              qa = cc * b00 + ss * b10;
+              qb = cc * b01 + ss * b11;
+            } else if (i == kl + 1) {
+              qa = cc * b10 - conj(ss) * b00;
+              qb = cc * b11 - conj(ss) * b01;
+            }
+            if (j < sz && j != kl && j != kl + 1) {
+              S[kl * QS + j] = cc * pa_ + ss * pb_;
+              S[(kl + 1) * QS + j] = cc * pb_ - conj(ss) * pa_;
+            }
+            if (i <= rmax) {
+              S[i * QS + kl] = cc * qa + conj(ss) * qb;
+              S[i * QS + kl + 1] = cc * qb - ss * qa;
+            }
+            wave_sync();
+          }
+          // the block back to H
+          for (int q = lane; q < sz * sz; q += 64) {
+            const int i = q / sz, j = q % sz;
+            H[(int64_t)(a + i) * m + a + j] = S[i * QS + j];
           }
         }
+      } else if (p >= 1) {
+        // window p - 1's rotations on the rest (entries k0..kend of each segment): rows of the
+        // columns right of its block (past the next block's columns), the rows above its block,
+        // and every row of Z
+        const int k0 = lo + (p - 1) * QW;
+        const int kend = min(k0 + QW, hi);
+        const int nrot = kend - k0;
+        const int a = (p == 1) ? lo : k0 - 1;
+        const int e = min(hi, k0 + QW + 1);
+        const int cfirst = (p < nwin) ? min(hi, kend + QW + 1) + 1 : e + 1;
+        const int ncol = m - cfirst, nabove = a;
+        const int items = ncol + nabove + m;
+        const int rb = buf ^ 1;
+        for (int it = tid - 64; it < items; it += QR_THREADS - 64) {
+          c64* M = H;
+          int64_t base, stride;
+          bool cols;
+          if (it < ncol) {
+            base = (int64_t)k0 * m + cfirst + it;
+            stride = m;
+            cols = false;
+          } else {
+            const bool isz = it >= ncol + nabove;
+            const int i = isz ? it - ncol - nabove : it - ncol;
+            if (isz) M = Z;
+            base = (int64_t)i * m + k0;
+            stride = 1;
+            cols = true;
+          }
+          // unconditional loads of entries k0..k0+QW (clamped to kend), issued together
+          c64 v[QW + 1];
 #pragma unroll
-        for (int q = 0; q <= QW; ++q)
-          if (q <= nrot) M[base + (int64_t)q * stride] = v[q];
+          for (int q = 0; q <= QW; ++q) v[q] = M[base + (int64_t)min(q, nrot) * stride];
+          qr_rotate_segment(v, nrot, cols, s_rc[rb], s_rs[rb]);
+#pragma unroll
+          for (int q = 0; q <= QW; ++q)
+            if (q <= nrot) M[base + (int64_t)q * stride] = v[q];
+        }
       }
       __syncthreads();
-      k0 = kend;
     }
   }
   double tn = 0.0;
