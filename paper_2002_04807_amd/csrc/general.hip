@@ -571,23 +571,27 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
             }
           }
           wave_sync();
-          // the chase inside the window: per rotation one round of LDS reads (its operands
-          // and the 2 x 2 block where the row and the column update meet), the row update of
-          // columns j != kl, kl+1 (lane j - c0l), the column update of rows i <= k+2 (lane i;
-          // the block's rows from the row-rotated values), one round of writes
+          // the chase inside the window: per rotation one round of LDS reads, the rotation
+          // (computed by every lane), one pair update per lane and one round of writes.
+          // Lanes 0-31 update rows kl, kl+1 at column c0l + lane (the row rotation; columns kl
+          // and kl+1 excluded), lanes 32-63 columns kl, kl+1 at row lane - 32 (the column
+          // rotation, rows i <= k+2; rows kl and kl+1 start from the row-rotated 2 x 2 block).
+          const bool rowl = lane < 32;
+          const int hl = lane & 31;
           for (int r = 0; r < nrot; ++r) {
             const int k = k0 + r, kl = k - a;
             const int c0l = (k == lo) ? kl : kl - 1;
-            const int j = c0l + lane;
             const int rmax = min(k + 2, hi) - a;
-            const int i = lane;
+            const int j = c0l + hl;  // row lanes: column
+            const int i = hl;        // column lanes: row
             const c64 x = (k == lo) ? S[kl * QS + kl] - mu : S[kl * QS + kl - 1];
             const c64 y = (k == lo) ? S[(kl + 1) * QS + kl] : S[(kl + 1) * QS + kl - 1];
             const c64 b00 = S[kl * QS + kl], b01 = S[kl * QS + kl + 1];
             const c64 b10 = S[(kl + 1) * QS + kl], b11 = S[(kl + 1) * QS + kl + 1];
             const int jc = min(j, QS - 1), ic = min(i, QS - 1);
-            const c64 pa_ = S[kl * QS + jc], pb_ = S[(kl + 1) * QS + jc];
-            c64 qa = S[ic * QS + kl], qb = S[ic * QS + kl + 1];
+            const int ua = rowl ? kl * QS + jc : ic * QS + kl;
+            const int wa = rowl ? (kl + 1) * QS + jc : ic * QS + kl + 1;
+            c64 u = S[ua], w = S[wa];
             // G = [c s; -conj(s) c] with G [x; y] = [r; 0], c real
             const double ax2 = norm2(x), ay2 = norm2(y);
             double cc;
@@ -603,8 +607,8 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
               // c = |x| / r, s = x conj(y) / (|x| r), r = sqrt(|x|^2 + |y|^2): the two square
               // roots side by side, then one division
               const double ax = sqrt(ax2);
-              const double r = sqrt(ax2 + ay2);
-              const double f = 1.0 / (ax * r);
+              const double rr = sqrt(ax2 + ay2);
+              const double f = 1.0 / (ax * rr);
               cc = ax2 * f;
               ss = c64(f * (x.re * y.re + x.im * y.im), f * (x.im * y.re - x.re * y.im));
             }
@@ -612,20 +616,24 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
               s_rc[buf][r] = cc;
               s_rs[buf][r] = ss;
             }
-            if (i == kl) {
-              qa = cc * b00 + ss * b10;
-              qb = cc * b01 + ss * b11;
-            } else if (i == kl + 1) {
-              qa = cc * b10 - conj(ss) * b00;
-              qb = cc * b11 - conj(ss) * b01;
+            // column lanes of rows kl, kl+1: the row-rotated block, row kl = (c b00 + s b10,
+            // c b01 + s b11), row kl+1 = (c b10 - conj(s) b00, c b11 - conj(s) b01)
+            const bool top = (i == kl);
+            const c64 tm = top ? ss : c64(-ss.re, ss.im);  // s, or -conj(s)
+            const c64 p1 = top ? b00 : b10, q1 = top ? b10 : b00;
+            const c64 p2 = top ? b01 : b11, q2 = top ? b11 : b01;
+            if (!rowl && (i == kl || i == kl + 1)) {
+              u = cc * p1 + tm * q1;
+              w = cc * p2 + tm * q2;
             }
-            if (j < sz && j != kl && j != kl + 1) {
-              S[kl * QS + j] = cc * pa_ + ss * pb_;
-              S[(kl + 1) * QS + j] = cc * pb_ - conj(ss) * pa_;
-            }
-            if (i <= rmax) {
-              S[i * QS + kl] = cc * qa + conj(ss) * qb;
-              S[i * QS + kl + 1] = cc * qb - ss * qa;
+            // row lanes rotate by [c s; -conj(s) c], column lanes by [c conj(s); -s c]
+            const c64 t = rowl ? ss : conj(ss);
+            const c64 un = cc * u + t * w;
+            const c64 wn = cc * w - conj(t) * u;
+            const bool act = rowl ? (j < sz && j != kl && j != kl + 1) : (i <= rmax);
+            if (act) {
+              S[ua] = un;
+              S[wa] = wn;
             }
             wave_sync();
           }
