@@ -448,6 +448,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
   __shared__ double red_v[QR_THREADS];
   __shared__ int red_i[QR_THREADS];
   __shared__ c64 sH[2][QS * QS];
+  __shared__ c64 sF[2][QS * QS];  // next block's entries from H, staged by wavefronts 1..7
   __shared__ double s_rc[2][QW];
   __shared__ c64 s_rs[2][QW];
   __shared__ c64 s_mu;
@@ -501,6 +502,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
     // on the columns it adds to the right (rows k0_{p-1}..k0_p of columns e_{p-1}+1..e_p):
     // wavefront 0 applies those itself first, and the other wavefronts leave them out.
     const int nwin = (hi - lo + QW - 1) / QW;
+    constexpr int NQ = (QS * QS + 63) / 64;  // block entries per lane
     for (int p = 0; p <= nwin; ++p) {
       const int buf = p & 1;
       if (tid < 64) {
@@ -513,9 +515,8 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
           const int e = min(hi, k0 + QW + 1);
           const int sz = e - a + 1;
           c64* __restrict__ S = sH[buf];
-          constexpr int NQ = (QS * QS + 63) / 64;  // block entries per lane
-          c64 g[NQ];
           if (p == 0) {
+            c64 g[NQ];
 #pragma unroll
             for (int t = 0; t < NQ; ++t) {
               const int q = lane + 64 * t;
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
             // block takes its top-left 3 x 3 from the previous block, rows k0-1 and k0 of the
             // columns right of pe from the catch-up (those columns' rows pk0..k0 receive the
             // previous window's row rotations here: the other wavefronts leave them out), and
-            // the rest from H (those loads issued together, before the catch-up's own).
+            // the rest from H (staged in LDS by the other wavefronts in the previous phase).
             const int pk0 = k0 - QW, pe = k0 + 1;
             const int pa = (p == 1) ? lo : pk0 - 1;
             const c64* __restrict__ P = sH[buf ^ 1];
@@ -540,18 +541,10 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
               const int q = lane + 64 * t;
               const int i = q / QS, j = q % QS;
               const int gi = a + i, gj = a + j;
-              const bool fresh = q < QS * QS && i < sz && j < sz && !(gi <= pe && gj <= pe) && !(gj > pe && gi <= k0);
-              g[t] = fresh ? H[(int64_t)gi * m + gj] : c64(0.0, 0.0);
-            }
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) {
-              const int q = lane + 64 * t;
-              const int i = q / QS, j = q % QS;
-              const int gi = a + i, gj = a + j;
               if (q < QS * QS) {
                 if (!(i < sz && j < sz)) S[q] = c64(0.0, 0.0);
                 else if (gi <= pe && gj <= pe) S[q] = P[(gi - pa) * QS + (gj - pa)];
-                else if (!(gj > pe && gi <= k0)) S[q] = g[t];
+                else if (!(gj > pe && gi <= k0)) S[q] = sF[buf][q];
               }
             }
             const int col = pe + 1 + lane;
@@ -643,7 +636,22 @@ __global__ __launch_bounds__(QR_THREADS) void k_nh_qr(int m, c64* __restrict__ H
             H[(int64_t)(a + i) * m + a + j] = S[i * QS + j];
           }
         }
-      } else if (p >= 1) {
+      } else {
+        if (p + 1 < nwin) {
+          // the entries of window p+1's block that come from H (rows k0n+1 and below, past the
+          // columns its top-left 3 x 3 and its catch-up cover; none of them changes before that
+          // block is formed), staged in LDS for wavefront 0
+          const int k0n = lo + (p + 1) * QW, an = k0n - 1, pen = k0n + 1;
+          const int szn = min(hi, k0n + QW + 1) - an + 1;
+          for (int q = tid - 64; q < QS * QS; q += QR_THREADS - 64) {
+            const int i = q / QS, j = q % QS;
+            const int gi = an + i, gj = an + j;
+            if (i < szn && j < szn && !(gi <= pen && gj <= pen) && !(gj > pen && gi <= k0n))
+              sF[buf ^ 1][q] = H[(int64_t)gi * m + gj];
+          }
+        }
+      }
+      if (tid >= 64 && p >= 1) {
         // window p - 1's rotations on the rest (entries k0..kend of each segment): rows of the
         // columns right of its block (past the next block's columns), the rows above its block,
         // and every row of Z
