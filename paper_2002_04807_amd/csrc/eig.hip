@@ -364,6 +364,15 @@ __global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, int rn
   block_pair(b - npr, rn, nbp, P, Q);
   const int i = bj_pair_of(P, round, nbp), j = bj_pair_of(Q, round, nbp);
   if (i == j) return;
+  // two next-round pairs can couple the same two pairs of this round (with four blocks both
+  // do): only the first of them updates that super-block, or two workgroups would rotate
+  // the same entries at once
+  for (int t = 0; t < b - npr; ++t) {
+    int Pt, Qt;
+    block_pair(t, rn, nbp, Pt, Qt);
+    const int it = bj_pair_of(Pt, round, nbp), jt = bj_pair_of(Qt, round, nbp);
+    if (min(it, jt) == min(i, j) && max(it, jt) == max(i, j)) return;
+  }
   bj_h_update<T, JB>(m, nbp, round, min(i, j), max(i, j), H, Ubuf, X, Um);
 }
 

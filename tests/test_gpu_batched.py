@@ -105,10 +105,10 @@ def test_full_batched_workload():
 def test_graph_replay_repeats_the_first_call_and_follows_new_intervals():
     """The first call factors every (problem, node) item in padded size classes with the
     tile autotuner on and captures the launches in a graph; the second call replays it and
-    must find the same pairs (count, loop, eigenvalues within 1e-12 relative, vectors within
-    sin 1e-10; the Ritz values outside the interval are not converged and are not compared);
-    a third call with other intervals (same sizes, so the same graph, new nodes uploaded)
-    must match the single-problem driver."""
+    must return the same results bit for bit (the problems run concurrently on several
+    worker streams, so this also checks that no kernel's result depends on what runs beside
+    it); a third call with other intervals (same sizes, so the same graph, new nodes
+    uploaded) must match the single-problem driver."""
     probs = gen.batched_real_problems(10, seed=11, n_lo=200, n_hi=700, c_lo=6, c_hi=14)
     _say("batched graph replay: n = %s" % [p["A"].shape[0] for p in probs])
     fpm = mf.mfeast_init()
@@ -123,9 +123,8 @@ def test_graph_replay_repeats_the_first_call_and_follows_new_intervals():
     assert r1 == r2 == 0
     for a, b, p in zip(o1, o2, probs):
         _check(b, p, 1e-10)
-        assert a["loop"] == b["loop"] and a["M"] == b["M"]
-        compare_eigenpairs(b["E"].cpu().numpy(), b["X"].cpu().numpy(), a["E"].cpu().numpy(), a["X"].cpu().numpy(),
-                           a["M"], p["emin"], p["emax"], eig_tol=1e-12, angle_tol=1e-10)
+        assert a["loop"] == b["loop"] and a["M"] == b["M"] and a["info"] == b["info"]
+        assert torch.equal(a["E"], b["E"]) and torch.equal(a["X"], b["X"]) and torch.equal(a["res"], b["res"])
     # new intervals: the lower half of each problem's eigenvalues (edges mid-gap)
     emins, emaxs, m0s, counts = [], [], [], []
     for p in probs:
