@@ -329,8 +329,8 @@ int mfeast_dcsrgv(mfeast_handle h, char uplo, int64_t n, const double* a, const 
  *  M          number of pairs (1 <= M <= n)
  *  E          device, M doubles; X device n x M column-major (ldx >= n), orthonormal
  *  gE         device, M doubles, or NULL (zero); gX device n x M (ldgx >= n) or NULL (zero)
- *  precision  0: complex FP64 factorization, one refinement step;
- *             1: complex FP32 factorization, up to four FP64 refinement steps
+ *  precision  0: real FP64 factorization, one refinement step;
+ *             1: real FP32 factorization, up to four FP64 refinement steps
  *  gA         device, n x n column-major (ldga >= n), or NULL
  *  gdiag      device, n doubles: the diagonal of dL/dA (dL/dv for A + diag(v)), or NULL
  * At least one of gA, gdiag.  Returns 0, 202 (n), 201 (M), -(100+i) for argument i,

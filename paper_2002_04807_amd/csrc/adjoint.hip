@@ -9,9 +9,10 @@
 // the unique solution orthogonal to X_S of the deflated shifted system
 //   (lambda_i I - A + sigma X X^T) y_i = (I - X X^T) G_i,
 // nonsingular for sigma != lambda_j - lambda_i (j in S); sigma = 1 + 2 (max - min) of the
-// given eigenvalues.  The M shifted matrices are factored together by the batched LU of
-// the contour solves (nodes z_i = lambda_i) in complex FP64 (precision 0) or complex
-// FP32 (precision 1); each solve is refined with FP64 residuals of the deflated system.
+// given eigenvalues.  The M shifted matrices are real; they are factored together by the
+// batched LU of the contour solves (nodes z_i = lambda_i) in real arithmetic, FP64
+// (precision 0) or FP32 (precision 1); each solve is refined with FP64 residuals of the
+// deflated system.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,7 +34,7 @@ __global__ void k_adj_extract(int64_t n, int M, const C* __restrict__ W, const d
   if (e >= n * (int64_t)M) return;
   const int64_t r = e / M;
   const int i = (int)(e % M);
-  const double v = (double)W[((int64_t)i * n + r) * M + i].re * us[i];
+  const double v = (double)real_part(W[((int64_t)i * n + r) * M + i]) * us[i];
   Y[e] = add ? Y[e] + v : v;
 }
 
@@ -220,8 +221,8 @@ extern "C" int mfeast_dsy_adjoint(mfeast_handle h, int64_t n, const double* A, i
   GemmScratchScope scratch_scope(h);
   prof_enable(h->prof_all);
   for (int i = 0; i < K_NCLASS * 4; ++i) h->prof[i] = 0.0;
-  const int rc = precision == 1 ? adjoint_run<c32>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 4)
-                                : adjoint_run<c64>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 1);
+  const int rc = precision == 1 ? adjoint_run<float>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 4)
+                                : adjoint_run<double>(h, n, A, lda, M, E, X, ldx, gE, gX, ldgx, gA, ldga, gdiag, 1);
   if (prof_on()) {
     (void)hipStreamSynchronize(h->stream);
     prof_collect(h->prof);

@@ -43,6 +43,11 @@ __host__ __device__ inline float conj(float a) { return a; }
 __host__ __device__ inline double norm2(double a) { return a * a; }
 __host__ __device__ inline double abs1(double a) { return fabs(a); }
 __host__ __device__ inline double real_part(double a) { return a; }
+__host__ __device__ inline float norm2(float a) { return a * a; }
+__host__ __device__ inline float abs1(float a) { return fabsf(a); }
+__host__ __device__ inline float real_part(float a) { return a; }
+__host__ __device__ inline double cdiv(double a, double b) { return a / b; }
+__host__ __device__ inline float cdiv(float a, float b) { return a / b; }
 template <typename R> __host__ __device__ inline R real_part(cplx<R> a) { return a.re; }
 
 using c32 = cplx<float>;
@@ -60,6 +65,10 @@ template <> __host__ __device__ inline c64 convert<c64, c64>(c64 a) { return a; 
 template <> __host__ __device__ inline c64 convert<c64, c32>(c32 a) { return {(double)a.re, (double)a.im}; }
 template <> __host__ __device__ inline c32 convert<c32, double>(double a) { return {(float)a, 0.f}; }
 template <> __host__ __device__ inline c64 convert<c64, double>(double a) { return {a, 0.0}; }
+// real solve types (real shifted matrices): the real part
+template <> __host__ __device__ inline float convert<float, c64>(c64 a) { return (float)a.re; }
+template <> __host__ __device__ inline double convert<double, c64>(c64 a) { return a.re; }
+template <> __host__ __device__ inline c64 convert<c64, float>(float a) { return {(double)a, 0.0}; }
 
 }  // namespace mf
 

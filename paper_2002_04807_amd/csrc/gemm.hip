@@ -550,5 +550,7 @@ template int gemm_op<double, false>(hipStream_t, GemmOp, GemmOp, const GemmArgs&
 template int gemm<float, true>(hipStream_t, bool, bool, const GemmArgs&, int);
 template int gemm<double, true>(hipStream_t, bool, bool, const GemmArgs&, int);
 template int gemm<double, false>(hipStream_t, bool, bool, const GemmArgs&, int);
+template int gemm_op<float, false>(hipStream_t, GemmOp, GemmOp, const GemmArgs&, int);
+template int gemm<float, false>(hipStream_t, bool, bool, const GemmArgs&, int);
 
 }  // namespace mf

@@ -691,7 +691,7 @@ int lu_factor(hipStream_t s, int64_t n, int ne, C* LU, int* ipiv, int* perm, int
       t.alpha = -1.0; t.beta = 1.0;
       t.tag = 1;
       tok = prof_begin(s);
-      if (gemm<R, true>(s, false, false, t, ne)) return -2;
+      if (gemm<R, is_cplx<C>::value>(s, false, false, t, ne)) return -2;
       prof_end(tok, s, K_LU_GEMM, 8.0 * (double)rest * rest * nbc * ne,
                (double)sizeof(C) * ne * (2.0 * rest * rest + 2.0 * rest * nbc));
     }
@@ -713,5 +713,9 @@ template int shift_form<c64, c32>(hipStream_t, int64_t, const c64*, int64_t, con
 template int shift_form<c64, c64>(hipStream_t, int64_t, const c64*, int64_t, const c64*, int64_t, const c64*, int, c64*, int*, bool);
 template int lu_factor<c32>(hipStream_t, int64_t, int, c32*, int*, int*, int*, int*, c32*);
 template int lu_factor<c64>(hipStream_t, int64_t, int, c64*, int*, int*, int*, int*, c64*);
+template int shift_form<double, float>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, float*, int*, bool);
+template int shift_form<double, double>(hipStream_t, int64_t, const double*, int64_t, const double*, int64_t, const c64*, int, double*, int*, bool);
+template int lu_factor<float>(hipStream_t, int64_t, int, float*, int*, int*, int*, int*, float*);
+template int lu_factor<double>(hipStream_t, int64_t, int, double*, int*, int*, int*, int*, double*);
 
 }  // namespace mf

@@ -243,7 +243,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
       d.B = in + p0 * m; d.ldb = m; d.b_bs = wstride;
       d.C = out + p0 * m; d.ldc = m; d.c_bs = wstride;
       d.alpha = 1.0; d.beta = 0.0;
-      if (gemm<R, true>(st, herm, herm, d, ne)) return -2;
+      if (gemm<R, is_cplx<C>::value>(st, herm, herm, d, ne)) return -2;
       // rows beyond the panel: in_rest -= A out_P
       GemmArgs g{};
       g.N = m; g.K = (int)ph;
@@ -265,7 +265,7 @@ int lu_solve(hipStream_t s, int64_t n, int m, int ne, const C* LU, const C* Pinv
         // U: rows above the panel, its columns; L^H: M-contiguous view of the panel's L rows
         g.A = herm ? LU + p0 * ld : LU + p0;
       }
-      if (gemm<R, true>(st, herm, herm, g, ne)) return -2;
+      if (gemm<R, is_cplx<C>::value>(st, herm, herm, g, ne)) return -2;
     }
     return 0;
   };
@@ -434,6 +434,14 @@ template int lu_solve<c64>(hipStream_t, int64_t, int, int, const c64*, const c64
                           const SolveSide<c64>*, int);
 template int panel_inverses<c32>(hipStream_t, int64_t, int, const c32*, const c32*, c32*);
 template int panel_inverses<c64>(hipStream_t, int64_t, int, const c64*, const c64*, c64*);
+template int rhs_prepare<double, float>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, float*, float*, int64_t);
+template int rhs_prepare<double, double>(hipStream_t, int64_t, int, const double*, int64_t, const double*, int, const int*, double*, double*, int64_t);
+template int lu_solve<float>(hipStream_t, int64_t, int, int, const float*, const float*, float*, float*, float*,
+                             const SolveSide<float>*, int);
+template int lu_solve<double>(hipStream_t, int64_t, int, int, const double*, const double*, double*, double*, double*,
+                              const SolveSide<double>*, int);
+template int panel_inverses<float>(hipStream_t, int64_t, int, const float*, const float*, float*);
+template int panel_inverses<double>(hipStream_t, int64_t, int, const double*, const double*, double*);
 template int accumulate<double, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int, int64_t);
 template int accumulate<double, c64>(hipStream_t, int64_t, int, int, const c64*, const c64*, const int*, const c64*, const c64*, const double*, const double*, const double*, double*, int, int64_t);
 template int accumulate<c64, c32>(hipStream_t, int64_t, int, int, const c32*, const c32*, const int*, const c64*, const c64*, const double*, const double*, const c64*, c64*, int, int64_t);
