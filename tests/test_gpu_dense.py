@@ -235,3 +235,29 @@ def test_four_product_scheme_matches_oracle():
     out = _run_gpu(A, B, emin, emax, m0, Y, True, extra={52: 1})
     ref = _run_oracle(A, B, emin, emax, m0, Y)
     _check(out, ref, emin, emax, B=B)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_repeated_calls_are_bit_for_bit_equal(fp32):
+    """A complex generalized pencil (its forward and conjugate-transpose solves run on two
+    streams at once) solved three times on one handle: count, loop, eigenvalues, vectors and
+    residuals equal bit for bit, so no kernel's result depends on scheduling."""
+    _say("dense repeated calls fp32=%s" % fp32)
+    A, B, lam, _ = gen.prescribed_complex_pencil(333, 2)
+    cnt = int(np.sum((lam >= -1.0) & (lam <= 1.0)))
+    At = torch.from_numpy(np.asfortranarray(A)).to(DEV)
+    Bt = torch.from_numpy(np.asfortranarray(B)).to(DEV)
+    h = mf.Handle(0)
+    outs = []
+    for _ in range(3):
+        fpm = mf.mfeast_init()
+        fpm[41] = 1 if fp32 else 0
+        o = mf.feast(At, Bt, -1.0, 1.0, int(1.5 * cnt) + 8, fpm=fpm, handle=h)
+        torch.cuda.synchronize()
+        outs.append(o)
+    h.close()
+    a = outs[0]
+    assert a["info"] == 0 and a["M"] == cnt
+    for b in outs[1:]:
+        assert (b["info"], b["M"], b["loop"]) == (a["info"], a["M"], a["loop"])
+        assert torch.equal(a["E"], b["E"]) and torch.equal(a["X"], b["X"]) and torch.equal(a["res"], b["res"])
