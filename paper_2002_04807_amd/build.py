@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmfeast.so")
-SOURCES = ["gemm.hip", "lu.hip", "solve.hip", "rr.hip", "orth.hip", "eig.hip", "prof.hip", "sparse.hip", "feast.hip", "adjoint.hip", "general.hip"]
+SOURCES = ["gemm.hip", "lu.hip", "solve.hip", "rr.hip", "orth.hip", "eig.hip", "tri.hip", "prof.hip", "sparse.hip", "feast.hip", "adjoint.hip", "general.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -240,17 +240,35 @@ static int check_fpm(const int32_t* fpm, bool expert) {
 // reduced eigensolver call, timed as its own class.  Algorithmic work of a two-sided
 // Jacobi sweep: m(m-1)/2 rotations, each updating two rows and two columns of H and
 // two columns of V, about 6 m^3 multiply-adds (48 m^3 flops complex, 12 m^3 real).
+// Solves whose eigenvectors only seed later work (seed_only) use the tridiagonal solver
+// from order TRI_MIN on (reduction 4/3 m^3 and back-transformation 2 m^3 multiply-adds);
+// MFEAST_TRIDIAG=0 keeps the Jacobi solver for them.
+constexpr int TRI_MIN = 128;
+
+static bool tri_enabled() {
+  static const int mode = getenv("MFEAST_TRIDIAG") ? atoi(getenv("MFEAST_TRIDIAG")) : 1;
+  return mode != 0;
+}
+
 template <typename T>
 static int eig_timed(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps, double* work,
-                     double big_rel = 1.0e-10) {
+                     double big_rel = 1.0e-10, bool seed_only = false, bool* used_tri = nullptr) {
+  const bool tri = seed_only && tri_enabled() && m >= TRI_MIN;
+  if (used_tri) *used_tri = tri;
   const int tok = prof_begin(s);
-  const int rc = jacobi_eigh<T>(s, m, H, V, evals, sweeps, work, big_rel);
+  int fell_back = 0;
+  const int rc = tri ? tri_eigh<T>(s, m, H, V, evals, reinterpret_cast<char*>(work), &fell_back, sweeps, big_rel)
+                     : jacobi_eigh<T>(s, m, H, V, evals, sweeps, work, big_rel);
   double flops = 0.0;
   if (prof_on() && rc == 0) {
-    int sw = 0;
-    if (hipMemcpyAsync(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
-    if (hipStreamSynchronize(s) != hipSuccess) return -2;
-    flops = (is_cplx<T>::value ? 48.0 : 12.0) * (double)m * m * m * sw;
+    if (tri && !fell_back) {
+      flops = (is_cplx<T>::value ? 8.0 : 2.0) * (4.0 / 3.0 + 2.0) * (double)m * m * m;
+    } else {
+      int sw = 0;
+      if (hipMemcpyAsync(&sw, sweeps, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return -2;
+      if (hipStreamSynchronize(s) != hipSuccess) return -2;
+      flops = (is_cplx<T>::value ? 48.0 : 12.0) * (double)m * m * m * sw;
+    }
   }
   prof_end(tok, s, K_EIG, flops, 0.0);
   return rc;
@@ -281,6 +299,9 @@ struct Operator {
   // out[c] = r_c^H B^-1 r_c for the columns of the row-major n x m block R (only called
   // when hasB); cs[c] > 0 scales column c before the solve; partial: ceil(n/256) * m doubles
   virtual int binv_dots(hipStream_t s, int m, const T* R, const double* cs, double* out, double* partial) = 0;
+  // FP32 solves near their accuracy limit: later contours add one FP64 refinement step per
+  // solve (as fpm(50) = 1).  Returns whether the operator changed.
+  virtual bool raise_precision(hipStream_t) { return false; }
 };
 
 // dense storage: LU of every shifted matrix, blocked triangular solves
@@ -319,6 +340,29 @@ struct DenseOp : Operator<T> {
     nw = n_;
   }
 
+  // FP64 blocks of the refinement steps
+  bool ir_buffers() {
+    constexpr bool CPLX = is_cplx<T>::value;
+    const size_t blk64 = (size_t)ne * n * m0max * sizeof(c64);
+    irXf = (c64*)h->ws(S_IR_XF, blk64);
+    irYc = CPLX ? (c64*)h->ws(S_IR_YC, blk64) : nullptr;
+    irT = CPLX ? (c64*)h->ws(S_IR_T, blk64) : nullptr;
+    irAX = (c64*)h->ws(S_IR_AX, blk64);
+    irBX = B ? (c64*)h->ws(S_IR_BX, blk64) : nullptr;
+    const bool ok = irXf && (!CPLX || (irYc && irT)) && irAX && (!B || irBX);
+    if (!ok) irXf = nullptr;
+    return ok;
+  }
+
+  // not for caller-supplied (padded) factors, and not inside the no-allocation entry point,
+  // whose fixed array is sized for the call as requested
+  bool raise_precision(hipStream_t) override {
+    if (sizeof(C) != sizeof(c32) || ext || ir_steps != 0 || h->arena != nullptr) return false;
+    if (!ir_buffers()) return false;
+    ir_steps = 1;
+    return true;
+  }
+
   int prepare(hipStream_t s) override {
     constexpr bool CPLX = is_cplx<T>::value;
     if (ext) {
@@ -353,15 +397,7 @@ struct DenseOp : Operator<T> {
     }
     Pinv = (C*)h->ws(S_PANINV, (size_t)nf * panel_inverse_entries(n) * szC);
     if (!LU || !Dinv || !ipiv || !perm || !pinv || !linfo || !zdev || !Wf || (CPLX && !Wc) || !Wy || !Pinv) return -2;
-    if (ir_steps > 0 && sizeof(C) == sizeof(c32)) {
-      const size_t blk64 = (size_t)ne * n * m0max * sizeof(c64);
-      irXf = (c64*)h->ws(S_IR_XF, blk64);
-      irYc = CPLX ? (c64*)h->ws(S_IR_YC, blk64) : nullptr;
-      irT = CPLX ? (c64*)h->ws(S_IR_T, blk64) : nullptr;
-      irAX = (c64*)h->ws(S_IR_AX, blk64);
-      irBX = B ? (c64*)h->ws(S_IR_BX, blk64) : nullptr;
-      if (!irXf || (CPLX && (!irYc || !irT)) || !irAX || (B && !irBX)) return -2;
-    }
+    if (ir_steps > 0 && sizeof(C) == sizeof(c32) && !ir_buffers()) return -2;
     // full storage if a triangle was given
     Af = A;
     ldaf = lda;
@@ -693,7 +729,8 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   const size_t sq = (size_t)m0 * m0 * szT;
   T* Sm = (T*)h->ws(S_S, sq);
   T* Tm = (T*)h->ws(S_T, sq);
-  T* Hw = (T*)h->ws(S_HW, std::max(sq, jacobi_work_bytes(m0, szT)));
+  T* Hw = (T*)h->ws(S_HW, std::max({sq, jacobi_work_bytes(m0, szT),
+                                     m0 >= TRI_MIN ? tri_work_bytes(m0, szT) : (size_t)0}));
   T* V = (T*)h->ws(S_V, sq);
   T* G = (T*)h->ws(S_G, sq);
   T* TG = (T*)h->ws(S_TG, std::max(3 * sq, (size_t)m0 * 32 * szT));  // also Cholesky / Newton-Schulz work
@@ -772,6 +809,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
   static const int deflate_mode = getenv("MFEAST_DEFLATE") ? atoi(getenv("MFEAST_DEFLATE")) : 1;
   const bool deflate = deflate_mode != 0;
   double trace_prev = 0.0;
+  double maxres_prev = 1.0e300;
   int info = 0;
   int M = 0;
   int k = 0;
@@ -1007,7 +1045,17 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       MF_TRY(copy_block<T>(s, mo, mo, Coo_o, kk2, Coo, mo, false));
       // (V_OO only prepares the full sweeps below, whose 1e-10 test decides the accuracy,
       // so its own sweeps stop at rotations below 1e-4 max|diag|)
-      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw, 1.0e-4));
+      bool oo_tri = false;
+      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw, 1.0e-4, true, &oo_tri));
+      if (oo_tri) {
+        // inverse-iteration vectors are orthogonal to about eps over the relative gap: V_OO
+        // is replaced by its polar factor V_OO (V_OO^H V_OO)^-1/2 (Newton-Schulz), so that
+        // the blocks formed with it below are similar to those of C
+        MF_TRY(rm_gemm<T>(s, mo, mo, mo, Voo, mo, true, true, Voo, mo, Coo, mo));
+        MF_TRY(ns_invsqrt<T>(s, mo, Coo, Hw, 4, TG));
+        MF_TRY(rm_gemm<T>(s, mo, mo, mo, Voo, mo, false, false, Hw, mo, Coo, mo));
+        MF_TRY(copy_block<T>(s, mo, mo, Coo, mo, Voo, mo, false));
+      }
       // the rotated blocks are formed from the original C (V_OO^H C_OO V_OO keeps what the
       // eigensolver left off the diagonal, which the full sweeps below then remove)
       T* IOr = TG;                        // mi x mo
@@ -1028,7 +1076,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       // depend on the basis chosen inside span(Q), and their residuals are far above the
       // threshold), so its sweeps stop at rotations below 1e-4 max|diag|, which still leaves
       // off-diagonal entries of the order of 1e-8 max|diag|
-      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw, k == 0 ? 1.0e-4 : 1.0e-10));
+      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw, k == 0 ? 1.0e-4 : 1.0e-10, k == 0));
     }
     int sweeps = 0;
     MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1148,6 +1196,13 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     const bool conv = M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps));
     if (conv) { info = 0; break; }
     if (k >= f(4)) { info = 2; break; }
+    // FP32 solves leave a residual floor of about 1e-11 here: once the found pairs are within
+    // reach of it (largest residual below 1e-9) or their residual falls by less than ten
+    // times in an iteration, the later contours refine every solve once in FP64
+    if (k >= 2 && M > 0 && maxres >= eps && (maxres < 1.0e-9 || maxres > 0.1 * maxres_prev) &&
+        op.raise_precision(s) && f(1) != 0)
+      fprintf(stderr, "    FP32 solves refined once in FP64 from the next contour on\n");
+    maxres_prev = M > 0 ? maxres : maxres_prev;
     ++k;
   }
 

@@ -158,6 +158,16 @@ int gram_equilibrate(hipStream_t s, int m, T* S, T* Tm, double* d, int* flag);
 template <typename T>
 int jacobi_eigh(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, double* work,
                 double big_rel = 1.0e-10);
+// Hermitian eigensolver by Householder reduction to real tridiagonal form, multisection
+// bisection, inverse iteration and a blocked back-transformation (tri.hip); m <= 1024.
+// H (m x m row-major, full storage) is destroyed; V gets the eigenvectors (columns),
+// evals the eigenvalues in ascending order.  A group of more than 64 eigenvalues within
+// 1e-10 of the spectral radius of each other is handed to jacobi_eigh (fell_back = 1,
+// big_rel passed on).  Synchronizes the stream once.  work: tri_work_bytes(m, sizeof(T)).
+template <typename T>
+int tri_eigh(hipStream_t s, int m, T* H, T* V, double* evals, char* work, int* fell_back, int* sweeps_out,
+             double big_rel);
+size_t tri_work_bytes(int m, size_t elem);
 template <typename T>
 int block_jacobi(hipStream_t s, int m, T* H, T* V, double* evals, int* sweeps_out, T* ubuf, int* counter,
                  int max_sweeps, double big_rel);
