@@ -1196,11 +1196,13 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
     const bool conv = M > 0 && ((f(6) == 1) ? (maxres < eps) : (eo < eps));
     if (conv) { info = 0; break; }
     if (k >= f(4)) { info = 2; break; }
-    // FP32 solves leave a residual floor of about 1e-11 here: once the found pairs are within
-    // reach of it (largest residual below 1e-9) or their residual falls by less than ten
-    // times in an iteration, the later contours refine every solve once in FP64
-    if (k >= 2 && M > 0 && maxres >= eps && (maxres < 1.0e-9 || maxres > 0.1 * maxres_prev) &&
-        op.raise_precision(s) && f(1) != 0)
+    // FP32 solves leave a residual floor of about 1e-11 (it varies with rounding up to about
+    // 6e-11): for a tolerance below 1e-10, once the found pairs are within reach of that floor
+    // (largest residual below 1e-9), and for any tolerance once their residual falls by less
+    // than ten times in an iteration, the later contours refine every solve once in FP64
+    const bool near_floor = eps < 1.0e-10 && maxres < 1.0e-9;
+    const bool stalled = maxres > 0.1 * maxres_prev;
+    if (k >= 2 && M > 0 && maxres >= eps && (near_floor || stalled) && op.raise_precision(s) && f(1) != 0)
       fprintf(stderr, "    FP32 solves refined once in FP64 from the next contour on\n");
     maxres_prev = M > 0 ? maxres : maxres_prev;
     ++k;

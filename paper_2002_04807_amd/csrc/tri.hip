@@ -77,12 +77,19 @@ __global__ __launch_bounds__(256) void k_trd_step(int m, int k, T* __restrict__ 
   const int r = k + 1 + (int)blockIdx.x * 4 + wave;
   const bool has_row = k <= m - 2 && r < m;
 
-  // this wavefront's row of the trailing block, loaded before anything waits on it
+  // this wavefront's row of the trailing block and this thread's entries of row k, loaded
+  // before anything waits on them
   T a[TRD_CPL];
 #pragma unroll
   for (int t = 0; t < TRD_CPL; ++t) {
     const int c = k + 1 + lane + 64 * t;
     a[t] = (has_row && c < m) ? A[(int64_t)r * m + c] : T(0);
+  }
+  T xr[TRD_MAXM / 256];
+#pragma unroll
+  for (int t = 0; t < TRD_MAXM / 256; ++t) {
+    const int c = k + tid + 256 * t;
+    xr[t] = c < m ? A[(int64_t)k * m + c] : T(0);
   }
 
   // ---- w_{k-1}
@@ -103,16 +110,12 @@ __global__ __launch_bounds__(256) void k_trd_step(int m, int k, T* __restrict__ 
   }
 
   // ---- row k of A^(k): d_k, and the reflector of column k (its conjugate below the diagonal)
-  T xr[TRD_MAXM / 256];
   double xn2 = 0.0;
 #pragma unroll
   for (int t = 0; t < TRD_MAXM / 256; ++t) {
     const int c = k + tid + 256 * t;
-    T val = T(0);
-    if (c < m) {
-      val = A[(int64_t)k * m + c];
-      if (prev) val = val - s_vo[k] * conj(s_wo[c]) - s_wo[k] * conj(s_vo[c]);
-    }
+    T val = xr[t];
+    if (c < m && prev) val = val - s_vo[k] * conj(s_wo[c]) - s_wo[k] * conj(s_vo[c]);
     xr[t] = conj(val);
     if (c >= k + 2 && c < m) xn2 += norm2(val);
   }
@@ -233,7 +236,11 @@ __device__ inline int sturm_count(int m, const double* s_d, const double* s_e2, 
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
   for (int j = 1; j < m; ++j) {
-    q = (s_d[j] - x) - s_e2[j - 1] / q;
+    // e2 / q by the hardware reciprocal and one Newton step (the count only needs the signs
+    // of a backward-stable recurrence)
+    double rq = __builtin_amdgcn_rcp(q);
+    rq = fma(fma(-q, rq, 1.0), rq, rq);
+    q = (s_d[j] - x) - s_e2[j - 1] * rq;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -335,16 +342,19 @@ __global__ __launch_bounds__(64) void k_trd_invit(int m, const double* __restric
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
       if (lane == 0) {
+        // the running entry stays in a register (no LDS store is read back in the chain)
+        double cur = s_x[0];
         for (int j = 0; j < m - 1; ++j) {
-          double xj = s_x[j], xn = s_x[j + 1];
+          double nxt = s_x[j + 1];
           if (s_pv[j]) {
-            const double t = xj;
-            xj = xn;
-            xn = t;
+            const double t = cur;
+            cur = nxt;
+            nxt = t;
           }
-          s_x[j] = xj;
-          s_x[j + 1] = xn - s_l[j] * xj;
+          s_x[j] = cur;
+          cur = nxt - s_l[j] * cur;
         }
+        s_x[m - 1] = cur;
         double x2 = s_x[m - 1] * s_u0[m - 1];
         s_x[m - 1] = x2;
         double x1 = x2;
