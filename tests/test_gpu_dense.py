@@ -261,3 +261,64 @@ def test_repeated_calls_are_bit_for_bit_equal(fp32):
     for b in outs[1:]:
         assert (b["info"], b["M"], b["loop"]) == (a["info"], a["M"], a["loop"])
         assert torch.equal(a["E"], b["E"]) and torch.equal(a["X"], b["X"]) and torch.equal(a["res"], b["res"])
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_large_subspace_tridiagonal_eigensolver(fp32):
+    """M0 = 260 with about 100 eigenvalues inside: the first iteration's reduced problem and
+    the block of the pairs not yet found (about 160) are both solved through the real
+    tridiagonal form (order >= 128); parity with the oracle as in every dense case."""
+    _say("large subspace fp32=%s" % fp32)
+    n = 520
+    A, B, lam, _ = gen.prescribed_complex_pencil(n, seed=77, lam_lo=-5, lam_hi=5)
+    emin, emax = -1.0, 1.0
+    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    m0 = 260
+    Y = oracle.initial_subspace(n, m0, 3, True)
+    out = _run_gpu(A, B, emin, emax, m0, Y, fp32)
+    ref = _run_oracle(A, B, emin, emax, m0, Y)
+    assert ref["M"] == cnt
+    _check(out, ref, emin, emax, B=B)
+    np.testing.assert_allclose(out["E"].cpu().numpy()[:cnt], lam[(lam >= emin) & (lam <= emax)], atol=1e-10)
+
+
+def test_multiple_eigenvalues_large_subspace():
+    """Real symmetric A with eigenvalue 0.3 of multiplicity 80 and 0.6 of multiplicity 20
+    (the rest spread over [-4, 4]), M0 >= 128: the reduced problems hold nearly repeated
+    Ritz values, which the tridiagonal solver orthogonalizes together in groups (a group
+    of more than 64 goes to the Jacobi solver).  Exact count, the repeated eigenvalues to
+    1e-12, and oracle parity of every cluster subspace."""
+    _say("multiple eigenvalues")
+    rng = np.random.default_rng(21)
+    n = 400
+    lam = np.concatenate([np.full(80, 0.3), np.full(20, 0.6), rng.uniform(-4.0, 4.0, n - 100)])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (U * lam[None, :]) @ U.T
+    A = 0.5 * (A + A.T)
+    emin, emax = -1.0, 1.0
+    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    m0 = max(128, cnt + 40)
+    Y = oracle.initial_subspace(n, m0, 4, False)
+    out = _run_gpu(A, None, emin, emax, m0, Y, False)
+    ref = _run_oracle(A, None, emin, emax, m0, Y)
+    assert ref["M"] == cnt
+    _check(out, ref, emin, emax)
+    E = np.sort(out["E"].cpu().numpy()[:cnt])
+    np.testing.assert_allclose(E, np.sort(lam[(lam >= emin) & (lam <= emax)]), atol=1e-12)
+
+
+def test_fp32_solves_below_their_floor():
+    """Tolerance 1e-13 with FP32 solves: below the residual floor that FP32 solves reach on
+    their own, so the loop refines the solves once in FP64 when it gets there; it must
+    converge (info 0) with every residual below 1e-13 and match the oracle."""
+    _say("fp32 tolerance 1e-13")
+    n = 333
+    A, B, lam, _ = gen.prescribed_complex_pencil(n, seed=n, lam_lo=-5, lam_hi=5)
+    emin, emax = -1.0, 1.0
+    cnt = int(np.sum((lam >= emin) & (lam <= emax)))
+    m0 = int(np.ceil(1.5 * cnt)) + 3
+    Y = oracle.initial_subspace(n, m0, 1, True)
+    out = _run_gpu(A, B, emin, emax, m0, Y, True, extra={2: 13})
+    ref = _run_oracle(A, B, emin, emax, m0, Y, extra={2: 13})
+    assert ref["M"] == cnt
+    _check(out, ref, emin, emax, B=B, res_tol=1e-13)
