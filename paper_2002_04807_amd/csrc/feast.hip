@@ -302,6 +302,9 @@ struct Operator {
   // FP32 solves near their accuracy limit: later contours add one FP64 refinement step per
   // solve (as fpm(50) = 1).  Returns whether the operator changed.
   virtual bool raise_precision(hipStream_t) { return false; }
+  // the seeding eigensolves (first iteration, not-found block) may use the tridiagonal
+  // solver; off where an iteration costs seconds and the eigensolve does not matter
+  bool tri_seed = true;
 };
 
 // dense storage: LU of every shifted matrix, blocked triangular solves
@@ -575,6 +578,9 @@ struct CsrOp : Operator<double> {
       : h(h_), uplo(uplo_), n(n_), a(a_), b(b_), ia(ia_), ja(ja_), ib(ib_), jb(jb_), base(base_), z(z_),
         ne((int)z_.size()), m0max(m0_), maxit(maxit_), tol(tol_) {
     this->hasB = b_ != nullptr;
+    // BiCGSTAB takes seconds per iteration here; with the tridiagonal first eigensolve the
+    // 64^3 Laplacian needed one iteration more (27.2 against 21.7 s), so Jacobi stays
+    this->tri_seed = false;
   }
 
   int prepare(hipStream_t s) override {
@@ -1046,7 +1052,7 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       // (V_OO only prepares the full sweeps below, whose 1e-10 test decides the accuracy,
       // so its own sweeps stop at rotations below 1e-4 max|diag|)
       bool oo_tri = false;
-      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw, 1.0e-4, true, &oo_tri));
+      MF_TRY(eig_timed<T>(s, mo, Coo, Voo, ev_oo, d_sweeps + 1, (double*)Hw, 1.0e-4, op.tri_seed, &oo_tri));
       if (oo_tri) {
         // inverse-iteration vectors are orthogonal to about eps over the relative gap: V_OO
         // is replaced by its polar factor V_OO (V_OO^H V_OO)^-1/2 (Newton-Schulz), so that
@@ -1076,7 +1082,8 @@ static int feast_loop(mfeast_ctx* h, Operator<T>& op, int64_t n, int32_t* fpm, d
       // depend on the basis chosen inside span(Q), and their residuals are far above the
       // threshold), so its sweeps stop at rotations below 1e-4 max|diag|, which still leaves
       // off-diagonal entries of the order of 1e-8 max|diag|
-      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw, k == 0 ? 1.0e-4 : 1.0e-10, k == 0));
+      MF_TRY(eig_timed<T>(s, kk2, Cm, Zm, d_evals, d_sweeps, (double*)Hw, k == 0 ? 1.0e-4 : 1.0e-10,
+                          k == 0 && op.tri_seed));
     }
     int sweeps = 0;
     MF_HIP_CHECK(hipMemcpyAsync(h_evals, d_evals, kk2 * sizeof(double), hipMemcpyDeviceToHost, s));
