@@ -28,12 +28,12 @@ METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res
 # HBM bytes per launch unit from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
 # plain copy's readings), valid while the listed sources hash to the profiled ones
 TRAFFIC = {
-    "contour_solve": {"bytes": 14.05e9,
+    "contour_solve": {"bytes": 14.07e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "95d87b85e37b624c"},
-    "reduced_eig": {"bytes": 3.73e9,
-                    "sources": ["paper_2002_04807_amd/csrc/eig.hip"],
-                    "sha256_16": "6da79370437ec863"},
+                      "sha256_16": "b6c7e4a7f24782e9"},
+    "reduced_eig": {"bytes": 1.48e9,
+                    "sources": ["paper_2002_04807_amd/csrc/eig.hip", "paper_2002_04807_amd/csrc/tri.hip"],
+                    "sha256_16": "fc0e7013ae4336c4"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
@@ -125,8 +125,8 @@ KERNELS = {
                       "one contour's block solves, all 8 nodes: the forward (L, U) and the "
                       "conjugate-transpose (U^H, L^H) sweeps, which run concurrently on two streams"),
     "rr_gemm": ("k_gemm (FP64 Rayleigh-Ritz)", "mfma", "fp64_mfma", "one FP64 product"),
-    "reduced_eig": ("k_bj_sub + k_bj_upd (block Jacobi)", "alu", "fp64_vector",
-                    "one reduced eigensolve (48 m^3 flops per Jacobi sweep)"),
+    "reduced_eig": ("k_bj_sub + k_bj_upd (block Jacobi), k_trd_* (tridiagonal seeding solves)", "alu", "fp64_vector",
+                    "one reduced eigensolve (48 m^3 flops per Jacobi sweep; 8 (4/3 + 2) m^3 for a tridiagonal one)"),
     "batched_factor": ("factorization graph: k_bt_shift_form + blocked LU + panel inverses of every size class",
                        "mfma", "fp32_mfma", "one replay: all problems and nodes (flops of the unpadded matrices)"),
 }
