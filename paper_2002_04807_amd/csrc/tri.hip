@@ -310,6 +310,8 @@ __global__ __launch_bounds__(64) void k_trd_invit(int m, const double* __restric
     if (lane == 0) {
       // T - lm I = P L U with row interchanges; U has two superdiagonals
       double alpha = s_d[0] - lm, beta = s_e[0];
+      // unrolled so that the independent LDS reads of later steps are issued early
+#pragma unroll 8
       for (int j = 0; j < m - 1; ++j) {
         const double c = s_e[j], an = s_d[j + 1] - lm, bn = s_e[j + 1];
         if (fabs(alpha) >= fabs(c)) {
@@ -333,6 +335,7 @@ __global__ __launch_bounds__(64) void k_trd_invit(int m, const double* __restric
         }
       }
       s_u0[m - 1] = alpha;
+#pragma unroll 8
       for (int j = 0; j < m; ++j) {
         const double u = s_u0[j];
         s_u0[j] = 1.0 / (fabs(u) < pivtol ? (u >= 0.0 ? pivtol : -pivtol) : u);
@@ -344,6 +347,7 @@ __global__ __launch_bounds__(64) void k_trd_invit(int m, const double* __restric
       if (lane == 0) {
         // the running entry stays in a register (no LDS store is read back in the chain)
         double cur = s_x[0];
+#pragma unroll 8
         for (int j = 0; j < m - 1; ++j) {
           double nxt = s_x[j + 1];
           if (s_pv[j]) {
@@ -362,6 +366,7 @@ __global__ __launch_bounds__(64) void k_trd_invit(int m, const double* __restric
           x1 = (s_x[m - 2] - s_u1[m - 2] * x2) * s_u0[m - 2];
           s_x[m - 2] = x1;
         }
+#pragma unroll 8
         for (int j = m - 3; j >= 0; --j) {
           const double x0 = (s_x[j] - s_u1[j] * x1 - s_u2[j] * x2) * s_u0[j];
           s_x[j] = x0;
