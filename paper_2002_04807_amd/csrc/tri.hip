@@ -235,6 +235,7 @@ __device__ inline int sturm_count(int m, const double* s_d, const double* s_e2, 
   double q = s_d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
+#pragma unroll 8
   for (int j = 1; j < m; ++j) {
     // e2 / q by the hardware reciprocal and one Newton step (the count only needs the signs
     // of a backward-stable recurrence)
