@@ -123,8 +123,12 @@ int mfeast_zolotarev(double emin, double emax, int32_t ne, int32_t band_pct, dou
  *          fpm(16), fpm(18), and fpm(54) for the Zolotarev rule (fpm(16)=2)
  * fpm(42)=1 (default) factors and solves the shifted systems in complex FP32 with the
  * FP64 residual form of the iteration (plus fpm(50) refinement steps of each solve);
- * fpm(42)=0 uses complex FP64 throughout.  Return 150: fpm(50) outside 0..8; 153:
- * fpm(53) not 0 or 1. */
+ * fpm(42)=0 uses complex FP64 throughout.  FP32 solves reach a residual floor near 1e-11:
+ * with fpm(50)=0, once the found pairs' largest residual is above the tolerance and
+ * either below 1e-9 with a tolerance below 1e-10, or has fallen by less than ten times in
+ * an iteration, the later contours add one refinement step per solve (not in
+ * mfeast_dsygv_noalloc, and not for the batched driver's padded factors).  Return 150:
+ * fpm(50) outside 0..8; 153: fpm(53) not 0 or 1. */
 int mfeast_dsygv(mfeast_handle h, char uplo, int64_t n, const double* A, int64_t lda,
                  const double* B, int64_t ldb, int32_t* fpm, double emin, double emax,
                  int32_t* m0, double* E, double* X, int64_t ldx, int32_t* M, double* res,
