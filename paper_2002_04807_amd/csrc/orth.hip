@@ -59,20 +59,18 @@ __global__ __launch_bounds__(256) void k_chol_diag(int m, int jb, T* A, T* Linv,
   if (tid < CH_NB) {
     const int c = tid;
     T xr[CH_NB];
-    bool kp[CH_NB];
+    double rd[CH_NB];
 #pragma unroll
-    for (int k = 0; k < CH_NB; ++k) kp[k] = s_keep[k] != 0;
+    for (int i = 0; i < CH_NB; ++i) rd[i] = 1.0 / real_part(a[i][i]);
+    // the terms of rows k < c and of dropped rows are exact zeros (xr[k] = 0 there), so
+    // every term is taken without a branch and the LDS reads are not serialized
 #pragma unroll
     for (int i = 0; i < CH_NB; ++i) {
-      T v = T(0.0);
-      if (i < bc && c < bc && i >= c && kp[i] && kp[c]) {
-        v = (i == c) ? T(1.0) : T(0.0);
+      T v = (i == c) ? T(1.0) : T(0.0);
 #pragma unroll
-        for (int k = 0; k < i; ++k)
-          if (k >= c && kp[k]) v = v - a[i][k] * xr[k];
-        v = (1.0 / real_part(a[i][i])) * v;
-      }
-      xr[i] = v;
+      for (int k = 0; k < i; ++k) v = v - a[i][k] * xr[k];
+      const bool ok = i < bc && c < bc && i >= c && s_keep[i] != 0 && s_keep[c] != 0;
+      xr[i] = ok ? rd[i] * v : T(0.0);
     }
 #pragma unroll
     for (int i = 0; i < CH_NB; ++i) x[i][c] = xr[i];
