@@ -103,7 +103,10 @@ constexpr int TRSM_PH = TRSM_SUB * LU_NB;
 int64_t panel_count(int64_t n) { return (n + TRSM_PH - 1) / TRSM_PH; }
 size_t panel_inverse_entries(int64_t n) { return (size_t)panel_count(n) * 2 * TRSM_PH * TRSM_PH; }
 
-template <typename C> struct trsm_cols { static constexpr int value = sizeof(C) == 8 ? 32 : 16; };
+// right-hand-side columns per workgroup: 16 keeps the LDS tiles of complex FP32 at 65 KB, two
+// workgroups per compute unit (32 columns: 97 KB, one; the batched factorizations' panel
+// inverses took 14 ms more per call)
+template <typename C> struct trsm_cols { static constexpr int value = 16; };
 
 // In-LDS block solve of one panel, used to form the panel inverses from the
 // identity.  Workgroup (x, y, z): CW right-hand-side columns x, panel pan0 + y, node
