@@ -30,10 +30,10 @@ METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res
 TRAFFIC = {
     "contour_solve": {"bytes": 14.07e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "b6c7e4a7f24782e9"},
-    "reduced_eig": {"bytes": 1.48e9,
+                      "sha256_16": "3699ea9dfe64f1a7"},
+    "reduced_eig": {"bytes": 1.66e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip", "paper_2002_04807_amd/csrc/tri.hip"],
-                    "sha256_16": "fc0e7013ae4336c4"},
+                    "sha256_16": "cba9e83170104e58"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
