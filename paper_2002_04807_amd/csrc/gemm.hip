@@ -513,13 +513,20 @@ static void launch(const GemmArgs& g, int batch, hipStream_t s) {
       return;
     }
   }
+  // Fewer than two 64 x 64 tiles per compute unit (the 256-row panel-inverse products of the
+  // block solves: 320 for 8 nodes and 600 columns, 28 for one matrix; the M0 x M0 products of
+  // the Rayleigh-Ritz step: 100): 32 x 32 tiles, four times as many workgroups.  The tile
+  // does not change the order of any K sum.
+  const bool few = tiles < 512;
   if constexpr (CPLX && sizeof(R) == 4) {
     if (g_3m) {
-      launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, true>(g, batch, s);
+      if (few) launch_tile<R, CPLX, AM, CJ, BK_, CJB, 32, 32, TBK, true>(g, batch, s);
+      else launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, true>(g, batch, s);
       return;
     }
   }
-  launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, false>(g, batch, s);
+  if (few) launch_tile<R, CPLX, AM, CJ, BK_, CJB, 32, 32, TBK, false>(g, batch, s);
+  else launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, false>(g, batch, s);
 }
 
 template <typename R, bool CPLX, bool AM, bool CJ>
