@@ -28,9 +28,9 @@ METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res
 # HBM bytes per launch unit from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
 # plain copy's readings), valid while the listed sources hash to the profiled ones
 TRAFFIC = {
-    "contour_solve": {"bytes": 14.07e9,
+    "contour_solve": {"bytes": 14.05e9,
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
-                      "sha256_16": "3699ea9dfe64f1a7"},
+                      "sha256_16": "119d73507ecaddd7"},
     "reduced_eig": {"bytes": 1.66e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip", "paper_2002_04807_amd/csrc/tri.hip"],
                     "sha256_16": "cba9e83170104e58"},
