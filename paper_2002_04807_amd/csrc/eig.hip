@@ -135,10 +135,12 @@ __device__ inline void bj_v_update(int m, int nbp, int round, int bid, T* __rest
 }
 
 // H[I_i, I_j] <- U_i^H H[I_i, I_j] U_j for the pairs i <= j of round `round` (the (j, i)
-// block is written as the conjugate transpose); X and Um are LDS tiles of the caller.
+// block is written as the conjugate transpose); X, Um and Ui_s are LDS tiles of the caller
+// (the block and both unitaries are loaded together, one global round trip).
 template <typename T, int JB>
 __device__ inline void bj_h_update(int m, int nbp, int round, int i, int j, T* __restrict__ H,
-                                   const T* __restrict__ Ubuf, T (*X)[2 * JB + 1], T (*Um)[2 * JB + 1]) {
+                                   const T* __restrict__ Ubuf, T (*X)[2 * JB + 1], T (*Um)[2 * JB + 1],
+                                   T (*Ui_s)[2 * JB + 1]) {
   constexpr int JS = 2 * JB;
   constexpr int RW = JS / 16;  // rows (and columns) of the result per thread: 16 x 16 threads
   const int tid = threadIdx.x;
@@ -156,6 +158,7 @@ __device__ inline void bj_h_update(int m, int nbp, int round, int i, int j, T* _
       const int ga = gidx<JB>(a, Pi, Qi), gc = gidx<JB>(c, Pj, Qj);
       X[a][c] = (ga < m && gc < m) ? H[(int64_t)ga * m + gc] : T(0.0);
       Um[a][c] = Uj[e];
+      Ui_s[a][c] = Ui[e];
     }
     __syncthreads();
     // T = X Uj
@@ -171,14 +174,13 @@ __device__ inline void bj_h_update(int m, int nbp, int round, int i, int j, T* _
     __syncthreads();
     for (int a = 0; a < RW; ++a)
       for (int c = 0; c < RW; ++c) X[r0 + a][c0 + c] = acc[a][c];
-    for (int e = tid; e < JS * JS; e += JT) Um[e / JS][e % JS] = Ui[e];
     __syncthreads();
     // out = Ui^H T
     for (int a = 0; a < RW; ++a)
       for (int c = 0; c < RW; ++c) acc[a][c] = T(0.0);
     for (int k = 0; k < JS; ++k) {
       T ua[RW], xb[RW];
-      for (int a = 0; a < RW; ++a) ua[a] = conj(Um[k][r0 + a]);
+      for (int a = 0; a < RW; ++a) ua[a] = conj(Ui_s[k][r0 + a]);
       for (int c = 0; c < RW; ++c) xb[c] = X[k][c0 + c];
       for (int a = 0; a < RW; ++a)
         for (int c = 0; c < RW; ++c) acc[a][c] = acc[a][c] + ua[a] * xb[c];
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(256) void k_bj_sub(int m, int nbp, int round, int n
       int i, j;
       bj_sb_index(b - nvi, npr, i, j);
       if (!bj_sb_critical(i, j, vround, (vround + 1) % (nbp - 1), nbp))
-        bj_h_update<T, JB>(m, nbp, vround, i, j, H, Uv, S[0], S[1]);
+        bj_h_update<T, JB>(m, nbp, vround, i, j, H, Uv, S[0], S[1], U);
     }
     return;
   }
@@ -354,10 +356,11 @@ __global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, int rn
   constexpr int JS = 2 * JB;
   __shared__ T X[JS][JS + 1];
   __shared__ T Um[JS][JS + 1];
+  __shared__ T Ui_s[JS][JS + 1];
   const int npr = nbp / 2;
   const int b = blockIdx.x;
   if (b < npr) {
-    bj_h_update<T, JB>(m, nbp, round, b, b, H, Ubuf, X, Um);
+    bj_h_update<T, JB>(m, nbp, round, b, b, H, Ubuf, X, Um, Ui_s);
     return;
   }
   int P, Q;
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(JT) void k_bj_upd(int m, int nbp, int round, int rn
     const int it = bj_pair_of(Pt, round, nbp), jt = bj_pair_of(Qt, round, nbp);
     if (min(it, jt) == min(i, j) && max(it, jt) == max(i, j)) return;
   }
-  bj_h_update<T, JB>(m, nbp, round, min(i, j), max(i, j), H, Ubuf, X, Um);
+  bj_h_update<T, JB>(m, nbp, round, min(i, j), max(i, j), H, Ubuf, X, Um, Ui_s);
 }
 
 template <typename T>
