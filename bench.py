@@ -33,7 +33,7 @@ TRAFFIC = {
                       "sha256_16": "119d73507ecaddd7"},
     "reduced_eig": {"bytes": 1.66e9,
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip", "paper_2002_04807_amd/csrc/tri.hip"],
-                    "sha256_16": "cba9e83170104e58"},
+                    "sha256_16": "0ada7b7777fd1d85"},
 }
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 N, M0, NE, EMIN, EMAX, SEED = 4096, 600, 8, -1.0, 1.0, 0
