@@ -26,12 +26,13 @@ sys.path.insert(0, ROOT)
 METRIC = "converged eigenpairs/s + contour-solve TFLOP/s, FP32+IR vs FP64 at res≤1e-10"
 
 # HBM bytes per launch unit from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
-# plain copy's readings), valid while the listed sources hash to the profiled ones
+# plain copy's readings), measured on the pencil workload (n = 4096, M0 = 600, 8 nodes) and
+# reported for that workload only, while the listed sources hash to the profiled ones
 TRAFFIC = {
-    "contour_solve": {"bytes": 14.05e9,
+    "contour_solve": {"bytes": 14.05e9, "workload": "pencil",
                       "sources": ["paper_2002_04807_amd/csrc/gemm.hip", "paper_2002_04807_amd/csrc/solve.hip"],
                       "sha256_16": "119d73507ecaddd7"},
-    "reduced_eig": {"bytes": 1.66e9,
+    "reduced_eig": {"bytes": 1.66e9, "workload": "pencil",
                     "sources": ["paper_2002_04807_amd/csrc/eig.hip", "paper_2002_04807_amd/csrc/tri.hip"],
                     "sha256_16": "0ada7b7777fd1d85"},
 }
@@ -143,10 +144,11 @@ def _source_unchanged(entry):
     return h.hexdigest()[:16] == entry["sha256_16"]
 
 
-def roofline_of(prof, rank=0):
+def roofline_of(prof, rank=0, workload=None):
     """Roofline of the kernel class with the largest device time in this call (rank 0; rank 1
     the next one): algorithmic flops (8 per complex multiply-add) or bytes per launch over
-    the mean launch time, both from the library's HIP-event profile of the timed call."""
+    the mean launch time, both from the library's HIP-event profile of the timed call.  The
+    measured traffic is attached only for the workload it was taken on."""
     cands = sorted([c for c in KERNELS if prof.get(c, {}).get("ms", 0.0) > 0.0], key=lambda c: -prof[c]["ms"])
     if rank >= len(cands):
         return None
@@ -164,7 +166,8 @@ def roofline_of(prof, rank=0):
         achieved = work_per_launch / per_launch_s / 1e12
         unit = "TFLOP/s"
     tr = TRAFFIC.get(cls)
-    traffic = tr["bytes"] if tr is not None and _source_unchanged(tr) else None
+    traffic = (tr["bytes"] if tr is not None and tr["workload"] == workload and _source_unchanged(tr)
+               else None)
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": traffic, "kernel": kernel, "kernel_class": cls,
             "unit_of_work": unit_desc, ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): work_per_launch,
@@ -849,10 +852,9 @@ def main():
     t_contour = sum(prof[c]["ms"] for c in CONTOUR_CLASSES) / 1e3
     contour_tflops = f_alg / t_contour / 1e12 if t_contour > 0 else None
 
-    roofline = roofline_of(prof)
-    # the two largest classes are close on this workload (reduced eigensolver, block solves):
-    # the second one's roofline is reported beside the first
-    roofline_next = roofline_of(prof, 1)
+    roofline = roofline_of(prof, workload="pencil")
+    # the second-largest class's roofline is reported beside the first
+    roofline_next = roofline_of(prof, 1, workload="pencil")
 
     if roofline is not None and roofline["kernel_class"] == "contour_solve":
         roofline["rate"] = ("effective: algorithmic flops (8 per complex multiply-add) over time; the kernel "
