@@ -62,8 +62,9 @@ int mfeast_set_stream(mfeast_handle h, void* hip_stream);
  * FP32 contour solves of the dense drivers (default 0; each step forms the FP64
  * residual of every node's system and solves it again with the FP32 factors),
  * fpm(51) seed of the random starting block, fpm(52) = 1 records per-class kernel
- * timings for mfeast_get_profile, fpm(53) = 1 forms complex FP32 products with four
- * real products instead of Gauss's three (default 0: three), fpm(54) = 1..99 the flat
+ * timings for mfeast_get_profile, fpm(53) = 1 forms complex products with four real
+ * products instead of Gauss's three (default 0: three; FP32 products everywhere, FP64
+ * products outside the LU trailing updates, which always take four), fpm(54) = 1..99 the flat
  * band of the Zolotarev rule in percent of the half-width (default 90; see
  * mfeast_zolotarev).  Return 154 from the drivers: fpm(16)=2 with fpm(54) outside 1..99. */
 void mfeast_init(int32_t* fpm);

@@ -61,12 +61,14 @@ template <> struct vec2<double> { using t = double2; };
 // Workgroups of 4 waves per compute unit the register allocation has to leave room for:
 // 3 for complex FP64 (the accumulators move from AGPRs into VGPRs; 12-15% faster on the
 // LU and solve shapes than at 2), 5 for FP32 (1-8% faster than at 4).
-template <typename R, bool CPLX>
-constexpr int gemm_min_blocks() { return (sizeof(R) == 8 && CPLX) ? 3 : (sizeof(R) == 4 ? 5 : 1); }
+template <typename R, bool CPLX, bool G3M>
+constexpr int gemm_min_blocks() {
+  return (sizeof(R) == 8 && CPLX) ? (G3M ? 2 : 3) : (sizeof(R) == 4 ? 5 : 1);
+}
 
 template <typename R, bool CPLX, bool A_MCONTIG, bool CONJ_A, bool B_KCONTIG, bool CONJ_B, int BM, int BN, int BK,
           int TAG, bool SPLIT = false, bool G3M = false>
-__global__ __launch_bounds__(256, (gemm_min_blocks<R, CPLX>())) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
+__global__ __launch_bounds__(256, (gemm_min_blocks<R, CPLX, G3M>())) void k_gemm(GemmArgs g, int nsplit, int kchunk, R* __restrict__ part) {
   using M_ = mfma_op<R>;
   using acc_t = typename M_::acc_t;
   using V2 = typename vec2<R>::t;
@@ -488,8 +490,13 @@ static void launch(const GemmArgs& g, int batch, hipStream_t s) {
     R* part = static_cast<R*>(splitk_scratch((size_t)nsplit * batch * g.M * g.N * ES * sizeof(R)));
     if (part != nullptr && nsplit > 1) {
       dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, batch * nsplit);
-      hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true>), grid, dim3(256), 0, s, g, nsplit,
-                         kchunk, part);
+      constexpr bool F64C = CPLX && sizeof(R) == 8;  // complex FP64: three products unless fpm(53) = 1
+      if (F64C && g_3m)
+        hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true, F64C>), grid, dim3(256), 0, s, g,
+                           nsplit, kchunk, part);
+      else
+        hipLaunchKernelGGL((k_gemm<R, CPLX, AM, CJ, BK_, CJB, BM, BN, BK, 0, true>), grid, dim3(256), 0, s, g, nsplit,
+                           kchunk, part);
       const int64_t mn = (int64_t)g.M * g.N;
       hipLaunchKernelGGL((k_gemm_splitk_sum<R, CPLX>), dim3((unsigned)((mn + 255) / 256), batch), dim3(256), 0, s, g,
                          nsplit, (const R*)part);
@@ -518,7 +525,7 @@ static void launch(const GemmArgs& g, int batch, hipStream_t s) {
   // the Rayleigh-Ritz step: 100): 32 x 32 tiles, four times as many workgroups.  The tile
   // does not change the order of any K sum.
   const bool few = tiles < 512;
-  if constexpr (CPLX && sizeof(R) == 4) {
+  if constexpr (CPLX) {
     if (g_3m) {
       if (few) launch_tile<R, CPLX, AM, CJ, BK_, CJB, 32, 32, TBK, true>(g, batch, s);
       else launch_tile<R, CPLX, AM, CJ, BK_, CJB, 64, 64, TBK, true>(g, batch, s);
